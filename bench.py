@@ -1,0 +1,149 @@
+"""Benchmark: raw (min,+) product throughput on one MI355X.
+
+Workload (one step): C = A x B in the (min,+) semiring for square uint16
+matrices of order 8192, entries uniform in 0..24 with 30 % set to INF = 65535,
+drawn with numpy.random.default_rng(0), A before B.  Inputs are resident in
+HBM before timing starts.  One step = one launch of the dense product kernel;
+algorithmic work = N^3 (min,+) operations per step.
+
+Prints one JSON line with the throughput, the kernel's roofline position and
+the CPU oracle timed on a bounded sample of the same product.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz; one v_pk_add_u16 plus one v_pk_min_u16
+# make two (min,+) operations, i.e. one per lane per clock.
+PEAK_MINPLUS = 256 * 64 * 2.4e9
+N_DEFAULT = 8192
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
+# dispatch, scaled by the copy-kernel calibration factor); None until measured
+# for the current kernel.
+MEASURED_TRAFFIC_BYTES = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N_DEFAULT, help="matrix order")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(A, B, target_s):
+    """The CPU oracle on a bounded sample of the same product: a block of rows
+    of C = A x B (each row is an independent (min,+) vector-matrix product)."""
+    import numpy as np
+
+    import oracle
+    Ai = A.astype(np.int32)
+    Bi = B.astype(np.int32)
+    N = A.shape[0]
+    rows = 8
+    t0 = time.perf_counter()
+    oracle.minplus(Ai[:rows], Bi)
+    dt = time.perf_counter() - t0
+    rows = int(max(8, min(N, rows * target_s / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.minplus(Ai[:rows], Bi)
+    dt = time.perf_counter() - t0
+    ops = float(rows) * N * N
+    return {"value": ops / dt / 1e9, "unit": "Gminplus-ops/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{rows} of {N} rows of C = A x B (same inputs), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this workload has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2409_17688_amd as tp
+    import synth
+
+    N = args.n
+    A, B = synth.raw_gemm_pair(N, seed=0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    dA = torch.from_numpy(A).to(dev)
+    dB = torch.from_numpy(B).to(dev)
+    dC = torch.empty((N, N), dtype=torch.uint16, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        tp.tp_minplus_gemm(dA, dB, dC, stream=stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        tp.tp_minplus_gemm(dA, dB, dC, stream=stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    ops = float(N) ** 3
+    value = ops * args.steps / wall / 1e9
+    achieved = ops / avg_kernel_s
+
+    # sanity: a few outputs against a direct evaluation of the definition
+    C = dC.cpu().numpy()
+    rng = np.random.default_rng(1)
+    for _ in range(16):
+        i, j = (int(v) for v in rng.integers(0, N, 2))
+        ref = int(np.minimum(A[i].astype(np.int64) + B[:, j].astype(np.int64), 65535).min())
+        if int(C[i, j]) != ref:
+            print(f"MISMATCH at ({i},{j}): {int(C[i, j])} != {ref}", file=sys.stderr)
+            sys.exit(1)
+
+    line = {
+        "metric": "Gminplus-ops/s (raw minplus_gemm)",
+        "value": round(value, 1),
+        "unit": "Gminplus-ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": f"minplus_gemm u16 square N={N}, entries uniform 0..24, "
+                               "30% INF=65535, numpy default_rng(0) A then B",
+                   "N": N, "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                     "peak": round(PEAK_MINPLUS / 1e12, 3), "unit": "Tminplus-ops/s",
+                     "frac": round(achieved / PEAK_MINPLUS, 4),
+                     "traffic": MEASURED_TRAFFIC_BYTES},
+        "kernel_ms": round(avg_kernel_s * 1e3, 3),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * tropical.h -- C ABI of libtropical.so: exact integer (min,+) matrix
+ * arithmetic on an MI355X (gfx950) and the 2-domination number of cylinders
+ * P_n x C_m by tropical matrix powers (arXiv 2409.17688).
+ *
+ * Notation: n is the order of the path (the paper's m), m the order of the
+ * cycle (the paper's n).  The state matrix A(D_n) of Section 2.2 has one row
+ * and one column per correct word of length n over {0,1,2}; words are indexed
+ * in increasing order of their base-3 value with the first letter most
+ * significant.  A[q][p] = number of zeros of p when p can follow q, else INF.
+ *
+ * Element types.  Matrices hold small non-negative integers in unsigned 8-bit
+ * (INF = 255) or 16-bit (INF = 65535) storage.  Every value >= INF means INF;
+ * sums saturate: a + b >= INF gives INF.  Results are exact: the semiring of
+ * Section 1 on integers, with no rounding anywhere.
+ *
+ * Conventions for every call below.
+ *   Layout     row-major; leading dimensions are in elements and >= the row
+ *              length.  Pointers named d_* or documented as device pointers
+ *              are device memory owned by the caller; the library never frees
+ *              them.
+ *   Streams    work is queued on `stream` (NULL = the default stream) and the
+ *              call returns without waiting, unless stated otherwise.
+ *   Errors     a negative TP_E* status; nothing is written or queued when the
+ *              arguments are rejected (TP_EINVAL, TP_EOVERFLOW).  A failing
+ *              HIP call gives TP_EHIP.  tp_last_error() returns a text for the
+ *              last failure of the calling thread.
+ *   Sizes      0 <= M, N, K < 2^31 elements per dimension; empty shapes are
+ *              accepted and do nothing (an empty inner dimension gives INF).
+ *   Aliasing   outputs must not overlap inputs unless stated otherwise.
+ *   Determinism results are bit-identical for any tiling, launch shape or
+ *              batching: min and saturating + on integers are exact.
+ */
+#ifndef TROPICAL_H
+#define TROPICAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element types */
+#define TP_U8 1  /* uint8_t, INF = 255 */
+#define TP_U16 2 /* uint16_t, INF = 65535 */
+
+/* status codes */
+#define TP_OK 0
+#define TP_EINVAL (-1)    /* bad argument: size, pointer, dtype, n or m      */
+#define TP_ENOMEM (-2)    /* device memory or the context budget exhausted   */
+#define TP_EOVERFLOW (-3) /* finite results could reach INF: n*m >= INF      */
+#define TP_EHIP (-4)      /* a HIP runtime call failed                       */
+#define TP_EBUSY (-5)     /* the context cannot take more work right now     */
+#define TP_ECANCELED (-6) /* the request was cancelled before it ran         */
+
+/* Text describing the calling thread's last failure ("" if none). */
+const char *tp_last_error(void);
+
+/* ABI version, currently 1. */
+int tp_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* State matrix A(D_n): Section 2.2 (correct words, the "can follow" rule,    */
+/* arc label = zeros of the successor) and Algorithm 1 of Section 3.          */
+/* ------------------------------------------------------------------------ */
+
+/* N = |C_n|, the number of correct words of length n (Table 1), for
+ * 1 <= n <= 13; TP_EINVAL otherwise.  Host-side count, no GPU work. */
+int64_t tp_state_dim(int n);
+
+/* Number of arcs of D_n (non-INF entries of A(D_n)), 1 <= n <= 13.  The first
+ * call for a given n counts them on the current device and blocks; later
+ * calls return a cached value.  Negative status on failure. */
+int64_t tp_state_nnz(int n);
+
+/* d_codes[0..N-1] = base-3 codes of the correct words of length n in
+ * increasing order (device uint32_t array of N entries). */
+int tp_words(int n, uint32_t *d_codes, hipStream_t stream);
+
+/* Dense A(D_n) into d_A (N x N, leading dimension lda >= N), dtype TP_U8 or
+ * TP_U16. */
+int tp_build_state_matrix(int n, int dtype, void *d_A, int64_t lda, hipStream_t stream);
+
+/* A(D_n) in compressed sparse rows.  d_rowptr: N+1 int64 (row q's arcs are
+ * d_col[d_rowptr[q] .. d_rowptr[q+1]-1]), d_col: tp_state_nnz(n) uint32
+ * successor indices in increasing order, d_z: N uint8 zero counts, so that
+ * A[q][p] = d_z[p] for every stored p.  Any of d_col / d_z may be NULL to
+ * skip it. */
+int tp_build_state_csr(int n, int64_t *d_rowptr, uint32_t *d_col, uint8_t *d_z,
+                       hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* (min,+) products: (A x B)_ij = min_k (a_ik + b_kj), Section 1.            */
+/* ------------------------------------------------------------------------ */
+
+/* C (M x N) = A (M x K) x B (K x N); with accumulate != 0,
+ * C = min(C, A x B) elementwise.  Device pointers of the given dtype. */
+int tp_minplus_gemm(int dtype, int64_t M, int64_t N, int64_t K,
+                    const void *d_A, int64_t lda, const void *d_B, int64_t ldb,
+                    void *d_C, int64_t ldc, int accumulate, hipStream_t stream);
+
+/* Number of tile configurations of the dense product (for tuning). */
+int tp_gemm_config_count(void);
+
+/* tp_minplus_gemm with an explicit tile configuration 0 <= config <
+ * tp_gemm_config_count(); every configuration gives the same result.  For an
+ * autotuner and for tests that cover every configuration. */
+int tp_minplus_gemm_config(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A,
+                           int64_t lda, const void *d_B, int64_t ldb, void *d_C, int64_t ldc,
+                           int accumulate, int config, hipStream_t stream);
+
+/* Matrix-vector products with the M x K matrix A:
+ *   trans == 0:  y (M)  = A x x (x has K entries),  y_i = min_k a_ik + x_k
+ *   trans == 1:  y (K)  = x x A (x has M entries),  y_k = min_i x_i + a_ik
+ * Device pointers of the given dtype. */
+int tp_minplus_gemv(int dtype, int64_t M, int64_t K, const void *d_A, int64_t lda,
+                    const void *d_x, void *d_y, int trans, hipStream_t stream);
+
+/* Y (rows x ncols) = S x X where S is the sparse rows x K matrix with
+ * S[q][p] = d_z[p] for p in d_col[d_rowptr[q] .. d_rowptr[q+1]-1] and INF
+ * elsewhere (the shape of A(D_n) from tp_build_state_csr, whose labels depend
+ * on the column only), and X is dense K x ncols.  One left multiplication of
+ * the power chain of Algorithm 2 costs nnz * ncols (min,+) operations this
+ * way.  Column indices must be < K; K is only used for that check. */
+int tp_minplus_spmm(int dtype, int64_t rows, int64_t K, const int64_t *d_rowptr,
+                    const uint32_t *d_col, const uint8_t *d_z, const void *d_X, int64_t ldx,
+                    void *d_Y, int64_t ldy, int64_t ncols, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Traces: Theorem 2 reads gamma_2 as the minimum of the diagonal.            */
+/* ------------------------------------------------------------------------ */
+
+/* *d_out (device int32) = min_i X_ii over the N x N matrix X (INF if N = 0). */
+int tp_trace_min(int dtype, int64_t N, const void *d_X, int64_t ldx, int32_t *d_out,
+                 hipStream_t stream);
+
+/* *d_out = min_i (X x Y)_ii = min_{i,k} x_ik + y_ki for N x N matrices, without
+ * forming the product; saturates at the dtype's INF. */
+int tp_trace_of_product(int dtype, int64_t N, const void *d_X, int64_t ldx, const void *d_Y,
+                        int64_t ldy, int32_t *d_out, hipStream_t stream);
+
+/* *d_out = min over arcs q -> p of d_z[p] + X[p][q]: the trace of S x X for the
+ * sparse S of tp_minplus_spmm with rows = K = N. */
+int tp_sparse_trace_of_product(int dtype, int64_t N, const int64_t *d_rowptr,
+                               const uint32_t *d_col, const uint8_t *d_z, const void *d_X,
+                               int64_t ldx, int32_t *d_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* gamma_2(P_n x C_m) = min_i (A(D_n)^m)_ii (Theorem 2).                       */
+/* ------------------------------------------------------------------------ */
+
+/* Computes gamma_2(P_n x C_m) for 1 <= n <= 12, m >= 3 into *gamma2_host and
+ * blocks until it is known.  The schedule (chain of sparse left products,
+ * dense squarings, a final trace of a product) is chosen by a cost model; the
+ * result does not depend on it.  State matrices and work buffers are kept in
+ * a process-wide cache on the current device (grown on demand; freed by
+ * tp_release_cache).  TP_EOVERFLOW when n*m >= 65535. */
+int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t stream);
+
+/* Frees the process-wide cache used by tp_tropical_power_trace. */
+int tp_release_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TROPICAL_H */

@@ -75,6 +75,8 @@ def _load():
     lib.oracle_power.restype = ctypes.c_int64
     lib.oracle_recurrence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int32, i64p]
     lib.oracle_recurrence.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     lib.brute_is_2dominating.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
     lib.brute_is_2dominating.restype = ctypes.c_int
     lib.brute_gamma2.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -182,6 +184,11 @@ def recurrence(n: int, K: int = 50, inf: int = INF16):
     if ok != 1:
         return None
     return tuple(int(v) for v in out)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's row-parallel loops use."""
+    return int(_load().oracle_threads())
 
 
 def brute_gamma2(n: int, m: int) -> int:

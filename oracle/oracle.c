@@ -31,8 +31,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXN 16
+
+/* threads the row-parallel loops use */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* letters w[0..n-1] of a base-3 code, w[0] = p^1 (most significant) */
 static void decode(uint32_t code, int n, int *w)

@@ -1,0 +1,295 @@
+"""ctypes binding of libtropical.so (the C ABI declared in include/tropical.h).
+
+Each function here has the name of the C entry point it calls and does
+argument marshalling only: it checks tensor dtypes, devices and strides,
+passes raw device pointers, leading dimensions and the current HIP stream, and
+turns a negative status into ``TropicalError``.  Every step of the computation
+runs in the library's HIP kernels; PyTorch provides device memory and streams.
+There is no fallback: when the library is missing, importing this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtropical.so")
+
+TP_U8 = 1
+TP_U16 = 2
+TP_OK = 0
+TP_EINVAL = -1
+TP_ENOMEM = -2
+TP_EOVERFLOW = -3
+TP_EHIP = -4
+TP_EBUSY = -5
+TP_ECANCELED = -6
+
+INF = {TP_U8: 255, TP_U16: 65535}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i = ctypes.c_int
+
+_SIGS = {
+    "tp_last_error": ([], ctypes.c_char_p),
+    "tp_version": ([], _i),
+    "tp_state_dim": ([_i], _i64),
+    "tp_state_nnz": ([_i], _i64),
+    "tp_words": ([_i, _p, _p], _i),
+    "tp_build_state_matrix": ([_i, _i, _p, _i64, _p], _i),
+    "tp_build_state_csr": ([_i, _p, _p, _p, _p], _i),
+    "tp_minplus_gemm": ([_i, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i, _p], _i),
+    "tp_gemm_config_count": ([], _i),
+    "tp_minplus_gemm_config": ([_i, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i, _i, _p],
+                               _i),
+    "tp_minplus_gemv": ([_i, _i64, _i64, _p, _i64, _p, _p, _i, _p], _i),
+    "tp_minplus_spmm": ([_i, _i64, _i64, _p, _p, _p, _p, _i64, _p, _i64, _i64, _p], _i),
+    "tp_trace_min": ([_i, _i64, _p, _i64, _p, _p], _i),
+    "tp_trace_of_product": ([_i, _i64, _p, _i64, _p, _i64, _p, _p], _i),
+    "tp_sparse_trace_of_product": ([_i, _i64, _p, _p, _p, _p, _i64, _p, _p], _i),
+    "tp_tropical_power_trace": ([_i, _i64, ctypes.POINTER(ctypes.c_int32), _p], _i),
+    "tp_release_cache": ([], _i),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class TropicalError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what} (status {status})")
+        self.status = status
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise TropicalError(rc, lib.tp_last_error().decode(errors="replace"))
+    return rc
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint16:
+        return TP_U16
+    if t.dtype == torch.uint8:
+        return TP_U8
+    raise TypeError(f"expected a uint8 or uint16 tensor, got {t.dtype}")
+
+
+def _torch_dtype(code: int):
+    return torch.uint16 if code == TP_U16 else torch.uint8
+
+
+def _mat(t: torch.Tensor, name: str):
+    """(pointer, rows, cols, leading dimension) of a row-major device matrix."""
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    rows, cols = t.shape
+    if cols > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    ld = t.stride(0) if rows > 1 else max(cols, 1)
+    return t.data_ptr(), rows, cols, max(ld, cols, 1)
+
+
+def _vec(t: torch.Tensor, name: str):
+    if t.dim() != 1 or not t.is_cuda:
+        raise ValueError(f"{name} must be a 1-D device tensor")
+    if t.numel() > 1 and t.stride(0) != 1:
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+# ----------------------------------------------------------------- state --
+
+def tp_version() -> int:
+    return int(lib.tp_version())
+
+
+def tp_state_dim(n: int) -> int:
+    return _check(int(lib.tp_state_dim(n)))
+
+
+def tp_state_nnz(n: int) -> int:
+    return _check(int(lib.tp_state_nnz(n)))
+
+
+def tp_words(n: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    N = tp_state_dim(n)
+    if out is None:
+        out = torch.empty(N, dtype=torch.int32, device="cuda")
+    if out.numel() < N or out.element_size() != 4:
+        raise ValueError("out must hold N 32-bit entries")
+    _check(lib.tp_words(n, _vec(out, "out"), _stream(stream)))
+    return out
+
+
+def tp_build_state_matrix(n: int, dtype: int = TP_U16, out: torch.Tensor | None = None,
+                          stream=None) -> torch.Tensor:
+    N = tp_state_dim(n)
+    if out is None:
+        out = torch.empty((N, N), dtype=_torch_dtype(dtype), device="cuda")
+    ptr, r, c, ld = _mat(out, "out")
+    if r < N or c < N or _dtype_code(out) != dtype:
+        raise ValueError("out must be at least N x N of the requested dtype")
+    _check(lib.tp_build_state_matrix(n, dtype, ptr, ld, _stream(stream)))
+    return out
+
+
+def tp_build_state_csr(n: int, stream=None):
+    """(rowptr int64[N+1], col int32[nnz] holding uint32 indices, z uint8[N])."""
+    N = tp_state_dim(n)
+    nnz = tp_state_nnz(n)
+    rowptr = torch.empty(N + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    z = torch.empty(N, dtype=torch.uint8, device="cuda")
+    _check(lib.tp_build_state_csr(n, rowptr.data_ptr(), col.data_ptr(), z.data_ptr(),
+                                  _stream(stream)))
+    return rowptr, col[:nnz], z
+
+
+# -------------------------------------------------------------- products --
+
+def tp_gemm_config_count() -> int:
+    return int(lib.tp_gemm_config_count())
+
+
+def tp_minplus_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
+                    accumulate: bool = False, config: int | None = None,
+                    stream=None) -> torch.Tensor:
+    dt = _dtype_code(A)
+    if _dtype_code(B) != dt:
+        raise TypeError("A and B must have the same dtype")
+    pa, M, K, lda = _mat(A, "A")
+    pb, K2, N, ldb = _mat(B, "B")
+    if K2 != K:
+        raise ValueError(f"inner dimensions differ: {K} vs {K2}")
+    if C is None:
+        if accumulate:
+            raise ValueError("accumulate needs C")
+        C = torch.empty((M, N), dtype=A.dtype, device=A.device)
+    pc, M2, N2, ldc = _mat(C, "C")
+    if (M2, N2) != (M, N) or _dtype_code(C) != dt:
+        raise ValueError("C has the wrong shape or dtype")
+    if config is None:
+        _check(lib.tp_minplus_gemm(dt, M, N, K, pa, lda, pb, ldb, pc, ldc, int(accumulate),
+                                   _stream(stream)))
+    else:
+        _check(lib.tp_minplus_gemm_config(dt, M, N, K, pa, lda, pb, ldb, pc, ldc,
+                                          int(accumulate), int(config), _stream(stream)))
+    return C
+
+
+def tp_minplus_gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False,
+                    y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    dt = _dtype_code(A)
+    if _dtype_code(x) != dt:
+        raise TypeError("A and x must have the same dtype")
+    pa, M, K, lda = _mat(A, "A")
+    nx, ny = (M, K) if trans else (K, M)
+    if x.numel() != nx:
+        raise ValueError(f"x must have {nx} entries")
+    if y is None:
+        y = torch.empty(ny, dtype=A.dtype, device=A.device)
+    if y.numel() != ny or _dtype_code(y) != dt:
+        raise ValueError("y has the wrong size or dtype")
+    _check(lib.tp_minplus_gemv(dt, M, K, pa, lda, _vec(x, "x") if nx else None,
+                               _vec(y, "y") if ny else None, int(trans), _stream(stream)))
+    return y
+
+
+def tp_minplus_spmm(rowptr: torch.Tensor, col: torch.Tensor, z: torch.Tensor, X: torch.Tensor,
+                    Y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    dt = _dtype_code(X)
+    rows = rowptr.numel() - 1
+    px, K, ncols, ldx = _mat(X, "X")
+    if Y is None:
+        Y = torch.empty((rows, ncols), dtype=X.dtype, device=X.device)
+    py, r2, c2, ldy = _mat(Y, "Y")
+    if (r2, c2) != (rows, ncols) or _dtype_code(Y) != dt:
+        raise ValueError("Y has the wrong shape or dtype")
+    if rowptr.dtype != torch.int64 or col.element_size() != 4 or z.dtype != torch.uint8:
+        raise TypeError("rowptr int64, col 32-bit, z uint8")
+    _check(lib.tp_minplus_spmm(dt, rows, K, _vec(rowptr, "rowptr"),
+                               col.data_ptr() if col.numel() else None, _vec(z, "z"), px, ldx,
+                               py, ldy, ncols, _stream(stream)))
+    return Y
+
+
+# ---------------------------------------------------------------- traces --
+
+def _scalar_out(out):
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device="cuda")
+    return out
+
+
+def tp_trace_min(X: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    dt = _dtype_code(X)
+    px, N, N2, ldx = _mat(X, "X")
+    if N != N2:
+        raise ValueError("X must be square")
+    out = _scalar_out(out)
+    _check(lib.tp_trace_min(dt, N, px, ldx, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def tp_trace_of_product(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+    dt = _dtype_code(X)
+    if _dtype_code(Y) != dt:
+        raise TypeError("X and Y must have the same dtype")
+    px, N, N2, ldx = _mat(X, "X")
+    py, N3, N4, ldy = _mat(Y, "Y")
+    if not (N == N2 == N3 == N4):
+        raise ValueError("X and Y must be square of one size")
+    out = _scalar_out(out)
+    _check(lib.tp_trace_of_product(dt, N, px, ldx, py, ldy, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def tp_sparse_trace_of_product(rowptr, col, z, X: torch.Tensor, out=None, stream=None):
+    dt = _dtype_code(X)
+    px, N, N2, ldx = _mat(X, "X")
+    if N != N2 or rowptr.numel() != N + 1:
+        raise ValueError("X must be N x N with rowptr of N + 1 entries")
+    out = _scalar_out(out)
+    _check(lib.tp_sparse_trace_of_product(dt, N, _vec(rowptr, "rowptr"),
+                                          col.data_ptr() if col.numel() else None, _vec(z, "z"),
+                                          px, ldx, out.data_ptr(), _stream(stream)))
+    return out
+
+
+# --------------------------------------------------------------- gamma_2 --
+
+def tp_tropical_power_trace(n: int, m: int, stream=None) -> int:
+    """gamma_2(P_n x C_m) = min_i (A(D_n)^m)_ii (Theorem 2); blocks."""
+    res = ctypes.c_int32(-1)
+    _check(lib.tp_tropical_power_trace(n, m, ctypes.byref(res), _stream(stream)))
+    return int(res.value)
+
+
+def tp_release_cache() -> None:
+    _check(lib.tp_release_cache())
+
+
+def tp_last_error() -> str:
+    return lib.tp_last_error().decode(errors="replace")

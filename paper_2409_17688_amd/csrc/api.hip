@@ -1,0 +1,477 @@
+// C ABI of libtropical.so: argument checks, the per-device cache of state
+// matrices, and the schedule of tp_tropical_power_trace.
+//
+// gamma_2(P_n x C_m) = min_i (A^m)_ii (Theorem 2).  Every schedule below
+// computes exactly that number, because the (min,+) semiring on integers is
+// associative and exact:
+//   * chain:  X <- A x X with the sparse left factor (Algorithm 2's order,
+//             one pass costs nnz(A) * N operations instead of N^3);
+//   * squaring: dense products P x P, P x Q of powers already formed;
+//   * closing trace: min_{i,k} (A^a)_ik + (A^b)_ki gives the trace of A^(a+b)
+//             without forming that product.
+// Plan(c): chain to A^c (snapshotting A^r, r = m mod c, on the way), raise
+// A^c to the q = m div c by square-and-multiply, and close with one trace of a
+// product.  The planner prices every c with per-operation rates and picks the
+// cheapest; c >= m/2 is a pure chain closed by one trace.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return TP_EHIP;
+}
+
+namespace {
+
+bool valid_dtype(int dt) { return dt == TP_U8 || dt == TP_U16; }
+size_t elem_size(int dt) { return dt == TP_U16 ? 2 : 1; }
+
+// Device buffer owned by the cache.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+hipError_t ensure(DevBuf &b, size_t bytes) {
+  if (b.bytes >= bytes && b.ptr) return hipSuccess;
+  if (b.ptr) {
+    hipError_t e = hipFree(b.ptr);
+    if (e != hipSuccess) return e;
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e == hipSuccess) b.bytes = bytes;
+  return e;
+}
+
+void release(DevBuf &b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+// Per (device, n): word masks, zero counts and the CSR of A(D_n).
+struct State {
+  int n = 0;
+  int64_t N = 0, nnz = -1;
+  DevBuf masks, z, rowptr, col;
+  bool csr_ready = false;
+};
+
+struct Workspace {
+  DevBuf buf[6];
+  DevBuf scalar;  // int32 results
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, State> g_states;  // (device, n)
+std::map<int, Workspace> g_ws;                  // device
+
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+
+// Builds masks, zero counts and the CSR of A(D_n) on `s` (blocking only
+// for the arc count, which sizes the column array).  Caller holds g_mu.
+int get_state(int n, hipStream_t s, State **out) {
+  State &st = g_states[{current_device(), n}];
+  if (!st.csr_ready) {
+    st.n = n;
+    st.N = word_count_host(n);
+    const int64_t N = st.N;
+    TP_HIP_CHECK(ensure(st.masks, N * sizeof(uint32_t)));
+    TP_HIP_CHECK(ensure(st.z, N));
+    TP_HIP_CHECK(ensure(st.rowptr, (N + 1) * sizeof(int64_t)));
+    TP_HIP_CHECK(launch_words(n, nullptr, (uint8_t *)st.z.ptr, (uint32_t *)st.masks.ptr, s));
+    TP_HIP_CHECK(launch_csr_count(N, n, (const uint32_t *)st.masks.ptr, (int64_t *)st.rowptr.ptr, s));
+    TP_HIP_CHECK(launch_scan_rowptr(N, (int64_t *)st.rowptr.ptr, s));
+    int64_t nnz = 0;
+    TP_HIP_CHECK(hipMemcpyAsync(&nnz, (int64_t *)st.rowptr.ptr + N, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+    TP_HIP_CHECK(hipStreamSynchronize(s));
+    st.nnz = nnz;
+    TP_HIP_CHECK(ensure(st.col, (size_t)nnz * sizeof(uint32_t)));
+    TP_HIP_CHECK(launch_csr_fill(N, n, (const uint32_t *)st.masks.ptr,
+                                 (const int64_t *)st.rowptr.ptr, (uint32_t *)st.col.ptr, s));
+    st.csr_ready = true;
+  }
+  *out = &st;
+  return TP_OK;
+}
+
+// ---------------------------------------------------------------- planner --
+
+// Seconds per operation class; launch overhead per kernel.  Measured on an
+// MI355X (see the benchmark); only the ratios steer the plan.
+constexpr double kSpmmRate = 4.0e12;   // (min,+) ops / s of the sparse left step
+constexpr double kGemmRate = 2.0e13;   // (min,+) ops / s of the dense product
+constexpr double kHbm = 5.0e12;        // bytes / s for traces and copies
+constexpr double kLaunch = 6.0e-6;     // s per kernel launch
+
+int bit_length(int64_t v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+int popcount64(int64_t v) { return __builtin_popcountll((unsigned long long)v); }
+
+// products needed by left-to-right square-and-multiply to form P^q from P
+int64_t sqm_products(int64_t q) { return q <= 1 ? 0 : (bit_length(q) - 1) + (popcount64(q) - 1); }
+
+struct Plan {
+  int64_t c = 1;        // chain length
+  double cost = 1e300;  // estimated seconds
+};
+
+double plan_cost(int64_t m, int64_t c, double N, double nnz) {
+  const double S = nnz * N / kSpmmRate + kLaunch;
+  const double G = N * N * N / kGemmRate + kLaunch;
+  const double T = 4.0 * N * N / kHbm + 2 * kLaunch;  // trace of a product, u16
+  const double copy = 4.0 * N * N / kHbm + kLaunch;
+  const int64_t q = m / c, r = m % c;
+  double cost = (double)(c - 1) * S + N * N * 2.0 / kHbm;  // chain + dense start
+  if (r > 0) {
+    cost += copy + (double)sqm_products(q) * G + T;
+  } else if (q == 1) {
+    cost += N / kHbm + kLaunch;  // diagonal of A^m
+  } else {
+    const int64_t h = q / 2;
+    cost += (double)sqm_products(h) * G + ((q & 1) ? G : 0.0) + T;
+  }
+  return cost;
+}
+
+Plan choose_plan(int64_t m, double N, double nnz) {
+  Plan best;
+  for (int64_t c = 1; c <= m; ++c) {
+    const double cst = plan_cost(m, c, N, nnz);
+    if (cst < best.cost) {
+      best.cost = cst;
+      best.c = c;
+    }
+  }
+  return best;
+}
+
+// Square-and-multiply: dst = P^q (q >= 1), P untouched; uses tmp.  Returns
+// the buffer that holds the result (dst or P itself when q == 1).
+int power_of(uint16_t *P, int64_t q, int64_t N, uint16_t *dst, uint16_t *tmp, hipStream_t s,
+             uint16_t **result) {
+  if (q == 1) {
+    *result = P;
+    return TP_OK;
+  }
+  // left to right over the bits of q below the top one
+  const int top = bit_length(q) - 1;
+  uint16_t *cur = P;
+  uint16_t *bufs[2] = {dst, tmp};
+  int which = 0;
+  for (int b = top - 1; b >= 0; --b) {
+    uint16_t *o = bufs[which];
+    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, N, cur, N, o, N, 0, -1, s));
+    cur = o;
+    which ^= 1;
+    if ((q >> b) & 1) {
+      uint16_t *o2 = bufs[which];
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, N, P, N, o2, N, 0, -1, s));
+      cur = o2;
+      which ^= 1;
+    }
+  }
+  *result = cur;
+  return TP_OK;
+}
+
+int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
+  State *st = nullptr;
+  int rc = get_state(n, s, &st);
+  if (rc != TP_OK) return rc;
+  const int64_t N = st->N;
+  Workspace &ws = g_ws[current_device()];
+  const size_t mat = (size_t)N * (size_t)N * sizeof(uint16_t);
+  const Plan plan = choose_plan(m, (double)N, (double)st->nnz);
+  const int64_t c = plan.c, q = m / c, r = m % c;
+
+  TP_HIP_CHECK(ensure(ws.scalar, 64));
+  int32_t *d_res = (int32_t *)ws.scalar.ptr;
+  // buffers: 0,1 chain ping-pong; 2 snapshot A^r; 3,4 powering; 5 spare
+  const int pw = r > 0 ? 3 : 2;
+  const int needed = pw + (q > 1 ? 2 : 0);
+  for (int i = 0; i < needed; ++i) TP_HIP_CHECK(ensure(ws.buf[i], mat));
+  uint16_t *X = (uint16_t *)ws.buf[0].ptr, *Y = (uint16_t *)ws.buf[1].ptr;
+  uint16_t *snap = r > 0 ? (uint16_t *)ws.buf[2].ptr : nullptr;
+
+  // X = A^1, then the chain up to A^c
+  const uint32_t *masks = (const uint32_t *)st->masks.ptr;
+  TP_HIP_CHECK(launch_dense_state(n, N, masks, TP_U16, X, N, s));
+  if (r == 1) TP_HIP_CHECK(hipMemcpyAsync(snap, X, mat, hipMemcpyDeviceToDevice, s));
+  const int64_t *rowptr = (const int64_t *)st->rowptr.ptr;
+  const uint32_t *col = (const uint32_t *)st->col.ptr;
+  const uint8_t *z = (const uint8_t *)st->z.ptr;
+  for (int64_t k = 2; k <= c; ++k) {
+    TP_HIP_CHECK(launch_spmm(TP_U16, N, rowptr, col, z, X, N, Y, N, N, s));
+    uint16_t *t = X;
+    X = Y;
+    Y = t;
+    if (k == r) TP_HIP_CHECK(hipMemcpyAsync(snap, X, mat, hipMemcpyDeviceToDevice, s));
+  }
+  // X = A^c
+  if (r > 0) {
+    uint16_t *R = nullptr;
+    rc = power_of(X, q, N, (uint16_t *)ws.buf[pw].ptr, (uint16_t *)ws.buf[pw + 1].ptr, s, &R);
+    if (rc != TP_OK) return rc;
+    TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, R, N, snap, N, d_res, s));
+  } else if (q == 1) {
+    TP_HIP_CHECK(launch_trace_min(TP_U16, N, X, N, d_res, s));
+  } else {
+    const int64_t h = q / 2;
+    uint16_t *H = nullptr;
+    uint16_t *tmp_a = (uint16_t *)ws.buf[pw].ptr, *tmp_b = (uint16_t *)ws.buf[pw + 1].ptr;
+    rc = power_of(X, h, N, tmp_a, tmp_b, s, &H);
+    if (rc != TP_OK) return rc;
+    if (q & 1) {
+      // H x X = P^(h+1) into a buffer that is neither H nor X
+      uint16_t *o = (H == tmp_a) ? tmp_b : tmp_a;
+      if (H == X) o = tmp_a;
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, N, X, N, o, N, 0, -1, s));
+      TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, N, o, N, d_res, s));
+    } else {
+      TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, N, H, N, d_res, s));
+    }
+  }
+  int32_t host = 0;
+  TP_HIP_CHECK(hipMemcpyAsync(&host, d_res, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TP_HIP_CHECK(hipStreamSynchronize(s));
+  *gamma2_host = host;
+  return TP_OK;
+}
+
+}  // namespace
+}  // namespace tp
+
+using namespace tp;
+
+extern "C" {
+
+const char *tp_last_error(void) { return g_err; }
+
+int tp_version(void) { return 1; }
+
+int64_t tp_state_dim(int n) {
+  if (n < 1 || n > 13) {
+    set_error("n = %d outside 1..13", n);
+    return TP_EINVAL;
+  }
+  return word_count_host(n);
+}
+
+int64_t tp_state_nnz(int n) {
+  if (n < 1 || n > 13) {
+    set_error("n = %d outside 1..13", n);
+    return TP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  int rc = get_state(n, nullptr, &st);
+  if (rc != TP_OK) return rc;
+  return st->nnz;
+}
+
+int tp_words(int n, uint32_t *d_codes, hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(d_codes != nullptr, "d_codes is NULL");
+  TP_HIP_CHECK(launch_words(n, d_codes, nullptr, nullptr, stream));
+  return TP_OK;
+}
+
+int tp_build_state_matrix(int n, int dtype, void *d_A, int64_t lda, hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  const int64_t N = word_count_host(n);
+  TP_REQUIRE(lda >= N, "lda = %lld < N = %lld", (long long)lda, (long long)N);
+  TP_REQUIRE(d_A != nullptr, "d_A is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  int rc = get_state(n, stream, &st);
+  if (rc != TP_OK) return rc;
+  TP_HIP_CHECK(launch_dense_state(n, N, (const uint32_t *)st->masks.ptr, dtype, d_A, lda, stream));
+  return TP_OK;
+}
+
+int tp_build_state_csr(int n, int64_t *d_rowptr, uint32_t *d_col, uint8_t *d_z,
+                       hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(d_rowptr != nullptr, "d_rowptr is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  int rc = get_state(n, stream, &st);
+  if (rc != TP_OK) return rc;
+  const int64_t N = st->N;
+  TP_HIP_CHECK(hipMemcpyAsync(d_rowptr, st->rowptr.ptr, (N + 1) * sizeof(int64_t),
+                              hipMemcpyDeviceToDevice, stream));
+  if (d_col && st->nnz > 0)
+    TP_HIP_CHECK(hipMemcpyAsync(d_col, st->col.ptr, (size_t)st->nnz * sizeof(uint32_t),
+                                hipMemcpyDeviceToDevice, stream));
+  if (d_z) TP_HIP_CHECK(hipMemcpyAsync(d_z, st->z.ptr, N, hipMemcpyDeviceToDevice, stream));
+  return TP_OK;
+}
+
+static int check_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, const void *C, int64_t ldc) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(M >= 0 && N >= 0 && K >= 0, "negative size");
+  TP_REQUIRE(M < (1ll << 31) && N < (1ll << 31) && K < (1ll << 31), "size >= 2^31");
+  TP_REQUIRE(lda >= (K > 0 ? K : 1) && ldb >= (N > 0 ? N : 1) && ldc >= (N > 0 ? N : 1),
+             "leading dimension smaller than the row length");
+  TP_REQUIRE((M == 0 || N == 0) || C != nullptr, "C is NULL");
+  TP_REQUIRE((M == 0 || K == 0) || A != nullptr, "A is NULL");
+  TP_REQUIRE((N == 0 || K == 0) || B != nullptr, "B is NULL");
+  return TP_OK;
+}
+
+int tp_minplus_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A, int64_t lda,
+                    const void *d_B, int64_t ldb, void *d_C, int64_t ldc, int accumulate,
+                    hipStream_t stream) {
+  int rc = check_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc);
+  if (rc != TP_OK) return rc;
+  TP_HIP_CHECK(launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, -1, stream));
+  return TP_OK;
+}
+
+int tp_minplus_gemm_config(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A,
+                           int64_t lda, const void *d_B, int64_t ldb, void *d_C, int64_t ldc,
+                           int accumulate, int config, hipStream_t stream) {
+  int rc = check_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc);
+  if (rc != TP_OK) return rc;
+  TP_REQUIRE(config >= 0 && config < gemm_config_count(), "config %d outside 0..%d", config,
+             gemm_config_count() - 1);
+  TP_HIP_CHECK(launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, config,
+                           stream));
+  return TP_OK;
+}
+
+int tp_gemm_config_count(void) { return gemm_config_count(); }
+
+int tp_minplus_gemv(int dtype, int64_t M, int64_t K, const void *d_A, int64_t lda,
+                    const void *d_x, void *d_y, int trans, hipStream_t stream) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(M >= 0 && K >= 0, "negative size");
+  TP_REQUIRE(lda >= (K > 0 ? K : 1), "lda < K");
+  TP_REQUIRE(trans == 0 || trans == 1, "trans must be 0 or 1");
+  const int64_t ny = trans ? K : M;
+  TP_REQUIRE(ny == 0 || d_y != nullptr, "y is NULL");
+  TP_REQUIRE((M == 0 || K == 0) || (d_A != nullptr && d_x != nullptr), "A or x is NULL");
+  if (!trans && K == 0 && M > 0) {
+    // empty minimum: INF everywhere
+    TP_HIP_CHECK(launch_fill_bytes(d_y, (size_t)M * elem_size(dtype), 0xFF, stream));
+    return TP_OK;
+  }
+  if (trans && M == 0 && K > 0) {
+    TP_HIP_CHECK(launch_fill_bytes(d_y, (size_t)K * elem_size(dtype), 0xFF, stream));
+    return TP_OK;
+  }
+  TP_HIP_CHECK(launch_gemv(dtype, M, K, d_A, lda, d_x, d_y, trans, stream));
+  return TP_OK;
+}
+
+int tp_minplus_spmm(int dtype, int64_t rows, int64_t K, const int64_t *d_rowptr,
+                    const uint32_t *d_col, const uint8_t *d_z, const void *d_X, int64_t ldx,
+                    void *d_Y, int64_t ldy, int64_t ncols, hipStream_t stream) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(rows >= 0 && K >= 0 && ncols >= 0, "negative size");
+  TP_REQUIRE(rows < (1ll << 31) && K < (1ll << 32), "size too large");
+  TP_REQUIRE(ldx >= (ncols > 0 ? ncols : 1) && ldy >= (ncols > 0 ? ncols : 1),
+             "leading dimension smaller than ncols");
+  if (rows == 0 || ncols == 0) return TP_OK;
+  TP_REQUIRE(d_rowptr && d_Y, "rowptr or Y is NULL");
+  TP_REQUIRE(K == 0 || (d_col && d_z && d_X), "col, z or X is NULL");
+  TP_HIP_CHECK(launch_spmm(dtype, rows, d_rowptr, d_col, d_z, d_X, ldx, d_Y, ldy, ncols, stream));
+  return TP_OK;
+}
+
+int tp_trace_min(int dtype, int64_t N, const void *d_X, int64_t ldx, int32_t *d_out,
+                 hipStream_t stream) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(N >= 0 && ldx >= (N > 0 ? N : 1), "bad N or ldx");
+  TP_REQUIRE(d_out != nullptr && (N == 0 || d_X != nullptr), "NULL pointer");
+  TP_HIP_CHECK(launch_trace_min(dtype, N, d_X, ldx, d_out, stream));
+  return TP_OK;
+}
+
+int tp_trace_of_product(int dtype, int64_t N, const void *d_X, int64_t ldx, const void *d_Y,
+                        int64_t ldy, int32_t *d_out, hipStream_t stream) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(N >= 0 && N < (1ll << 31), "bad N");
+  TP_REQUIRE(ldx >= (N > 0 ? N : 1) && ldy >= (N > 0 ? N : 1), "leading dimension < N");
+  TP_REQUIRE(d_out != nullptr && (N == 0 || (d_X && d_Y)), "NULL pointer");
+  TP_HIP_CHECK(launch_trace_of_product(dtype, N, d_X, ldx, d_Y, ldy, d_out, stream));
+  return TP_OK;
+}
+
+int tp_sparse_trace_of_product(int dtype, int64_t N, const int64_t *d_rowptr,
+                               const uint32_t *d_col, const uint8_t *d_z, const void *d_X,
+                               int64_t ldx, int32_t *d_out, hipStream_t stream) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(N >= 0 && ldx >= (N > 0 ? N : 1), "bad N or ldx");
+  TP_REQUIRE(d_out != nullptr, "out is NULL");
+  TP_REQUIRE(N == 0 || (d_rowptr && d_col && d_z && d_X), "NULL pointer");
+  TP_HIP_CHECK(launch_fill_i32(d_out, 1, dtype == TP_U16 ? 0xFFFF : 0xFF, stream));
+  TP_HIP_CHECK(launch_sparse_trace(dtype, N, d_rowptr, d_col, d_z, d_X, ldx, d_out, stream));
+  return TP_OK;
+}
+
+int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
+  TP_REQUIRE(m >= 3, "the cycle order m = %lld must be at least 3", (long long)m);
+  TP_REQUIRE(gamma2_host != nullptr, "gamma2_host is NULL");
+  if ((int64_t)n * m >= 0xFFFF) {
+    set_error("n * m = %lld could reach INF = 65535 in 16-bit entries", (long long)(n * m));
+    return TP_EOVERFLOW;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  return power_trace_locked(n, m, gamma2_host, stream);
+}
+
+int tp_release_cache(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto &kv : g_states) {
+    release(kv.second.masks);
+    release(kv.second.z);
+    release(kv.second.rowptr);
+    release(kv.second.col);
+  }
+  g_states.clear();
+  for (auto &kv : g_ws) {
+    for (auto &b : kv.second.buf) release(b);
+    release(kv.second.scalar);
+  }
+  g_ws.clear();
+  return TP_OK;
+}
+
+}  // extern "C"

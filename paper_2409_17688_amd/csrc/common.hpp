@@ -1,0 +1,90 @@
+// Internal helpers shared by the HIP translation units of libtropical.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tropical.h"
+
+namespace tp {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+constexpr uint16_t kInf16 = 0xFFFFu;
+constexpr uint8_t kInf8 = 0xFFu;
+
+// Saturating packed add and packed min: one v_pk_add_u16 (clamp) and one
+// v_pk_min_u16 per two lanes of 16-bit entries.  With entries in [0, INF]
+// the clamp makes INF absorbing, which is the semiring's rule a + INF = INF.
+__device__ __forceinline__ u16x2 pk_add_sat(u16x2 a, u16x2 b) {
+  return __builtin_elementwise_add_sat(a, b);
+}
+__device__ __forceinline__ u16x2 pk_min(u16x2 a, u16x2 b) {
+  return __builtin_elementwise_min(a, b);
+}
+__device__ __forceinline__ u16x2 splat(uint16_t v) { return u16x2{v, v}; }
+
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ u16x2 as_pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+
+// Host side: status plumbing.
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+}  // namespace tp
+
+#define TP_HIP_CHECK(expr)                                   \
+  do {                                                       \
+    hipError_t tp_e_ = (expr);                               \
+    if (tp_e_ != hipSuccess) return tp::hip_fail(tp_e_, #expr); \
+  } while (0)
+
+#define TP_REQUIRE(cond, ...)           \
+  do {                                  \
+    if (!(cond)) {                      \
+      tp::set_error(__VA_ARGS__);       \
+      return TP_EINVAL;                 \
+    }                                   \
+  } while (0)
+
+// Launchers implemented in the kernel translation units (host functions).
+namespace tp {
+
+// state.hip
+int64_t word_count_host(int n);
+hipError_t launch_words(int n, uint32_t *codes, uint8_t *zeros, uint32_t *masks, hipStream_t s);
+hipError_t launch_dense_state(int n, int64_t N, const uint32_t *masks, int dtype, void *A,
+                              int64_t lda, hipStream_t s);
+hipError_t launch_csr_count(int64_t N, int n, const uint32_t *masks, int64_t *rowptr,
+                            hipStream_t s);
+hipError_t launch_scan_rowptr(int64_t N, int64_t *rowptr, hipStream_t s);
+hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_t *rowptr,
+                           uint32_t *col, hipStream_t s);
+
+// gemm.hip
+hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
+                       const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
+                       int config, hipStream_t s);
+int gemm_config_count();
+
+// gemv.hip
+hipError_t launch_gemv(int dtype, int64_t M, int64_t K, const void *A, int64_t lda,
+                       const void *x, void *y, int trans, hipStream_t s);
+
+// spmm.hip
+hipError_t launch_spmm(int dtype, int64_t rows, const int64_t *rowptr, const uint32_t *col,
+                       const uint8_t *z, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                       int64_t ncols, hipStream_t s);
+hipError_t launch_sparse_trace(int dtype, int64_t N, const int64_t *rowptr, const uint32_t *col,
+                               const uint8_t *z, const void *X, int64_t ldx, int32_t *out,
+                               hipStream_t s);
+
+// trace.hip
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
+hipError_t launch_fill_bytes(void *p, size_t count, uint8_t value, hipStream_t s);
+hipError_t launch_trace_min(int dtype, int64_t N, const void *X, int64_t ldx, int32_t *out,
+                            hipStream_t s);
+hipError_t launch_trace_of_product(int dtype, int64_t N, const void *X, int64_t ldx,
+                                   const void *Y, int64_t ldy, int32_t *out, hipStream_t s);
+
+}  // namespace tp

@@ -1,0 +1,328 @@
+"""HIP path against the CPU oracle, element by element, through the C ABI.
+
+Every comparison is exact (integers).  Sizes span several tiles and ragged
+tails; the distributions stress INF handling and saturation, because the
+benchmark's own distribution makes almost every output 0.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from closed_form import gamma2_closed_form
+
+pytestmark = pytest.mark.gpu
+
+INF16, INF8 = 65535, 255
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2409_17688_amd as tp
+    return tp
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def np_dtype(code):
+    return np.uint16 if code == 2 else np.uint8
+
+
+def inf_of(code):
+    return INF16 if code == 2 else INF8
+
+
+# ------------------------------------------------------------------ state --
+
+def test_words_match_oracle(tp, oracle_mod):
+    for n in range(1, 13):
+        say("words n =", n)
+        got = host(tp.tp_words(n)).view(np.uint32)
+        assert np.array_equal(got, oracle_mod.words(n)), n
+
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_dense_state_matrix(tp, oracle_mod, dtype):
+    for n in range(1, 10):
+        say("state matrix n =", n, "dtype", dtype)
+        got = host(tp.tp_build_state_matrix(n, dtype)).astype(np.int32)
+        ref = oracle_mod.state_matrix(n, inf_of(dtype))
+        assert np.array_equal(got, ref), n
+
+
+def test_dense_state_matrix_padded_ld(tp, oracle_mod):
+    import torch
+    n, N = 5, 90
+    buf = torch.full((N, N + 13), 7, dtype=torch.uint16, device="cuda")
+    tp.tp_build_state_matrix(n, 2, out=buf[:, :N])
+    got = host(buf).astype(np.int32)
+    assert np.array_equal(got[:, :N], oracle_mod.state_matrix(n))
+    assert (got[:, N:] == 7).all()
+
+
+def test_csr_matches_dense(tp, oracle_mod):
+    for n in range(1, 10):
+        say("csr n =", n)
+        rowptr, col, z = tp.tp_build_state_csr(n)
+        rowptr, col, z = host(rowptr), host(col).view(np.uint32), host(z)
+        A = oracle_mod.state_matrix(n)
+        N = A.shape[0]
+        assert rowptr[0] == 0 and rowptr[-1] == (A < INF16).sum()
+        assert tp.tp_state_nnz(n) == int(rowptr[-1])
+        for q in range(N):
+            succ = np.nonzero(A[q] < INF16)[0]
+            assert np.array_equal(col[rowptr[q]:rowptr[q + 1]], succ), (n, q)
+        codes = oracle_mod.words(n)
+        assert np.array_equal(z, [oracle_mod.zeros(n, int(c)) for c in codes])
+
+
+# ------------------------------------------------------------------- gemm --
+
+SHAPES = [(1, 1, 1), (2, 3, 5), (63, 64, 65), (65, 63, 64), (128, 128, 32), (129, 257, 33),
+          (200, 130, 300), (256, 256, 256), (257, 129, 511), (64, 520, 7), (300, 70, 1)]
+DISTS = [  # (lo, hi, inf_frac)
+    (0, 24, 0.3), (0, 30000, 0.0), (0, 30000, 0.3), (0, 30000, 0.9), (0, 30000, 1.0),
+    (32000, 33000, 0.1),  # sums straddle INF = 65535
+]
+
+
+def _gemm_case(tp, oracle_mod, dtype, M, N, K, dist, seed, config, accumulate=False,
+               pad=0):
+    import torch
+    lo, hi, frac = dist
+    if dtype == 1:
+        hi = min(hi, 200)
+        lo = min(lo, 120)
+    A = synth.stress_matrix(M, K + pad, seed, lo, hi, frac, np_dtype(dtype))
+    B = synth.stress_matrix(K, N + pad, seed + 1, lo, hi, frac, np_dtype(dtype))
+    C0 = synth.stress_matrix(M, N + pad, seed + 2, 0, 60000 if dtype == 2 else 250, 0.2,
+                             np_dtype(dtype))
+    dA, dB, dC = dev(A), dev(B), dev(C0)
+    vA, vB, vC = dA[:, :K], dB[:, :N], dC[:, :N]
+    tp.tp_minplus_gemm(vA, vB, vC, accumulate=accumulate, config=config)
+    got = host(dC).astype(np.int32)
+    ref = oracle_mod.minplus(A[:, :K].astype(np.int32), B[:, :N].astype(np.int32),
+                             inf_of(dtype))
+    if accumulate:
+        ref = np.minimum(ref, C0[:, :N].astype(np.int32))
+    assert np.array_equal(got[:, :N], ref), (dtype, M, N, K, dist, config)
+    if pad:
+        assert np.array_equal(got[:, N:], C0[:, N:].astype(np.int32)), "wrote outside C"
+
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_gemm_every_config_shapes_dists(tp, oracle_mod, dtype):
+    ncfg = tp.tp_gemm_config_count()
+    seed = 10
+    for config in range(ncfg):
+        for (M, N, K) in SHAPES:
+            for dist in DISTS:
+                seed += 3
+                say("gemm", dtype, config, M, N, K, dist)
+                _gemm_case(tp, oracle_mod, dtype, M, N, K, dist, seed, config)
+
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_gemm_accumulate_and_padded_ld(tp, oracle_mod, dtype):
+    for config in [None] + list(range(tp.tp_gemm_config_count())):
+        for pad in (0, 3, 8):
+            say("gemm acc/pad", dtype, config, pad)
+            _gemm_case(tp, oracle_mod, dtype, 131, 77, 95, (0, 3000, 0.3), 99, config,
+                       accumulate=True, pad=pad)
+            _gemm_case(tp, oracle_mod, dtype, 64, 128, 40, (0, 24, 0.3), 98, config,
+                       accumulate=False, pad=pad)
+
+
+def test_gemm_empty_inner_dimension_gives_inf(tp):
+    import torch
+    A = torch.empty((5, 0), dtype=torch.uint16, device="cuda")
+    B = torch.empty((0, 7), dtype=torch.uint16, device="cuda")
+    C = tp.tp_minplus_gemm(A, B)
+    assert (host(C).astype(np.int64) == INF16).all()
+
+
+def test_gemm_real_powers(tp, oracle_mod):
+    """Products of actual state-matrix powers, u16 and u8."""
+    for n in (5, 6, 7):
+        P3, P4 = oracle_mod.power(n, 3), oracle_mod.power(n, 4)
+        say("gemm powers n =", n)
+        for config in range(tp.tp_gemm_config_count()):
+            got = host(tp.tp_minplus_gemm(dev(P3.astype(np.uint16)), dev(P4.astype(np.uint16)),
+                                          config=config)).astype(np.int32)
+            assert np.array_equal(got, oracle_mod.power(n, 7)), (n, config)
+        P3b = oracle_mod.power(n, 3, INF8)
+        got = host(tp.tp_minplus_gemm(dev(P3b.astype(np.uint8)), dev(P3b.astype(np.uint8))))
+        assert np.array_equal(got.astype(np.int32), oracle_mod.power(n, 6, INF8)), n
+
+
+@pytest.mark.parametrize("N", [4096])
+def test_gemm_benchmark_input_full(tp, oracle_mod, N):
+    """The benchmark's own input at N = 4096 (entries 0..24, 30 % INF, seed 0),
+    every output compared."""
+    A, B = synth.raw_gemm_pair(N, seed=0)
+    say("gemm full N =", N)
+    got = host(tp.tp_minplus_gemm(dev(A), dev(B))).astype(np.int32)
+    ref = oracle_mod.minplus(A.astype(np.int32), B.astype(np.int32))
+    assert np.array_equal(got, ref)
+
+
+def test_gemm_benchmark_input_8192_sampled_rows(tp, oracle_mod):
+    """N = 8192 in the benchmark's launch configuration; 64 seeded rows checked."""
+    N = 8192
+    A, B = synth.raw_gemm_pair(N, seed=0)
+    say("gemm N = 8192")
+    got = host(tp.tp_minplus_gemm(dev(A), dev(B)))
+    rows = np.random.default_rng(5).choice(N, size=64, replace=False)
+    rows = np.concatenate([rows, [0, N - 1]])
+    ref = oracle_mod.minplus_rows(A.astype(np.int32), B.astype(np.int32), rows)
+    assert np.array_equal(got[rows].astype(np.int32), ref)
+
+
+# ------------------------------------------------------------------- gemv --
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_gemv(tp, oracle_mod, dtype):
+    seed = 3
+    for (M, K) in [(1, 1), (5, 3), (63, 65), (130, 700), (1000, 513), (4099, 77), (33, 5000)]:
+        for dist in DISTS:
+            seed += 2
+            lo, hi, frac = dist
+            if dtype == 1:
+                hi, lo = min(hi, 200), min(lo, 120)
+            A = synth.stress_matrix(M, K, seed, lo, hi, frac, np_dtype(dtype))
+            x = synth.stress_matrix(1, K, seed + 1, lo, hi, frac, np_dtype(dtype))[0]
+            xt = synth.stress_matrix(1, M, seed + 2, lo, hi, frac, np_dtype(dtype))[0]
+            say("gemv", dtype, M, K, dist)
+            y = host(tp.tp_minplus_gemv(dev(A), dev(x))).astype(np.int32)
+            ref = oracle_mod.minplus(A.astype(np.int32), x.astype(np.int32)[:, None],
+                                     inf_of(dtype))[:, 0]
+            assert np.array_equal(y, ref), ("A x", M, K, dist)
+            yt = host(tp.tp_minplus_gemv(dev(A), dev(xt), trans=True)).astype(np.int32)
+            reft = oracle_mod.minplus(xt.astype(np.int32)[None, :], A.astype(np.int32),
+                                      inf_of(dtype))[0]
+            assert np.array_equal(yt, reft), ("x A", M, K, dist)
+
+
+# ------------------------------------------------------------------- spmm --
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_spmm_state_matrix_times_dense(tp, oracle_mod, dtype):
+    for n in (1, 2, 3, 5, 7, 8):
+        rowptr, col, z = tp.tp_build_state_csr(n)
+        A = oracle_mod.state_matrix(n, inf_of(dtype))
+        N = A.shape[0]
+        for ncols in (1, 7, 64, 513, N):
+            for dist in [(0, 24, 0.3), (0, 30000, 0.5), (65000, 65534, 0.0)]:
+                lo, hi, frac = dist
+                if dtype == 1:
+                    hi, lo = min(hi, 250), min(lo, 240)
+                X = synth.stress_matrix(N, ncols, n * 100 + ncols, lo, hi, frac, np_dtype(dtype))
+                say("spmm", dtype, n, ncols, dist)
+                Y = host(tp.tp_minplus_spmm(rowptr, col, z, dev(X))).astype(np.int32)
+                ref = oracle_mod.minplus(A, X.astype(np.int32), inf_of(dtype))
+                assert np.array_equal(Y, ref), (n, ncols, dist)
+
+
+def test_spmm_chain_gives_powers(tp, oracle_mod):
+    import torch
+    for n in (4, 6, 8):
+        rowptr, col, z = tp.tp_build_state_csr(n)
+        X = tp.tp_build_state_matrix(n, 2)
+        for k in range(2, 7):
+            X = tp.tp_minplus_spmm(rowptr, col, z, X)
+        say("spmm chain n =", n)
+        assert np.array_equal(host(X).astype(np.int32), oracle_mod.power(n, 6))
+
+
+# ----------------------------------------------------------------- traces --
+
+@pytest.mark.parametrize("dtype", [2, 1])
+def test_traces(tp, oracle_mod, dtype):
+    for N in (1, 2, 63, 64, 65, 200, 777):
+        for dist in [(0, 24, 0.3), (0, 30000, 0.9), (32000, 34000, 0.0), (0, 10, 1.0)]:
+            lo, hi, frac = dist
+            if dtype == 1:
+                hi, lo = min(hi, 200), min(lo, 120)
+            X = synth.stress_matrix(N, N, N + 1, lo, hi, frac, np_dtype(dtype))
+            Y = synth.stress_matrix(N, N, N + 2, lo, hi, frac, np_dtype(dtype))
+            say("trace", dtype, N, dist)
+            t = int(host(tp.tp_trace_min(dev(X)))[0])
+            assert t == oracle_mod.trace_min(X.astype(np.int32), inf_of(dtype))
+            tt = int(host(tp.tp_trace_of_product(dev(X), dev(Y)))[0])
+            prod = oracle_mod.minplus(X.astype(np.int32), Y.astype(np.int32), inf_of(dtype))
+            assert tt == oracle_mod.trace_min(prod, inf_of(dtype)), (N, dist)
+
+
+def test_sparse_trace(tp, oracle_mod):
+    for n in (2, 4, 6, 8):
+        rowptr, col, z = tp.tp_build_state_csr(n)
+        for k in (1, 2, 5):
+            Xk = oracle_mod.power(n, k)
+            say("sparse trace", n, k)
+            got = int(host(tp.tp_sparse_trace_of_product(rowptr, col, z,
+                                                         dev(Xk.astype(np.uint16))))[0])
+            assert got == oracle_mod.trace_min(oracle_mod.power(n, k + 1)), (n, k)
+
+
+# ---------------------------------------------------------------- gamma_2 --
+
+def test_power_trace_vs_oracle(tp, oracle_mod):
+    for n in range(1, 9):
+        g = oracle_mod.gamma2_sweep(n, 60)
+        for m in list(range(3, 41)) + [47, 53, 60]:
+            say("power_trace", n, m)
+            assert tp.tp_tropical_power_trace(n, m) == g[m - 1], (n, m)
+
+
+def test_power_trace_config1_n3(tp, oracle_mod):
+    """n = 3, m = 3..30: oracle, and exhaustive search for m <= 10."""
+    g = oracle_mod.gamma2_sweep(3, 30, INF8)
+    for m in range(3, 31):
+        got = tp.tp_tropical_power_trace(3, m)
+        assert got == g[m - 1] == -(-4 * m // 3)
+        if m <= 10:
+            assert got == oracle_mod.brute_gamma2(3, m)
+
+
+def test_power_trace_u8_chain_config1(tp, oracle_mod):
+    """The 8-bit storage path of the method: A(D_3) with INF = 255, chained with
+    the sparse left product and read with the diagonal trace."""
+    rowptr, col, z = tp.tp_build_state_csr(3)
+    X = tp.tp_build_state_matrix(3, 1)
+    g = oracle_mod.gamma2_sweep(3, 30, INF8)
+    for m in range(2, 31):
+        X = tp.tp_minplus_spmm(rowptr, col, z, X)
+        if m >= 3:
+            t = int(host(tp.tp_trace_min(X))[0])
+            assert t == g[m - 1], m
+
+
+def test_power_trace_larger_n_closed_form(tp):
+    cases = [(9, m) for m in (3, 4, 5, 17, 50, 101)] + [(10, m) for m in (3, 5, 8, 31, 64)] + \
+            [(11, m) for m in (3, 5, 7, 24)] + [(12, m) for m in (3, 4, 5)]
+    for n, m in cases:
+        say("power_trace closed form", n, m)
+        assert tp.tp_tropical_power_trace(n, m) == gamma2_closed_form(n, m), (n, m)
+
+
+def test_power_trace_repeatable(tp):
+    a = [tp.tp_tropical_power_trace(8, m) for m in (3, 100, 256)]
+    b = [tp.tp_tropical_power_trace(8, m) for m in (3, 100, 256)]
+    assert a == b == [gamma2_closed_form(8, m) for m in (3, 100, 256)]
