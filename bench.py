@@ -27,10 +27,12 @@ sys.path.insert(0, ROOT)
 PEAK_MINPLUS = 256 * 64 * 2.4e9
 N_DEFAULT = 8192
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
-# dispatch, scaled by the copy-kernel calibration factor); None until measured
-# for the current kernel.
-MEASURED_TRAFFIC_BYTES = None
+# HBM bytes per launch of the N = 8192 product from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, each scaled by what the counter reads for a
+# plain 256 MiB copy: factors 2.00 and 1.00).  Valid for the kernel named
+# below only; set to None when that kernel changes until it is measured again.
+MEASURED_TRAFFIC = {"kernel": "minplus_gemm_kernel<128,256,32,8,16,3,u16,vec>",
+                    "bytes": (1049903 * 2.00 + 131072 * 1.00) * 1024}
 
 
 def parse():
@@ -42,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device-to-device copy before the product, as "
+                         "the reference point for HBM byte counters")
     return ap.parse_args()
 
 
@@ -54,11 +59,13 @@ def cpu_baseline(A, B, target_s):
     Ai = A.astype(np.int32)
     Bi = B.astype(np.int32)
     N = A.shape[0]
-    rows = 8
-    t0 = time.perf_counter()
-    oracle.minplus(Ai[:rows], Bi)
-    dt = time.perf_counter() - t0
-    rows = int(max(8, min(N, rows * target_s / max(dt, 1e-6))))
+    rows, dt = 16, 0.0
+    while dt < 0.2 * target_s and rows < N:
+        rows = min(N, rows * 2)
+        t0 = time.perf_counter()
+        oracle.minplus(Ai[:rows], Bi)
+        dt = time.perf_counter() - t0
+    rows = int(max(16, min(N, rows * target_s / max(dt, 1e-6))))
     t0 = time.perf_counter()
     oracle.minplus(Ai[:rows], Bi)
     dt = time.perf_counter() - t0
@@ -88,6 +95,12 @@ def main():
     dB = torch.from_numpy(B).to(dev)
     dC = torch.empty((N, N), dtype=torch.uint16, device=dev)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         tp.tp_minplus_gemm(dA, dB, dC, stream=stream)
     torch.cuda.synchronize()
@@ -137,7 +150,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(PEAK_MINPLUS / 1e12, 3), "unit": "Tminplus-ops/s",
                      "frac": round(achieved / PEAK_MINPLUS, 4),
-                     "traffic": MEASURED_TRAFFIC_BYTES},
+                     "traffic": (round(MEASURED_TRAFFIC["bytes"])
+                                 if MEASURED_TRAFFIC and N == N_DEFAULT else None)},
         "kernel_ms": round(avg_kernel_s * 1e3, 3),
     }
     if not args.no_cpu:
