@@ -163,6 +163,44 @@ int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t 
 /* Frees the process-wide cache used by tp_tropical_power_trace. */
 int tp_release_cache(void);
 
+/* ------------------------------------------------------------------------ */
+/* Batching: many (n, m) instances in one persistent launch.                  */
+/* ------------------------------------------------------------------------ */
+
+/* A context keeps, per path order n, the powers A^1..A^K of the chain of
+ * Algorithm 2 resident in device memory (u16, rows padded to 64 entries), at
+ * most hbm_budget_bytes in total, and answers instances from them: with
+ * a = ceil(m/2), b = floor(m/2), gamma_2(P_n x C_m) = trace of A^a x A^b
+ * (Theorem 2).  Powers persist across batches until the context is destroyed.
+ * A context is used from one host thread and one stream at a time. */
+int tp_ctx_create(size_t hbm_budget_bytes, void **ctx);
+int tp_ctx_destroy(void *ctx);
+
+/* Tuning and test parameters of a context. */
+#define TP_PARAM_WAIT_LIMIT_US 1 /* bound on one dependency wait (default 20 s) */
+#define TP_PARAM_GRID 2          /* workgroups of the persistent kernel; 0 = fill the chip */
+#define TP_PARAM_SPMM_ROWS 16    /* TP_PARAM_SPMM_ROWS + n: rows per chain task; 0 = auto */
+int tp_ctx_set_param(void *ctx, int param, int64_t value);
+
+/* Bytes of resident powers held by the context. */
+int64_t tp_ctx_resident_bytes(void *ctx);
+
+/* gamma2_dev[j] (device int32) = gamma_2(P_{n[j]} x C_{m[j]}) for j < count,
+ * with n (host int32) in 1..12 and m (host int64) >= 3, n*m < 65535.  Queues
+ * the missing chain levels of every distinct n, the dense first powers and
+ * one trace per instance as one task queue, run by one persistent kernel
+ * launch from a captured hipGraph on `stream`; returns without waiting.
+ * TP_ENOMEM when the needed powers exceed the context's budget (nothing is
+ * queued).  Results of a batch are valid after tp_ctx_check returns TP_OK. */
+int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,
+                         int32_t *gamma2_dev, hipStream_t stream);
+
+/* Waits for `stream` and reports whether the batches queued since the last
+ * check completed: TP_OK, or TP_ECANCELED when a task's wait for its inputs
+ * exceeded the wait limit (the kernel then drains without computing, the
+ * results are invalid and the levels it was to compute are dropped). */
+int tp_ctx_check(void *ctx, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

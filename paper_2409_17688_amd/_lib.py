@@ -27,6 +27,9 @@ TP_EOVERFLOW = -3
 TP_EHIP = -4
 TP_EBUSY = -5
 TP_ECANCELED = -6
+TP_PARAM_WAIT_LIMIT_US = 1
+TP_PARAM_GRID = 2
+TP_PARAM_SPMM_ROWS = 16
 
 INF = {TP_U8: 255, TP_U16: 65535}
 
@@ -58,6 +61,12 @@ _SIGS = {
     "tp_sparse_trace_of_product": ([_i, _i64, _p, _p, _p, _p, _i64, _p, _p], _i),
     "tp_tropical_power_trace": ([_i, _i64, ctypes.POINTER(ctypes.c_int32), _p], _i),
     "tp_release_cache": ([], _i),
+    "tp_ctx_create": ([ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)], _i),
+    "tp_ctx_destroy": ([_p], _i),
+    "tp_ctx_set_param": ([_p, _i, _i64], _i),
+    "tp_ctx_resident_bytes": ([_p], _i64),
+    "tp_batch_power_trace": ([_p, _i, _p, _p, _p, _p], _i),
+    "tp_ctx_check": ([_p, _p], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -293,3 +302,46 @@ def tp_release_cache() -> None:
 
 def tp_last_error() -> str:
     return lib.tp_last_error().decode(errors="replace")
+
+
+# --------------------------------------------------------------- batching --
+
+def tp_ctx_create(hbm_budget_bytes: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.tp_ctx_create(int(hbm_budget_bytes), ctypes.byref(h)))
+    return h.value
+
+
+def tp_ctx_destroy(ctx: int) -> None:
+    _check(lib.tp_ctx_destroy(ctx))
+
+
+def tp_ctx_set_param(ctx: int, param: int, value: int) -> None:
+    _check(lib.tp_ctx_set_param(ctx, int(param), int(value)))
+
+
+def tp_ctx_resident_bytes(ctx: int) -> int:
+    return _check(int(lib.tp_ctx_resident_bytes(ctx)))
+
+
+def tp_batch_power_trace(ctx: int, ns, ms, out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    """Queues gamma_2 for every (ns[j], ms[j]); returns the device int32 result
+    tensor (valid once tp_ctx_check has returned)."""
+    import numpy as np
+    n_arr = np.ascontiguousarray(ns, dtype=np.int32)
+    m_arr = np.ascontiguousarray(ms, dtype=np.int64)
+    if n_arr.shape != m_arr.shape or n_arr.ndim != 1:
+        raise ValueError("ns and ms must be 1-D of one length")
+    count = int(n_arr.size)
+    if out is None:
+        out = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
+    if out.numel() < count or out.dtype != torch.int32:
+        raise ValueError("out must hold count int32 entries")
+    _check(lib.tp_batch_power_trace(ctx, count, n_arr.ctypes.data, m_arr.ctypes.data,
+                                    out.data_ptr(), _stream(stream)))
+    return out[:count]
+
+
+def tp_ctx_check(ctx: int, stream=None) -> None:
+    _check(lib.tp_ctx_check(ctx, _stream(stream)))

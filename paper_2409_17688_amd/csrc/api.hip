@@ -180,8 +180,8 @@ Plan choose_plan(int64_t m, double N, double nnz) {
 
 // Square-and-multiply: dst = P^q (q >= 1), P untouched; uses tmp.  Returns
 // the buffer that holds the result (dst or P itself when q == 1).
-int power_of(uint16_t *P, int64_t q, int64_t N, uint16_t *dst, uint16_t *tmp, hipStream_t s,
-             uint16_t **result) {
+int power_of(uint16_t *P, int64_t q, int64_t N, int64_t ld, uint16_t *dst, uint16_t *tmp,
+             hipStream_t s, uint16_t **result) {
   if (q == 1) {
     *result = P;
     return TP_OK;
@@ -193,12 +193,12 @@ int power_of(uint16_t *P, int64_t q, int64_t N, uint16_t *dst, uint16_t *tmp, hi
   int which = 0;
   for (int b = top - 1; b >= 0; --b) {
     uint16_t *o = bufs[which];
-    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, N, cur, N, o, N, 0, -1, s));
+    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, cur, ld, o, ld, 0, -1, s));
     cur = o;
     which ^= 1;
     if ((q >> b) & 1) {
       uint16_t *o2 = bufs[which];
-      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, N, P, N, o2, N, 0, -1, s));
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, P, ld, o2, ld, 0, -1, s));
       cur = o2;
       which ^= 1;
     }
@@ -213,7 +213,10 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
   if (rc != TP_OK) return rc;
   const int64_t N = st->N;
   Workspace &ws = g_ws[current_device()];
-  const size_t mat = (size_t)N * (size_t)N * sizeof(uint16_t);
+  // rows padded to 64 entries (128 bytes) so every row starts aligned for
+  // 16-byte loads whatever N is
+  const int64_t ld = (N + 63) / 64 * 64;
+  const size_t mat = (size_t)N * (size_t)ld * sizeof(uint16_t);
   const Plan plan = choose_plan(m, (double)N, (double)st->nnz);
   const int64_t c = plan.c, q = m / c, r = m % c;
 
@@ -228,13 +231,13 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
 
   // X = A^1, then the chain up to A^c
   const uint32_t *masks = (const uint32_t *)st->masks.ptr;
-  TP_HIP_CHECK(launch_dense_state(n, N, masks, TP_U16, X, N, s));
+  TP_HIP_CHECK(launch_dense_state(n, N, masks, TP_U16, X, ld, s));
   if (r == 1) TP_HIP_CHECK(hipMemcpyAsync(snap, X, mat, hipMemcpyDeviceToDevice, s));
   const int64_t *rowptr = (const int64_t *)st->rowptr.ptr;
   const uint32_t *col = (const uint32_t *)st->col.ptr;
   const uint8_t *z = (const uint8_t *)st->z.ptr;
   for (int64_t k = 2; k <= c; ++k) {
-    TP_HIP_CHECK(launch_spmm(TP_U16, N, rowptr, col, z, X, N, Y, N, N, s));
+    TP_HIP_CHECK(launch_spmm(TP_U16, N, rowptr, col, z, X, ld, Y, ld, N, s));
     uint16_t *t = X;
     X = Y;
     Y = t;
@@ -243,25 +246,25 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
   // X = A^c
   if (r > 0) {
     uint16_t *R = nullptr;
-    rc = power_of(X, q, N, (uint16_t *)ws.buf[pw].ptr, (uint16_t *)ws.buf[pw + 1].ptr, s, &R);
+    rc = power_of(X, q, N, ld, (uint16_t *)ws.buf[pw].ptr, (uint16_t *)ws.buf[pw + 1].ptr, s, &R);
     if (rc != TP_OK) return rc;
-    TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, R, N, snap, N, d_res, s));
+    TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, R, ld, snap, ld, d_res, s));
   } else if (q == 1) {
-    TP_HIP_CHECK(launch_trace_min(TP_U16, N, X, N, d_res, s));
+    TP_HIP_CHECK(launch_trace_min(TP_U16, N, X, ld, d_res, s));
   } else {
     const int64_t h = q / 2;
     uint16_t *H = nullptr;
     uint16_t *tmp_a = (uint16_t *)ws.buf[pw].ptr, *tmp_b = (uint16_t *)ws.buf[pw + 1].ptr;
-    rc = power_of(X, h, N, tmp_a, tmp_b, s, &H);
+    rc = power_of(X, h, N, ld, tmp_a, tmp_b, s, &H);
     if (rc != TP_OK) return rc;
     if (q & 1) {
       // H x X = P^(h+1) into a buffer that is neither H nor X
       uint16_t *o = (H == tmp_a) ? tmp_b : tmp_a;
       if (H == X) o = tmp_a;
-      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, N, X, N, o, N, 0, -1, s));
-      TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, N, o, N, d_res, s));
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, ld, X, ld, o, ld, 0, -1, s));
+      TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, ld, o, ld, d_res, s));
     } else {
-      TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, N, H, N, d_res, s));
+      TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, ld, H, ld, d_res, s));
     }
   }
   int32_t host = 0;
@@ -272,6 +275,22 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
 }
 
 }  // namespace
+
+int state_view(int n, hipStream_t s, StateView *out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  const int rc = get_state(n, s, &st);
+  if (rc != TP_OK) return rc;
+  out->n = n;
+  out->N = st->N;
+  out->nnz = st->nnz;
+  out->masks = (const uint32_t *)st->masks.ptr;
+  out->rowptr = (const int64_t *)st->rowptr.ptr;
+  out->col = (const uint32_t *)st->col.ptr;
+  out->z = (const uint8_t *)st->z.ptr;
+  return TP_OK;
+}
+
 }  // namespace tp
 
 using namespace tp;

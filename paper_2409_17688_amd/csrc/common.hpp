@@ -24,6 +24,15 @@ __device__ __forceinline__ u16x2 pk_min(u16x2 a, u16x2 b) {
 }
 __device__ __forceinline__ u16x2 splat(uint16_t v) { return u16x2{v, v}; }
 
+// The hardware deals consecutive workgroups to the 8 XCDs in turn.  This maps
+// the workgroup id to a work index such that each XCD receives a contiguous
+// range of [0, total) (a bijection), so neighbouring work shares an L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
+  const int64_t q = total >> 3, r = total & 7;
+  const int64_t x = bid & 7, local = bid >> 3;
+  return x * q + (x < r ? x : r) + local;
+}
+
 __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ u16x2 as_pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 
@@ -49,6 +58,18 @@ int hip_fail(hipError_t e, const char *what);
 
 // Launchers implemented in the kernel translation units (host functions).
 namespace tp {
+
+// Device-resident description of A(D_n) from the process-wide cache (api.hip);
+// pointers stay valid until tp_release_cache.
+struct StateView {
+  int n;
+  int64_t N, nnz;
+  const uint32_t *masks;
+  const int64_t *rowptr;
+  const uint32_t *col;
+  const uint8_t *z;
+};
+int state_view(int n, hipStream_t s, StateView *out);
 
 // state.hip
 int64_t word_count_host(int n);

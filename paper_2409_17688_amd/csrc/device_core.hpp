@@ -1,0 +1,206 @@
+// Device building blocks shared by the one-shot kernels and the persistent
+// batch kernel: the "can follow" test, one 16-byte chunk of a sparse left
+// product row, and one 64 x 64 tile of a trace of a product.
+#pragma once
+
+#include "common.hpp"
+
+namespace tp {
+
+// p can follow q (Section 2.2).  Masks hold the zeros of a word in bits
+// 0..15 and its ones in bits 16..31; `full` has the low n bits set.  With
+// x = zeros of q, y = zeros of p shifted to the next position, w = zeros of p
+// shifted to the previous one, "exactly one zero among q_i, p_{i-1}, p_{i+1}"
+// and "at least two" are bitwise functions of x, y, w.
+__device__ __forceinline__ bool can_follow(uint32_t mq, uint32_t mp, uint32_t full) {
+  const uint32_t zq = mq & 0xFFFFu, oq = mq >> 16, tq = full & ~(zq | oq);
+  const uint32_t zp = mp & 0xFFFFu, op = mp >> 16, tp = full & ~(zp | op);
+  const uint32_t x = zq, y = (zp << 1) & full, w = zp >> 1;
+  const uint32_t exactly_one = (x ^ y ^ w) & ~(x & y & w);
+  const uint32_t two_or_more = (x & y) | (x & w) | (y & w);
+  return ((tq & ~zp) | (tp & ~exactly_one) | (op & ~two_or_more)) == 0;
+}
+
+template <typename T>
+__device__ __forceinline__ uint16_t storage_inf() {
+  return sizeof(T) == 2 ? (uint16_t)0xFFFFu : (uint16_t)0xFFu;
+}
+
+// 16 bytes of row `row` of X from column `col`, as packed 16-bit pairs;
+// columns >= ncols read as the storage INF.
+template <typename T, bool VEC>
+__device__ __forceinline__ void load_row_chunk(const T *__restrict__ X, int64_t ldx, int64_t row,
+                                               int64_t col, int64_t ncols,
+                                               u16x2 (&out)[16 / sizeof(T) / 2]) {
+  constexpr int VE = 16 / sizeof(T);
+  const T *p = X + row * ldx + col;
+  if (VEC && col + VE <= ncols) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    if constexpr (sizeof(T) == 2) {
+      out[0] = as_pk(v.x);
+      out[1] = as_pk(v.y);
+      out[2] = as_pk(v.z);
+      out[3] = as_pk(v.w);
+    } else {
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // bytes b0 b1 b2 b3 -> (b0, b1), (b2, b3) widened to 16 bits
+        out[2 * e] = as_pk(__builtin_amdgcn_perm(0u, w[e], 0x0c010c00u));
+        out[2 * e + 1] = as_pk(__builtin_amdgcn_perm(0u, w[e], 0x0c030c02u));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < VE / 2; ++e) {
+      const int64_t c0 = col + 2 * e, c1 = c0 + 1;
+      const uint16_t x0 = c0 < ncols ? (uint16_t)p[2 * e] : storage_inf<T>();
+      const uint16_t x1 = c1 < ncols ? (uint16_t)p[2 * e + 1] : storage_inf<T>();
+      out[e] = u16x2{x0, x1};
+    }
+  }
+}
+
+// Y[q][c0 .. c0+VE) = min over successors p of q of (z_p + X[p][c0 ..]):
+// one lane's chunk of row q of the sparse left product.  The successor list
+// is the same for every lane of the wave.
+template <typename T, bool VEC>
+__device__ __forceinline__ void spmm_row_chunk(const int64_t *__restrict__ rowptr,
+                                               const uint32_t *__restrict__ col,
+                                               const uint8_t *__restrict__ z,
+                                               const T *__restrict__ X, int64_t ldx,
+                                               T *__restrict__ Y, int64_t ldy, int64_t ncols,
+                                               int64_t q, int64_t c0) {
+  constexpr int VE = 16 / sizeof(T);
+  constexpr int P = VE / 2;  // packed registers per lane
+  const int64_t begin = rowptr[q], end = rowptr[q + 1];
+  u16x2 acc[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) acc[e] = splat(0xFFFFu);
+  int64_t e = begin;
+  constexpr int U = 8;  // successor rows in flight per lane
+  for (; e + U <= end; e += U) {
+    u16x2 v[U][P];
+    uint16_t lab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t p = col[e + u];
+      lab[u] = z[p];
+      load_row_chunk<T, VEC>(X, ldx, p, c0, ncols, v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < P; ++r) acc[r] = pk_min(acc[r], pk_add_sat(splat(lab[u]), v[u][r]));
+  }
+  for (; e < end; ++e) {
+    const uint32_t p = col[e];
+    u16x2 v[P];
+    load_row_chunk<T, VEC>(X, ldx, p, c0, ncols, v);
+    const uint16_t lab = z[p];
+#pragma unroll
+    for (int r = 0; r < P; ++r) acc[r] = pk_min(acc[r], pk_add_sat(splat(lab), v[r]));
+  }
+  T *yrow = Y + q * ldy + c0;
+  if constexpr (sizeof(T) == 1) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) acc[r] = pk_min(acc[r], splat(0xFFu));
+  }
+  if (VEC && c0 + VE <= ncols) {
+    uint4 w;
+    if constexpr (sizeof(T) == 2) {
+      w = uint4{as_u32(acc[0]), as_u32(acc[1]), as_u32(acc[2]), as_u32(acc[3])};
+    } else {
+      uint32_t o[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        o[k] = __builtin_amdgcn_perm(as_u32(acc[2 * k + 1]), as_u32(acc[2 * k]), 0x06040200u);
+      w = uint4{o[0], o[1], o[2], o[3]};
+    }
+    *reinterpret_cast<uint4 *>(yrow) = w;
+  } else {
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      if (c0 + 2 * r < ncols) yrow[2 * r] = (T)acc[r].x;
+      if (c0 + 2 * r + 1 < ncols) yrow[2 * r + 1] = (T)acc[r].y;
+    }
+  }
+}
+
+// Eight consecutive entries of row `row` from column `col`, widened to 16
+// bits; entries outside [0, n) x [0, n) read as 0xFFFF.
+template <typename T, bool VEC>
+__device__ __forceinline__ uint4 load8(const T *__restrict__ M, int64_t ld, int64_t row,
+                                       int64_t col, int64_t n) {
+  const T *p = M + row * ld + col;
+  if (VEC && row < n && col + 8 <= n) {
+    if constexpr (sizeof(T) == 2) {
+      return *reinterpret_cast<const uint4 *>(p);
+    } else {
+      const uint2 v = *reinterpret_cast<const uint2 *>(p);
+      return uint4{__builtin_amdgcn_perm(0u, v.x, 0x0c010c00u),
+                   __builtin_amdgcn_perm(0u, v.x, 0x0c030c02u),
+                   __builtin_amdgcn_perm(0u, v.y, 0x0c010c00u),
+                   __builtin_amdgcn_perm(0u, v.y, 0x0c030c02u)};
+    }
+  }
+  uint32_t w[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t lo = (row < n && col + 2 * e < n) ? (uint32_t)p[2 * e] : 0xFFFFu;
+    const uint32_t hi = (row < n && col + 2 * e + 1 < n) ? (uint32_t)p[2 * e + 1] : 0xFFFFu;
+    w[e] = lo | (hi << 16);
+  }
+  return uint4{w[0], w[1], w[2], w[3]};
+}
+
+constexpr int kTraceLdsStride = 72;  // entries; 144-byte rows keep 16-byte reads aligned
+
+// Folds min over i in [i0, i0+64), k in [k0, k0+64) of x_ik + y_ki into acc.
+// Called by all 256 lanes of a workgroup; yt is 64 * kTraceLdsStride entries
+// of LDS.  Ends with a barrier, so yt can be reused right away.
+template <typename T, bool VEC>
+__device__ __forceinline__ void trace_tile(const T *__restrict__ X, int64_t ldx,
+                                           const T *__restrict__ Y, int64_t ldy, int64_t N,
+                                           int64_t i0, int64_t k0, uint16_t *yt,
+                                           u16x2 (&acc)[4]) {
+  constexpr int S = kTraceLdsStride;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = tid + h * 256;  // chunk: row kr of the Y tile, columns ch*8 .. ch*8+7
+    const int kr = c >> 3, ch = c & 7;
+    const uint4 v = load8<T, VEC>(Y, ldy, k0 + kr, i0 + ch * 8, N);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) yt[(ch * 8 + e) * S + kr] = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = tid + h * 256;  // chunk: row ir of the X tile, columns kc*8 .. kc*8+7
+    const int ir = c >> 3, kc = c & 7;
+    const uint4 xv = load8<T, VEC>(X, ldx, i0 + ir, k0 + kc * 8, N);
+    const uint4 yv = *reinterpret_cast<const uint4 *>(&yt[ir * S + kc * 8]);
+    acc[0] = pk_min(acc[0], pk_add_sat(as_pk(xv.x), as_pk(yv.x)));
+    acc[1] = pk_min(acc[1], pk_add_sat(as_pk(xv.y), as_pk(yv.y)));
+    acc[2] = pk_min(acc[2], pk_add_sat(as_pk(xv.z), as_pk(yv.z)));
+    acc[3] = pk_min(acc[3], pk_add_sat(as_pk(xv.w), as_pk(yv.w)));
+  }
+  __syncthreads();
+}
+
+// Minimum of the four packed accumulators over the whole workgroup (256
+// lanes); the result is valid in lane 0.  `part` is 4 ints of LDS.
+__device__ __forceinline__ int32_t block_min(const u16x2 (&acc)[4], int32_t *part) {
+  const u16x2 m2 = pk_min(pk_min(acc[0], acc[1]), pk_min(acc[2], acc[3]));
+  int32_t best = min((int32_t)m2.x, (int32_t)m2.y);
+  for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __syncthreads();
+  best = min(min(part[0], part[1]), min(part[2], part[3]));
+  __syncthreads();
+  return best;
+}
+
+}  // namespace tp

@@ -22,7 +22,7 @@
 // sets are bitwise functions of x, y, w, so the test is a handful of integer
 // operations for all n positions at once.  The arc label is the number of
 // zeros of p.
-#include "common.hpp"
+#include "device_core.hpp"
 
 namespace tp {
 
@@ -94,16 +94,6 @@ __global__ void words_kernel(int n, uint32_t total, uint32_t *__restrict__ codes
   if (codes) codes[rank] = x;
   if (zeros) zeros[rank] = (uint8_t)__builtin_popcount(zm);
   if (masks) masks[rank] = zm | (om << 16);
-}
-
-// p can follow q (masks as built by words_kernel).
-__device__ __forceinline__ bool can_follow(uint32_t mq, uint32_t mp, uint32_t full) {
-  uint32_t zq = mq & 0xFFFFu, oq = mq >> 16, tq = full & ~(zq | oq);
-  uint32_t zp = mp & 0xFFFFu, op = mp >> 16, tp = full & ~(zp | op);
-  uint32_t x = zq, y = (zp << 1) & full, w = zp >> 1;
-  uint32_t exactly_one = (x ^ y ^ w) & ~(x & y & w);
-  uint32_t two_or_more = (x & y) | (x & w) | (y & w);
-  return ((tq & ~zp) | (tp & ~exactly_one) | (op & ~two_or_more)) == 0;
 }
 
 template <typename T, T INF>

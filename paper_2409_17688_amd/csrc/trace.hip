@@ -6,9 +6,11 @@
 //                                                     reads 2 N^2 entries
 // The second one closes a power chain without forming its last product: with
 // X = A^a and Y = A^b it gives gamma_2 for m = a + b at the price of one pass
-// over two matrices, which is bound by HBM bandwidth.  Y is read in 64 x 64
-// tiles through LDS so that both matrices stream row-wise.
-#include "common.hpp"
+// over two matrices, which is bound by HBM bandwidth.  Both matrices stream
+// row-wise in 16-byte loads; Y's 64 x 64 tiles are transposed through LDS.
+#include <algorithm>
+
+#include "device_core.hpp"
 
 namespace tp {
 
@@ -44,52 +46,26 @@ __global__ void __launch_bounds__(1024) trace_min_kernel(int64_t N, const T *__r
   }
 }
 
-// One workgroup per 64 x 64 tile (i-block, k-block): every x_ik + y_ki of the
-// tile, reduced and folded into *out with an atomic min.
-template <typename T>
+// Workgroups walk 64 x 64 tiles (i-block, k-block) with a grid stride.  The
+// Y tile Y[k-block][i-block] is staged transposed in LDS so that x_ik and
+// y_ki meet as two 16-byte rows; the partial minimum is folded into *out with
+// one atomic per workgroup.
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(256) trace_of_product_kernel(int64_t N, const T *__restrict__ X,
                                                                int64_t ldx,
                                                                const T *__restrict__ Y,
-                                                               int64_t ldy, int tiles,
+                                                               int64_t ldy, int64_t tiles,
                                                                int32_t *__restrict__ out) {
-  __shared__ uint16_t yt[64][65];  // yt[i][k] = Y[k0 + k][i0 + i]
+  __shared__ __attribute__((aligned(16))) uint16_t yt[64 * kTraceLdsStride];
   __shared__ int32_t part[4];
-  const int tid = threadIdx.x;
-  const int ti = blockIdx.x % tiles, tk = blockIdx.x / tiles;
-  const int64_t i0 = (int64_t)ti * 64, k0 = (int64_t)tk * 64;
-  const int32_t inf = inf_of<T>();
-  // stage Y[k0..k0+63][i0..i0+63] transposed: thread reads row k, 16 columns
-  {
-    const int kr = tid >> 2, ic = (tid & 3) * 16;
-    const int64_t k = k0 + kr;
+  u16x2 acc[4];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t i = i0 + ic + e;
-      yt[ic + e][kr] = (k < N && i < N) ? (uint16_t)Y[k * ldy + i] : (uint16_t)inf;
-    }
-  }
-  __syncthreads();
-  // each thread: row i = i0 + tid / 4, 16 consecutive k
-  int32_t best = inf;
-  {
-    const int ir = tid >> 2, kc = (tid & 3) * 16;
-    const int64_t i = i0 + ir;
-    if (i < N) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t k = k0 + kc + e;
-        if (k < N) best = min(best, (int32_t)X[i * ldx + k] + (int32_t)yt[ir][kc + e]);
-      }
-    }
-  }
-  best = min(best, inf);
-  for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
-  if ((tid & 63) == 0) part[tid >> 6] = best;
-  __syncthreads();
-  if (tid == 0) {
-    best = min(min(part[0], part[1]), min(part[2], part[3]));
-    if (best < inf) atomicMin(out, best);
-  }
+  for (int e = 0; e < 4; ++e) acc[e] = splat(0xFFFFu);
+  const int64_t total = tiles * tiles;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x)
+    trace_tile<T, VEC>(X, ldx, Y, ldy, N, (t % tiles) * 64, (t / tiles) * 64, yt, acc);
+  const int32_t best = min(block_min(acc, part), inf_of<T>());
+  if (threadIdx.x == 0 && best < inf_of<T>()) atomicMin(out, best);
 }
 
 }  // namespace
@@ -123,14 +99,23 @@ hipError_t launch_trace_of_product(int dtype, int64_t N, const void *X, int64_t 
                                    const void *Y, int64_t ldy, int32_t *out, hipStream_t s) {
   hipError_t e = launch_fill_i32(out, 1, dtype == TP_U16 ? 0xFFFF : 0xFF, s);
   if (e != hipSuccess || N == 0) return e;
-  const int tiles = (int)((N + 63) / 64);
-  const int64_t blocks = (int64_t)tiles * tiles;
-  if (dtype == TP_U16)
-    hipLaunchKernelGGL(trace_of_product_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       N, (const uint16_t *)X, ldx, (const uint16_t *)Y, ldy, tiles, out);
-  else
-    hipLaunchKernelGGL(trace_of_product_kernel<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       N, (const uint8_t *)X, ldx, (const uint8_t *)Y, ldy, tiles, out);
+  const int64_t tiles = (N + 63) / 64;
+  const int64_t blocks = std::min<int64_t>(tiles * tiles, 4096);
+  const int64_t VE = 8;
+  const size_t es = dtype == TP_U16 ? 2 : 1;
+  const bool vec = (ldx % VE == 0) && (ldy % VE == 0) && ((uintptr_t)X % (VE * es) == 0) &&
+                   ((uintptr_t)Y % (VE * es) == 0);
+#define TP_TRACE_LAUNCH(T, V)                                                                  \
+  hipLaunchKernelGGL((trace_of_product_kernel<T, V>), dim3((unsigned)blocks), dim3(256), 0, s, \
+                     N, (const T *)X, ldx, (const T *)Y, ldy, tiles, out)
+  if (dtype == TP_U16) {
+    if (vec) TP_TRACE_LAUNCH(uint16_t, true);
+    else TP_TRACE_LAUNCH(uint16_t, false);
+  } else {
+    if (vec) TP_TRACE_LAUNCH(uint8_t, true);
+    else TP_TRACE_LAUNCH(uint8_t, false);
+  }
+#undef TP_TRACE_LAUNCH
   return hipGetLastError();
 }
 

@@ -1,0 +1,143 @@
+"""Batched gamma_2 (one persistent launch per batch) against the oracle and
+against the plain per-query path; resident powers reused across batches;
+budget and abort handling."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from closed_form import gamma2_closed_form
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2409_17688_amd as tp
+    return tp
+
+
+@pytest.fixture(scope="module")
+def oracle_table(oracle_mod):
+    """gamma_2(n, m) from one oracle chain per n, m <= 240, n = 1..9."""
+    return {n: oracle_mod.gamma2_sweep(n, 240) for n in range(1, 10)}
+
+
+def _run(tp, ctx, inst):
+    import torch
+    ns = [n for n, _ in inst]
+    ms = [m for _, m in inst]
+    out = tp.tp_batch_power_trace(ctx, ns, ms)
+    tp.tp_ctx_check(ctx)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().tolist()
+
+
+def test_mixed_batch_of_64(tp, oracle_table):
+    inst = synth.batch_instances(seed=0)
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        say("batch of 64")
+        got = _run(tp, ctx, inst)
+        ref = [int(oracle_table[n][m - 1]) for n, m in inst]
+        assert got == ref
+        # alone (plain path) == in the batch
+        for (n, m), g in zip(inst, got):
+            assert tp.tp_tropical_power_trace(n, m) == g, (n, m)
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_batches_reuse_resident_powers(tp, oracle_table):
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        rng = np.random.default_rng(7)
+        for rep in range(4):
+            count = int(rng.integers(1, 40))
+            inst = [(int(rng.integers(1, 10)), int(rng.integers(3, 120 + 30 * rep)))
+                    for _ in range(count)]
+            say("reuse batch", rep, count)
+            before = tp.tp_ctx_resident_bytes(ctx)
+            got = _run(tp, ctx, inst)
+            assert got == [int(oracle_table[n][m - 1]) for n, m in inst], rep
+            assert tp.tp_ctx_resident_bytes(ctx) >= before
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_order_and_duplicates_do_not_matter(tp, oracle_table):
+    inst = synth.batch_instances(seed=3, count=48)
+    inst = inst + inst[:5]
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        got = dict()
+        for seed in (0, 1):
+            perm = np.random.default_rng(seed).permutation(len(inst))
+            shuffled = [inst[i] for i in perm]
+            res = _run(tp, ctx, shuffled)
+            for (n, m), g in zip(shuffled, res):
+                assert got.setdefault((n, m), g) == g
+                assert g == int(oracle_table[n][m - 1])
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_large_n_in_batch_closed_form(tp):
+    inst = [(10, 3), (10, 40), (11, 5), (11, 24), (12, 3), (12, 5), (12, 8), (9, 100), (4, 7)]
+    ctx = tp.tp_ctx_create(200 << 30)
+    try:
+        got = _run(tp, ctx, inst)
+        assert got == [gamma2_closed_form(n, m) for n, m in inst]
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_budget_exceeded(tp):
+    ctx = tp.tp_ctx_create(1 << 20)
+    try:
+        with pytest.raises(tp.TropicalError) as e:
+            tp.tp_batch_power_trace(ctx, [9], [50])
+        assert e.value.status == tp.TP_ENOMEM
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_abort_path_forced_from_host(tp, oracle_table):
+    """A zero wait limit makes the first task that must wait abort the batch;
+    the kernel drains and exits, tp_ctx_check reports it, and the next batch
+    recomputes the dropped levels correctly."""
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_WAIT_LIMIT_US, 0)
+        inst = [(9, 60), (8, 41), (6, 30)]
+        tp.tp_batch_power_trace(ctx, [n for n, _ in inst], [m for _, m in inst])
+        with pytest.raises(tp.TropicalError) as e:
+            tp.tp_ctx_check(ctx)
+        assert e.value.status == tp.TP_ECANCELED
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_WAIT_LIMIT_US, 20_000_000)
+        got = _run(tp, ctx, inst)
+        assert got == [int(oracle_table[n][m - 1]) for n, m in inst]
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_task_granularity_does_not_change_results(tp, oracle_table):
+    inst = synth.batch_instances(seed=11, count=20)
+    for rows in (4, 16, 100):
+        ctx = tp.tp_ctx_create(64 << 30)
+        try:
+            for n in range(4, 10):
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_SPMM_ROWS + n, rows)
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_GRID, 37)
+            got = _run(tp, ctx, inst)
+            assert got == [int(oracle_table[n][m - 1]) for n, m in inst], rows
+        finally:
+            tp.tp_ctx_destroy(ctx)
