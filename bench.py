@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--suite", action="store_true",
+                    help="also time gamma_2 queries: plain per-query path vs batched")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy before the product, as "
                          "the reference point for HBM byte counters")
@@ -156,7 +158,62 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+    if args.suite:
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+        line["queries"] = query_suite(tp, synth)
     print(json.dumps(line), flush=True)
+
+
+def query_suite(tp, synth):
+    """gamma_2 queries, plain per-query path vs batched (one persistent launch).
+
+    mixed:  64 instances, n uniform in 4..9, m uniform in 3..200 (seed 0)
+    sweep:  n = 8, m = 3..256 (254 instances)
+    'plain' calls tp_tropical_power_trace once per instance (state matrices
+    cached, every chain recomputed); 'batched cold' answers all instances in
+    one batch on a fresh context (chains computed once per n inside the
+    batch); 'batched warm' repeats the batch on the same context (powers
+    resident, only the traces run).  Every batched answer is compared with
+    the plain one."""
+    import torch
+    out = {}
+    for name, inst in (("mixed64", synth.batch_instances(seed=0)),
+                       ("sweep_n8", [(8, m) for m in range(3, 257)])):
+        ns = [n for n, _ in inst]
+        ms = [m for _, m in inst]
+        for n in sorted(set(ns)):
+            tp.tp_tropical_power_trace(n, 3)  # state matrix and workspace in the cache
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = [tp.tp_tropical_power_trace(n, m) for n, m in inst]
+        t_plain = time.perf_counter() - t0
+        ctx = tp.tp_ctx_create(64 << 30)
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = tp.tp_batch_power_trace(ctx, ns, ms)
+            tp.tp_ctx_check(ctx)
+            t_cold = time.perf_counter() - t0
+            cold = res.cpu().numpy().tolist()
+            t0 = time.perf_counter()
+            res = tp.tp_batch_power_trace(ctx, ns, ms)
+            tp.tp_ctx_check(ctx)
+            t_warm = time.perf_counter() - t0
+            warm = res.cpu().numpy().tolist()
+        finally:
+            tp.tp_ctx_destroy(ctx)
+        if not (cold == warm == plain):
+            print(f"MISMATCH in {name}: batched and plain answers differ", file=sys.stderr)
+            sys.exit(1)
+        k = len(inst)
+        out[name] = {"instances": k,
+                     "plain_qps": round(k / t_plain, 1),
+                     "batched_cold_qps": round(k / t_cold, 1),
+                     "batched_warm_qps": round(k / t_warm, 1),
+                     "cold_speedup": round(t_plain / t_cold, 2),
+                     "warm_speedup": round(t_plain / t_warm, 2)}
+    return out
 
 
 if __name__ == "__main__":

@@ -167,12 +167,14 @@ int tp_release_cache(void);
 /* Batching: many (n, m) instances in one persistent launch.                  */
 /* ------------------------------------------------------------------------ */
 
-/* A context keeps, per path order n, the powers A^1..A^K of the chain of
- * Algorithm 2 resident in device memory (u16, rows padded to 64 entries), at
- * most hbm_budget_bytes in total, and answers instances from them: with
- * a = ceil(m/2), b = floor(m/2), gamma_2(P_n x C_m) = trace of A^a x A^b
- * (Theorem 2).  Powers persist across batches until the context is destroyed.
- * A context is used from one host thread and one stream at a time. */
+/* A context keeps powers of A = A(D_n) resident in device memory (u16, rows
+ * padded to 64 entries), at most hbm_budget_bytes in total: per n the chain
+ * A^1..A^c of Algorithm 2 and giants A^(jc) formed by dense products of
+ * resident powers.  gamma_2(P_n x C_m) is the trace of A^a x A^b for a + b = m
+ * (Theorem 2): (ceil(m/2), floor(m/2)) when m <= 2c, else (jc, m - jc) with
+ * 1 <= m - jc <= c.  Powers persist across batches until the context is
+ * destroyed.  A context is used from one host thread and one stream at a
+ * time. */
 int tp_ctx_create(size_t hbm_budget_bytes, void **ctx);
 int tp_ctx_destroy(void *ctx);
 
@@ -180,16 +182,23 @@ int tp_ctx_destroy(void *ctx);
 #define TP_PARAM_WAIT_LIMIT_US 1 /* bound on one dependency wait (default 20 s) */
 #define TP_PARAM_GRID 2          /* workgroups of the persistent kernel; 0 = fill the chip */
 #define TP_PARAM_SPMM_ROWS 16    /* TP_PARAM_SPMM_ROWS + n: rows per chain task; 0 = auto */
+#define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
+                                    n >= 8, else 32); fixed once powers of n are resident */
 int tp_ctx_set_param(void *ctx, int param, int64_t value);
 
 /* Bytes of resident powers held by the context. */
 int64_t tp_ctx_resident_bytes(void *ctx);
 
+/* Bytes of powers a batch of these instances would add to the context (0
+ * when everything it needs is resident); for admission control. */
+int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t *m);
+
 /* gamma2_dev[j] (device int32) = gamma_2(P_{n[j]} x C_{m[j]}) for j < count,
  * with n (host int32) in 1..12 and m (host int64) >= 3, n*m < 65535.  Queues
- * the missing chain levels of every distinct n, the dense first powers and
- * one trace per instance as one task queue, run by one persistent kernel
- * launch from a captured hipGraph on `stream`; returns without waiting.
+ * the missing powers of every distinct n (first power, chain levels, giant
+ * products) and one trace per instance as one dependency-ordered task queue,
+ * run by one persistent kernel launch from a captured hipGraph on `stream`;
+ * returns without waiting.
  * TP_ENOMEM when the needed powers exceed the context's budget (nothing is
  * queued).  Results of a batch are valid after tp_ctx_check returns TP_OK. */
 int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,

@@ -30,6 +30,7 @@ TP_ECANCELED = -6
 TP_PARAM_WAIT_LIMIT_US = 1
 TP_PARAM_GRID = 2
 TP_PARAM_SPMM_ROWS = 16
+TP_PARAM_BABY_STEPS = 32
 
 INF = {TP_U8: 255, TP_U16: 65535}
 
@@ -65,6 +66,7 @@ _SIGS = {
     "tp_ctx_destroy": ([_p], _i),
     "tp_ctx_set_param": ([_p, _i, _i64], _i),
     "tp_ctx_resident_bytes": ([_p], _i64),
+    "tp_ctx_need_bytes": ([_p, _i, _p, _p], _i64),
     "tp_batch_power_trace": ([_p, _i, _p, _p, _p, _p], _i),
     "tp_ctx_check": ([_p, _p], _i),
 }
@@ -322,6 +324,14 @@ def tp_ctx_set_param(ctx: int, param: int, value: int) -> None:
 
 def tp_ctx_resident_bytes(ctx: int) -> int:
     return _check(int(lib.tp_ctx_resident_bytes(ctx)))
+
+
+def tp_ctx_need_bytes(ctx: int, ns, ms) -> int:
+    import numpy as np
+    n_arr = np.ascontiguousarray(ns, dtype=np.int32)
+    m_arr = np.ascontiguousarray(ms, dtype=np.int64)
+    return _check(int(lib.tp_ctx_need_bytes(ctx, int(n_arr.size), n_arr.ctypes.data,
+                                            m_arr.ctypes.data)))
 
 
 def tp_batch_power_trace(ctx: int, ns, ms, out: torch.Tensor | None = None,

@@ -1,51 +1,62 @@
 // Batched gamma_2: many (n, m) instances in one persistent launch.
 //
-// gamma_2(P_n x C_m) = min_i (A^m)_ii (Theorem 2) = trace of A^a x A^b for any
-// a + b = m.  A context keeps, per path order n, the powers A^1 .. A^K of the
-// chain A^k = A x A^(k-1) (Algorithm 2) resident in HBM; every instance with
-// that n reads its answer from two of them (a = ceil(m/2), b = floor(m/2))
-// with one trace of a product.  A batch therefore costs one chain per
-// distinct n (only the levels not already resident) plus one trace per
-// instance.
+// gamma_2(P_n x C_m) = min_i (A^m)_ii (Theorem 2) = the trace of A^a x A^b for
+// any a + b = m, and the integer (min,+) semiring is associative, so any
+// powers that add up to m give the same exact answer.  A context keeps, per
+// path order n, a set of powers of A = A(D_n) resident in HBM:
+//   babies  A^1 .. A^c      by the chain A^k = A x A^(k-1) of Algorithm 2,
+//                           using the sparse left factor (nnz * N per level);
+//   giants  A^(jc), j >= 2  by dense (min,+) products of two resident powers,
+//                           j = h + (j - h) with h the largest power of two
+//                           <= j (h = j/2 when j is one), so J giants take
+//                           about log2(J) rounds of independent products.
+// Instance m is answered from two resident powers: m <= 2c by
+// (ceil(m/2), floor(m/2)), otherwise m = jc + r with 1 <= r <= c by
+// (jc, r).  Memory per n is (c + m_max/c) powers instead of m_max/2, and the
+// number of sequential chain levels is c instead of m_max/2.
 //
 // The work of a batch is a queue of tasks in dependency order:
 //   BUILD  rows of A^1 = A(D_n)
-//   SPMM   rows of A^k = A x A^(k-1) (needs all of level k-1 of that n)
-//   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki for one instance
-//          (needs level a of that n), folded into the instance's result
+//   SPMM   rows x one 512-column panel of A^k = A x A^(k-1)
+//   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
+//   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
+//          instance's result with an atomic min
 // A persistent kernel pops tasks in queue order with an atomic counter.  A
-// task waits only for tasks that precede it in the queue, which were popped
-// earlier by running workgroups, so the wait always ends; as a safety net
-// every wait is bounded in time, and a timed-out wait sets an abort flag that
-// makes every workgroup drain the queue without work.  Finished tasks publish
-// their rows with an agent-scope release (so other XCDs' L2s see them) and a
-// counter increment; waiting tasks acquire before reading.  Levels of
-// different n interleave in the queue, so small and large chains overlap on
-// the device.  The launch (counter reset, result reset, persistent kernel) is
-// captured once in a hipGraph and replayed for every batch.
-#include <stdarg.h>
+// task waits (on at most two per-power completion counters) only for tasks
+// that precede it in the queue, which were popped earlier by running
+// workgroups, so every wait ends; as a safety net each wait is bounded in
+// time, and a timed-out wait sets an abort flag that makes every workgroup
+// drain the queue without work.  A finished task publishes its rows with an
+// agent-scope release (so the L2s of other XCDs see them) and a counter
+// increment; a workgroup acquires once per power it starts depending on.
+// The launch (counter reset, result reset, persistent kernel) is captured
+// once in a hipGraph and replayed for every batch.
 #include <string.h>
 
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <set>
 #include <vector>
 
 #include "device_core.hpp"
+#include "gemm_core.hpp"
 
 namespace tp {
 
 namespace {
 
-enum : int32_t { kBuild = 0, kSpmm = 1, kTrace = 2 };
+enum : int32_t { kBuild = 0, kSpmm = 1, kGemm = 2, kTrace = 3 };
 
 struct Task {
   int32_t type, slot;
-  int32_t a, b;        // level written (BUILD, SPMM) or the two powers (TRACE)
-  int32_t row0, row1;  // output rows, or the 64 rows i of a trace
-  int32_t dep, dep_target;  // counter to wait for (-1: none) and the count it must reach
-  int32_t done;             // counter bumped when finished (-1: none)
-  int32_t inst;             // instance of a TRACE
+  int32_t out, x, y;           // exponents written / read
+  int32_t row0, row1, c0, c1;  // rows and columns of the output block
+  int32_t dep, dep_target;     // counters to wait for (-1: none) and the
+  int32_t dep2, dep2_target;   //   counts they must reach
+  int32_t done;                // counter bumped when finished (-1: none)
+  int32_t inst;                // instance of a TRACE
+  int32_t pad;
 };
 
 struct Slot {
@@ -57,61 +68,72 @@ struct Slot {
   const int64_t *rowptr;
   const uint32_t *col;
   const uint8_t *z;
-  uint16_t *const *powers;  // powers[k - 1] = A^k
+  uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
 struct Control {
-  int32_t head;      // next task to pop
+  int32_t head;  // next task to pop
   int32_t ntasks;
-  int32_t abort;     // set when a wait exceeded the limit
+  int32_t abort;  // set when a wait exceeded the limit
   int32_t pad;
   int64_t wait_limit;  // in s_memrealtime ticks (100 MHz)
 };
 
 constexpr int kMaxSlots = 16;
 constexpr uint16_t kInf = 0xFFFFu;
+constexpr int kPanel = 512;                       // columns of an SPMM task: 64 lanes x 8
+constexpr int kGBM = 128, kGBN = 128, kGBK = 32;  // dense product tile
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) batch_kernel(Control *__restrict__ ctl,
-                                                    const Task *__restrict__ tasks,
-                                                    const Slot *__restrict__ slots,
-                                                    int32_t *__restrict__ counters,
-                                                    int32_t *__restrict__ results) {
-  __shared__ __attribute__((aligned(16))) uint16_t yt[64 * kTraceLdsStride];
+// Thread 0: wait until counters[dep] >= target.  Returns 0 when the batch
+// was aborted (by this wait timing out or by another workgroup).
+__device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, int target,
+                                           Control *ctl, int64_t limit) {
+  if (dep < 0) return 1;
+  const uint64_t start = __builtin_amdgcn_s_memrealtime();
+  while (ld_relaxed(&counters[dep]) < target) {
+    if (ld_relaxed(&ctl->abort)) return 0;
+    if ((int64_t)(__builtin_amdgcn_s_memrealtime() - start) > limit) {
+      __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return 0;
+    }
+    __builtin_amdgcn_s_sleep(10);  // ~640 clocks between polls
+  }
+  return 1;
+}
+
+__global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl,
+                                                       const Task *__restrict__ tasks,
+                                                       const Slot *__restrict__ slots,
+                                                       int32_t *__restrict__ counters,
+                                                       int32_t *__restrict__ results) {
+  // one LDS arena: the dense product's A and B slabs, or a trace's Y tile
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kGBK * kGBM + 2 * kGBK * kGBN];
   __shared__ int32_t part[4];
-  __shared__ int32_t s_task, s_go;
+  __shared__ int32_t s_task, s_go, s_fresh;
+  int acq_dep = -1, acq_dep2 = -1;  // dependencies this workgroup has acquired (thread 0)
   const int ntasks = ctl->ntasks;
   const int64_t limit = ctl->wait_limit;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   while (true) {
     if (threadIdx.x == 0) {
       const int t = atomicAdd(&ctl->head, 1);
-      int go = 0;
+      int go = 0, fresh = 0;
       if (t < ntasks) {
         go = ld_relaxed(&ctl->abort) == 0;
-        const int dep = tasks[t].dep;
-        if (go && dep >= 0) {
-          const int target = tasks[t].dep_target;
-          const uint64_t start = __builtin_amdgcn_s_memrealtime();
-          while (ld_relaxed(&counters[dep]) < target) {
-            if (ld_relaxed(&ctl->abort)) {
-              go = 0;
-              break;
-            }
-            if ((int64_t)(__builtin_amdgcn_s_memrealtime() - start) > limit) {
-              __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              go = 0;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-          }
-        }
+        const int d1 = tasks[t].dep, d2 = tasks[t].dep2;
+        if (go) go = wait_counter(counters, d1, tasks[t].dep_target, ctl, limit);
+        if (go) go = wait_counter(counters, d2, tasks[t].dep2_target, ctl, limit);
+        fresh = (d1 != acq_dep || d2 != acq_dep2);
+        acq_dep = d1;
+        acq_dep2 = d2;
       }
       s_task = t;
       s_go = go;
+      s_fresh = fresh;
     }
     __syncthreads();
     const int t = s_task;
@@ -119,11 +141,36 @@ __global__ void __launch_bounds__(256) batch_kernel(Control *__restrict__ ctl,
     if (t >= ntasks) break;
     const Task task = tasks[t];
     if (go) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      // the powers this task reads are final once their counters are
+      // complete; acquiring once per new dependency makes them visible
+      if (s_fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const Slot sl = slots[task.slot];
       const int64_t N = sl.N, ld = sl.ld;
-      if (task.type == kBuild) {
-        uint16_t *out = sl.powers[0];
+      if (task.type == kSpmm) {
+        const uint16_t *X = sl.powers[task.x];
+        uint16_t *Y = sl.powers[task.out];
+        for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
+          const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
+          for (int64_t c0 = task.c0 + (int64_t)lane * 8; c0 < task.c1; c0 += kPanel)
+            spmm_row_chunk<uint16_t, true, 4>(sl.rowptr, sl.col, sl.z, X, ld, Y, ld, N, qu, c0);
+        }
+      } else if (task.type == kGemm) {
+        gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
+            (int)N, (int)N, (int)N, sl.powers[task.x], ld, sl.powers[task.y], ld,
+            sl.powers[task.out], ld, 0, task.row0, task.c0,
+            reinterpret_cast<uint16_t(*)[kGBK][kGBM]>(lds),
+            reinterpret_cast<uint16_t(*)[kGBK][kGBN]>(lds + 2 * kGBK * kGBM));
+      } else if (task.type == kTrace) {
+        u16x2 acc[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = splat(kInf);
+        for (int64_t k0 = 0; k0 < N; k0 += 64)
+          trace_tile<uint16_t, true>(sl.powers[task.x], ld, sl.powers[task.y], ld, N, task.row0,
+                                     k0, lds, acc);
+        const int32_t best = block_min(acc, part);
+        if (threadIdx.x == 0 && best < (int32_t)kInf) atomicMin(&results[task.inst], best);
+      } else {
+        uint16_t *out = sl.powers[1];
         const int64_t rows = task.row1 - task.row0;
         for (int64_t idx = threadIdx.x; idx < rows * N; idx += blockDim.x) {
           const int64_t q = task.row0 + idx / N, p = idx - (idx / N) * N;
@@ -132,28 +179,10 @@ __global__ void __launch_bounds__(256) batch_kernel(Control *__restrict__ ctl,
                                 ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
                                 : kInf;
         }
-      } else if (task.type == kSpmm) {
-        const uint16_t *X = sl.powers[task.a - 2];
-        uint16_t *Y = sl.powers[task.a - 1];
-        for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
-          const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
-          for (int64_t c0 = (int64_t)lane * 8; c0 < N; c0 += 512)
-            spmm_row_chunk<uint16_t, true>(sl.rowptr, sl.col, sl.z, X, ld, Y, ld, N, qu, c0);
-        }
-      } else {
-        const uint16_t *X = sl.powers[task.a - 1];
-        const uint16_t *Y = sl.powers[task.b - 1];
-        u16x2 acc[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = splat(kInf);
-        for (int64_t k0 = 0; k0 < N; k0 += 64)
-          trace_tile<uint16_t, true>(X, ld, Y, ld, N, task.row0, k0, yt, acc);
-        const int32_t best = block_min(acc, part);
-        if (threadIdx.x == 0 && best < (int32_t)kInf) atomicMin(&results[task.inst], best);
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    __syncthreads();
+    __syncthreads();  // also keeps the LDS arena from being reused too early
     if (threadIdx.x == 0 && task.done >= 0)
       __hip_atomic_fetch_add(&counters[task.done], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -197,8 +226,9 @@ hipError_t grow_host(Buf &b, size_t bytes) {
 
 struct PowerSet {
   int64_t N = 0, ld = 0;
-  std::vector<void *> pw;  // pw[k - 1] = A^k
-  int have = 0;            // powers known complete on the device
+  int c = 0;                 // baby steps (fixed at first use)
+  std::map<int, void *> pw;  // exponent -> device buffer
+  std::set<int> have;        // exponents known complete on the device
 };
 
 }  // namespace
@@ -208,7 +238,7 @@ struct Ctx {
   size_t budget = 0, used = 0;
   std::map<int, PowerSet> sets;
   Buf d_tasks, d_slots, d_ptrs, d_counters, d_results, d_ctl;
-  Buf h_tasks, h_slots, h_ptrs, h_ctl, h_flag;
+  Buf h_tasks, h_slots, h_ptrs, h_ctl;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   void *g_key[3] = {nullptr, nullptr, nullptr};
@@ -217,21 +247,81 @@ struct Ctx {
   hipEvent_t staged = nullptr;
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
   int spmm_rows[16] = {0};          // rows per SPMM task by n; 0 = automatic
+  int baby[16] = {0};               // baby steps by n; 0 = automatic
   int grid_override = 0;
-  bool pending = false;  // a batch was queued and not yet checked
-  std::vector<int> pending_n;
-  std::vector<int> pending_have;
+  bool pending = false;                      // a batch was queued and not yet checked
+  std::map<int, std::set<int>> pending_new;  // exponents that batch computes, by n
   std::mutex mu;
 };
 
 namespace {
 
 int auto_spmm_rows(int64_t N, int64_t nnz) {
-  // about 2^22 (min,+) operations per task, a multiple of 4 rows (one per wave)
-  const double per_row = (double)nnz / (double)N * (double)N;
-  int64_t r = (int64_t)(4194304.0 / std::max(per_row, 1.0));
-  r = std::max<int64_t>(4, std::min<int64_t>(r, 256));
+  // about 2^18 (min,+) operations per task over one panel, a multiple of 4
+  // rows (one per wave)
+  const double per_row = (double)nnz / (double)N * (double)std::min<int64_t>(N, kPanel);
+  int64_t r = (int64_t)(262144.0 / std::max(per_row, 1.0));
+  r = std::max<int64_t>(4, std::min<int64_t>(r, 64));
   return (int)((r + 3) / 4 * 4);
+}
+
+int auto_baby(int n) { return n >= 8 ? 16 : 32; }
+
+// largest power of two <= j
+int pow2_floor(int j) {
+  int h = 1;
+  while (h * 2 <= j) h *= 2;
+  return h;
+}
+
+// the two giant indices whose product gives giant j (in units of c)
+void giant_split(int j, int *l, int *r) {
+  const int h = pow2_floor(j);
+  if (h == j) {
+    *l = j / 2;
+    *r = j / 2;
+  } else {
+    *l = h;
+    *r = j - h;
+  }
+}
+
+// giant indices needed to build giant j (including j), into out
+void giant_closure(int j, std::set<int> &out) {
+  if (j <= 1 || out.count(j)) return;
+  int l, r;
+  giant_split(j, &l, &r);
+  giant_closure(l, out);
+  giant_closure(r, out);
+  out.insert(j);
+}
+
+// the pair of exponents answering instance m with baby steps c
+void split_instance(int64_t m, int c, int *a, int *b) {
+  if (m <= 2 * (int64_t)c) {
+    *a = (int)((m + 1) / 2);
+    *b = (int)(m / 2);
+  } else {
+    const int j = (int)((m - 1) / c);
+    *a = j * c;
+    *b = (int)(m - (int64_t)j * c);
+  }
+}
+
+// Exponents a batch needs for one path order with baby steps c: the chain
+// top (<= c) and the giant indices (in units of c).
+void batch_needs(const std::vector<int64_t> &ms, int c, int *chain_top, std::set<int> *giants) {
+  *chain_top = 1;
+  for (int64_t m : ms) {
+    int a, b;
+    split_instance(m, c, &a, &b);
+    if (m <= 2 * (int64_t)c) {
+      *chain_top = std::max(*chain_top, a);
+    } else {
+      *chain_top = std::max(*chain_top, c);
+      giant_closure(a / c, *giants);
+    }
+  }
 }
 
 int capture_graph(Ctx *c, int grid) {
@@ -276,141 +366,256 @@ int default_grid() {
   return cus * per_cu;
 }
 
+struct Plan {
+  int n = 0, chain_top = 0;
+  std::set<int> giants;   // giant indices (units of c)
+  std::vector<int> exps;  // every exponent of the batch, increasing
+  StateView view{};
+};
+
+int baby_of(Ctx *c, int n) {
+  auto it = c->sets.find(n);
+  if (it != c->sets.end() && it->second.c > 0) return it->second.c;
+  return c->baby[n] > 0 ? c->baby[n] : auto_baby(n);
+}
+
+std::vector<int> exponents_of(int chain_top, const std::set<int> &giants, int c) {
+  std::set<int> e;
+  for (int k = 1; k <= chain_top; ++k) e.insert(k);
+  for (int j : giants) e.insert(j * c);
+  return std::vector<int>(e.begin(), e.end());
+}
+
 }  // namespace
 
 int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *gamma2_dev,
               hipStream_t stream) {
   // wait until the previous batch's staging buffers have been consumed
   if (c->staged) TP_HIP_CHECK(hipEventSynchronize(c->staged));
-  // distinct n, in increasing order, with the highest level each one needs
-  std::map<int, int> need;  // n -> K = max ceil(m / 2)
-  for (int j = 0; j < count; ++j) {
-    const int a = (int)((ms[j] + 1) / 2);
-    int &k = need[ns[j]];
-    k = std::max(k, a);
-  }
-  TP_REQUIRE((int)need.size() <= kMaxSlots, "more than %d distinct n in one batch", kMaxSlots);
+  std::map<int, std::vector<int64_t>> by_n;
+  for (int j = 0; j < count; ++j) by_n[ns[j]].push_back(ms[j]);
+  TP_REQUIRE((int)by_n.size() <= kMaxSlots, "more than %d distinct n in one batch", kMaxSlots);
+
+  std::vector<Plan> plans;
   std::map<int, int> slot_of;
-  std::vector<StateView> views;
-  int kmax = 0;
-  for (auto &kv : need) {
-    StateView v{};
-    const int rc = state_view(kv.first, stream, &v);
+  int maxexp = 1;
+  for (auto &kv : by_n) {
+    Plan p;
+    p.n = kv.first;
+    const int rc = state_view(p.n, stream, &p.view);
     if (rc != TP_OK) return rc;
-    slot_of[kv.first] = (int)views.size();
-    views.push_back(v);
-    kmax = std::max(kmax, kv.second);
-    PowerSet &ps = c->sets[kv.first];
-    ps.N = v.N;
-    ps.ld = (v.N + 63) / 64 * 64;
-    const size_t bytes = (size_t)ps.N * (size_t)ps.ld * sizeof(uint16_t);
-    while ((int)ps.pw.size() < kv.second) {
-      if (c->used + bytes > c->budget) {
-        set_error("batch needs %d resident powers of A(D_%d) (%zu bytes each): over the budget of %zu bytes",
-                  kv.second, kv.first, bytes, c->budget);
-        return TP_ENOMEM;
+    PowerSet &ps = c->sets[p.n];
+    ps.N = p.view.N;
+    ps.ld = (p.view.N + 63) / 64 * 64;
+    if (ps.c == 0) ps.c = baby_of(c, p.n);
+    batch_needs(kv.second, ps.c, &p.chain_top, &p.giants);
+    p.exps = exponents_of(p.chain_top, p.giants, ps.c);
+    maxexp = std::max(maxexp, p.exps.back());
+    slot_of[p.n] = (int)plans.size();
+    plans.push_back(p);
+  }
+  // memory: allocate every missing power, all or nothing
+  {
+    size_t extra = 0;
+    for (const Plan &p : plans) {
+      const PowerSet &ps = c->sets[p.n];
+      const size_t bytes = (size_t)ps.N * (size_t)ps.ld * sizeof(uint16_t);
+      for (int e : p.exps)
+        if (!ps.pw.count(e)) extra += bytes;
+    }
+    if (c->used + extra > c->budget) {
+      set_error("batch needs %zu more bytes of resident powers; %zu of %zu bytes in use", extra,
+                c->used, c->budget);
+      return TP_ENOMEM;
+    }
+    for (const Plan &p : plans) {
+      PowerSet &ps = c->sets[p.n];
+      const size_t bytes = (size_t)ps.N * (size_t)ps.ld * sizeof(uint16_t);
+      for (int e : p.exps) {
+        if (ps.pw.count(e)) continue;
+        void *ptr = nullptr;
+        hipError_t err = hipMalloc(&ptr, bytes);
+        if (err != hipSuccess) return hip_fail(err, "hipMalloc (resident power)");
+        c->used += bytes;
+        ps.pw[e] = ptr;
       }
-      void *p = nullptr;
-      hipError_t e = hipMalloc(&p, bytes);
-      if (e != hipSuccess) return hip_fail(e, "hipMalloc (resident power)");
-      c->used += bytes;
-      ps.pw.push_back(p);
     }
   }
-  const int nslots = (int)views.size();
-  auto counter = [&](int slot, int level) { return slot * (kmax + 1) + level; };
+  const int nslots = (int)plans.size();
+  auto counter = [&](int slot, int e) { return slot * (maxexp + 1) + e; };
+  auto computed = [&](int s, int e) { return c->sets[plans[s].n].have.count(e) == 0; };
 
-  // tasks in dependency order: level by level over all n, traces right after
-  // the level they read
   std::vector<Task> tasks;
-  std::vector<std::vector<int>> level_tasks(nslots, std::vector<int>(kmax + 1, 0));
-  std::vector<std::vector<int>> by_level(kmax + 1);
-  for (int j = 0; j < count; ++j) by_level[(ms[j] + 1) / 2].push_back(j);
-  auto push_traces = [&](int j) {
-    const int s = slot_of[ns[j]];
-    const PowerSet &ps = c->sets[ns[j]];
-    const int a = (int)((ms[j] + 1) / 2), b = (int)(ms[j] / 2);
-    const bool computed = a > ps.have;
-    for (int64_t i0 = 0; i0 < ps.N; i0 += 64) {
-      Task t{};
-      t.type = kTrace;
-      t.slot = s;
-      t.a = a;
-      t.b = b;
-      t.row0 = (int32_t)i0;
-      t.row1 = (int32_t)std::min<int64_t>(i0 + 64, ps.N);
-      t.dep = computed ? counter(s, a) : -1;
-      t.dep_target = computed ? level_tasks[s][a] : 0;
-      t.done = -1;
-      t.inst = j;
-      tasks.push_back(t);
+  std::vector<std::vector<int>> ntask(nslots, std::vector<int>(maxexp + 1, 0));
+  // dependency on exponent e of slot s: none when e is resident already
+  auto dep_of = [&](int s, int e, int32_t *dep, int32_t *target) {
+    if (!computed(s, e)) {
+      *dep = -1;
+      *target = 0;
+    } else {
+      *dep = counter(s, e);
+      *target = ntask[s][e];
     }
   };
-  for (int k = 1; k <= kmax; ++k) {
-    for (int s = 0; s < nslots; ++s) {
-      const int n = views[s].n;
-      const PowerSet &ps = c->sets[n];
-      if (k > need[n] || k <= ps.have) continue;
-      const int64_t N = ps.N;
-      int rows;
-      if (k == 1)
-        rows = (int)std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)));
-      else
-        rows = c->spmm_rows[n] > 0 ? c->spmm_rows[n] : auto_spmm_rows(N, views[s].nnz);
-      const bool dep = k >= 2 && (k - 1) > ps.have;
-      for (int64_t r0 = 0; r0 < N; r0 += rows) {
+
+  // every instance's pair of exponents; traces are queued right after the
+  // last power they read
+  std::vector<int> ta(count), tb(count);
+  std::vector<std::vector<int>> waiting(nslots);
+  for (int j = 0; j < count; ++j) {
+    const int s = slot_of[ns[j]];
+    split_instance(ms[j], c->sets[ns[j]].c, &ta[j], &tb[j]);
+    waiting[s].push_back(j);
+  }
+  auto push_ready_traces = [&](int s, int upto) {
+    std::vector<int> rest;
+    for (int j : waiting[s]) {
+      const int a = ta[j], b = tb[j];
+      const bool ready = (!computed(s, a) || a <= upto) && (!computed(s, b) || b <= upto);
+      if (!ready) {
+        rest.push_back(j);
+        continue;
+      }
+      const int64_t N = c->sets[plans[s].n].N;
+      for (int64_t i0 = 0; i0 < N; i0 += 64) {
         Task t{};
-        t.type = k == 1 ? kBuild : kSpmm;
+        t.type = kTrace;
         t.slot = s;
-        t.a = k;
-        t.row0 = (int32_t)r0;
-        t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
-        t.dep = dep ? counter(s, k - 1) : -1;
-        t.dep_target = dep ? level_tasks[s][k - 1] : 0;
-        t.done = counter(s, k);
+        t.x = a;
+        t.y = b;
+        t.row0 = (int32_t)i0;
+        t.row1 = (int32_t)std::min<int64_t>(i0 + 64, N);
+        dep_of(s, a, &t.dep, &t.dep_target);
+        dep_of(s, b, &t.dep2, &t.dep2_target);
+        t.done = -1;
+        t.inst = j;
         tasks.push_back(t);
-        ++level_tasks[s][k];
       }
     }
-    // every instance is queued at its level a (a >= 2 because m >= 3); when
-    // that level is resident its trace has no dependency
-    for (int j : by_level[k]) push_traces(j);
+    waiting[s].swap(rest);
+  };
+
+  for (int s = 0; s < nslots; ++s) push_ready_traces(s, 0);  // answered by resident powers
+  // chain levels, level by level over all n
+  int max_top = 0;
+  for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
+  for (int k = 1; k <= max_top; ++k) {
+    for (int s = 0; s < nslots; ++s) {
+      const Plan &p = plans[s];
+      const PowerSet &ps = c->sets[p.n];
+      if (k > p.chain_top || !computed(s, k)) continue;
+      const int64_t N = ps.N;
+      const int rows =
+          k == 1 ? (int)std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)))
+                 : (c->spmm_rows[p.n] > 0 ? c->spmm_rows[p.n] : auto_spmm_rows(N, p.view.nnz));
+      const int64_t panel = k == 1 ? N : kPanel;
+      for (int64_t r0 = 0; r0 < N; r0 += rows) {
+        for (int64_t c0 = 0; c0 < N; c0 += panel) {
+          Task t{};
+          t.type = k == 1 ? kBuild : kSpmm;
+          t.slot = s;
+          t.out = k;
+          t.x = k - 1;
+          t.row0 = (int32_t)r0;
+          t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
+          t.c0 = (int32_t)c0;
+          t.c1 = (int32_t)std::min<int64_t>(c0 + panel, N);
+          if (k >= 2) {
+            dep_of(s, k - 1, &t.dep, &t.dep_target);
+          } else {
+            t.dep = -1;
+          }
+          t.dep2 = -1;
+          t.done = counter(s, k);
+          tasks.push_back(t);
+          ++ntask[s][k];
+        }
+      }
+    }
+    for (int s = 0; s < nslots; ++s)
+      if (k <= plans[s].chain_top) push_ready_traces(s, k);
   }
+  // giants in increasing exponent, interleaved over n; a giant's two factors
+  // have smaller exponents and are queued before it
+  std::vector<std::vector<int>> gl(nslots);
+  size_t rounds = 0;
+  for (int s = 0; s < nslots; ++s) {
+    gl[s].assign(plans[s].giants.begin(), plans[s].giants.end());
+    rounds = std::max(rounds, gl[s].size());
+  }
+  for (size_t r = 0; r < rounds; ++r) {
+    for (int s = 0; s < nslots; ++s) {
+      if (r >= gl[s].size()) continue;
+      const PowerSet &ps = c->sets[plans[s].n];
+      const int j = gl[s][r], e = j * ps.c;
+      if (computed(s, e)) {
+        int l, rr;
+        giant_split(j, &l, &rr);
+        const int x = l * ps.c, y = rr * ps.c;
+        for (int64_t m0 = 0; m0 < ps.N; m0 += kGBM) {
+          for (int64_t n0 = 0; n0 < ps.N; n0 += kGBN) {
+            Task t{};
+            t.type = kGemm;
+            t.slot = s;
+            t.out = e;
+            t.x = x;
+            t.y = y;
+            t.row0 = (int32_t)m0;
+            t.c0 = (int32_t)n0;
+            dep_of(s, x, &t.dep, &t.dep_target);
+            dep_of(s, y, &t.dep2, &t.dep2_target);
+            t.done = counter(s, e);
+            tasks.push_back(t);
+            ++ntask[s][e];
+          }
+        }
+      }
+      push_ready_traces(s, e);
+    }
+  }
+  for (int s = 0; s < nslots; ++s) push_ready_traces(s, maxexp);
+  for (int s = 0; s < nslots; ++s)
+    if (!waiting[s].empty()) {
+      set_error("internal: an instance of n = %d has no plan", plans[s].n);
+      return TP_EINVAL;
+    }
 
   // staging (pinned) and device buffers
-  const size_t tb = tasks.size() * sizeof(Task);
-  size_t nptr = 0;
-  for (int s = 0; s < nslots; ++s) nptr += c->sets[views[s].n].pw.size();
-  TP_HIP_CHECK(grow_host(c->h_tasks, std::max<size_t>(tb, sizeof(Task))));
+  const size_t tbytes = tasks.size() * sizeof(Task);
+  const size_t ptr_stride = (size_t)maxexp + 1;
+  const size_t nptr = ptr_stride * nslots;
+  TP_HIP_CHECK(grow_host(c->h_tasks, std::max<size_t>(tbytes, sizeof(Task))));
   TP_HIP_CHECK(grow_host(c->h_slots, kMaxSlots * sizeof(Slot)));
-  TP_HIP_CHECK(grow_host(c->h_ptrs, std::max<size_t>(nptr, 1) * sizeof(void *)));
+  TP_HIP_CHECK(grow_host(c->h_ptrs, nptr * sizeof(void *)));
   TP_HIP_CHECK(grow_host(c->h_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_tasks, std::max<size_t>(tb, sizeof(Task))));
+  TP_HIP_CHECK(grow(c->d_tasks, std::max<size_t>(tbytes, sizeof(Task))));
   TP_HIP_CHECK(grow(c->d_slots, kMaxSlots * sizeof(Slot)));
-  TP_HIP_CHECK(grow(c->d_ptrs, std::max<size_t>(nptr, 1) * sizeof(void *)));
+  TP_HIP_CHECK(grow(c->d_ptrs, nptr * sizeof(void *)));
   TP_HIP_CHECK(grow(c->d_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max(nslots * (kmax + 1), 1) * sizeof(int32_t)));
+  TP_HIP_CHECK(grow(c->d_counters, (size_t)nslots * (maxexp + 1) * sizeof(int32_t)));
   TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t)));
 
-  memcpy(c->h_tasks.p, tasks.data(), tb);
+  memcpy(c->h_tasks.p, tasks.data(), tbytes);
   Slot *hs = (Slot *)c->h_slots.p;
   void **hp = (void **)c->h_ptrs.p;
-  size_t off = 0;
   for (int s = 0; s < nslots; ++s) {
-    const PowerSet &ps = c->sets[views[s].n];
+    const Plan &p = plans[s];
+    const PowerSet &ps = c->sets[p.n];
     Slot sl{};
-    sl.n = views[s].n;
+    sl.n = p.n;
     sl.N = (int32_t)ps.N;
     sl.ld = ps.ld;
-    sl.full = (1u << sl.n) - 1u;
-    sl.masks = views[s].masks;
-    sl.rowptr = views[s].rowptr;
-    sl.col = views[s].col;
-    sl.z = views[s].z;
-    sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + off);
+    sl.full = (1u << p.n) - 1u;
+    sl.masks = p.view.masks;
+    sl.rowptr = p.view.rowptr;
+    sl.col = p.view.col;
+    sl.z = p.view.z;
+    sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
     hs[s] = sl;
-    for (size_t k = 0; k < ps.pw.size(); ++k) hp[off + k] = ps.pw[k];
-    off += ps.pw.size();
+    for (size_t e = 0; e < ptr_stride; ++e) {
+      auto it = ps.pw.find((int)e);
+      hp[ptr_stride * s + e] = it == ps.pw.end() ? nullptr : it->second;
+    }
   }
   Control *hc = (Control *)c->h_ctl.p;
   hc->head = 0;
@@ -426,10 +631,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     const int rc = capture_graph(c, grid);
     if (rc != TP_OK) return rc;
   }
-  TP_HIP_CHECK(hipMemcpyAsync(c->d_tasks.p, c->h_tasks.p, tb, hipMemcpyHostToDevice, stream));
+  TP_HIP_CHECK(hipMemcpyAsync(c->d_tasks.p, c->h_tasks.p, tbytes, hipMemcpyHostToDevice, stream));
   TP_HIP_CHECK(hipMemcpyAsync(c->d_slots.p, c->h_slots.p, nslots * sizeof(Slot),
                               hipMemcpyHostToDevice, stream));
-  TP_HIP_CHECK(hipMemcpyAsync(c->d_ptrs.p, c->h_ptrs.p, std::max<size_t>(nptr, 1) * sizeof(void *),
+  TP_HIP_CHECK(hipMemcpyAsync(c->d_ptrs.p, c->h_ptrs.p, nptr * sizeof(void *),
                               hipMemcpyHostToDevice, stream));
   TP_HIP_CHECK(hipMemcpyAsync(c->d_ctl.p, c->h_ctl.p, sizeof(Control), hipMemcpyHostToDevice,
                               stream));
@@ -438,14 +643,16 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   TP_HIP_CHECK(hipGraphLaunch(c->exec, stream));
   TP_HIP_CHECK(hipMemcpyAsync(gamma2_dev, c->d_results.p, (size_t)count * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, stream));
-  // the levels just queued count as resident for later batches on this
-  // stream; tp_ctx_check drops them again if the batch aborted
+  // what this batch computes counts as resident for later batches on this
+  // stream; tp_ctx_check drops it again if the batch aborted
   c->pending = true;
-  for (auto &kv : need) {
-    PowerSet &ps = c->sets[kv.first];
-    c->pending_n.push_back(kv.first);
-    c->pending_have.push_back(ps.have);
-    ps.have = std::max(ps.have, kv.second);
+  for (const Plan &p : plans) {
+    PowerSet &ps = c->sets[p.n];
+    for (int e : p.exps)
+      if (!ps.have.count(e)) {
+        ps.have.insert(e);
+        c->pending_new[p.n].insert(e);
+      }
   }
   return TP_OK;
 }
@@ -459,16 +666,14 @@ int ctx_check(Ctx *c, hipStream_t stream) {
     TP_HIP_CHECK(hipMemcpy(&abort, (char *)c->d_ctl.p + offsetof(Control, abort), sizeof(int32_t),
                            hipMemcpyDeviceToHost));
   if (abort) {
-    // nothing computed by the aborted batches can be trusted
-    for (size_t i = 0; i < c->pending_n.size(); ++i)
-      c->sets[c->pending_n[i]].have = std::min(c->sets[c->pending_n[i]].have, c->pending_have[i]);
-    c->pending_n.clear();
-    c->pending_have.clear();
+    // nothing the aborted batches were to compute can be trusted
+    for (auto &kv : c->pending_new)
+      for (int e : kv.second) c->sets[kv.first].have.erase(e);
+    c->pending_new.clear();
     set_error("batch aborted: a task waited longer than the limit for its inputs");
     return TP_ECANCELED;
   }
-  c->pending_n.clear();
-  c->pending_have.clear();
+  c->pending_new.clear();
   return TP_OK;
 }
 
@@ -477,11 +682,11 @@ void ctx_free(Ctx *c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->staged) (void)hipEventDestroy(c->staged);
   for (auto &kv : c->sets)
-    for (void *p : kv.second.pw) (void)hipFree(p);
+    for (auto &e : kv.second.pw) (void)hipFree(e.second);
   Buf *dev[] = {&c->d_tasks, &c->d_slots, &c->d_ptrs, &c->d_counters, &c->d_results, &c->d_ctl};
   for (Buf *b : dev)
     if (b->p) (void)hipFree(b->p);
-  Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl, &c->h_flag};
+  Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl};
   for (Buf *b : host)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -517,24 +722,31 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
   TP_REQUIRE(ctx != nullptr, "ctx is NULL");
   Ctx *c = (Ctx *)ctx;
   std::lock_guard<std::mutex> lk(c->mu);
-  switch (param) {
-    case TP_PARAM_WAIT_LIMIT_US:
-      TP_REQUIRE(value >= 0, "negative wait limit");
-      c->wait_limit = value * 100;  // 100 MHz ticks
-      return TP_OK;
-    case TP_PARAM_GRID:
-      TP_REQUIRE(value >= 0 && value <= (1 << 20), "grid out of range");
-      c->grid_override = (int)value;
-      return TP_OK;
-    default:
-      if (param >= TP_PARAM_SPMM_ROWS && param < TP_PARAM_SPMM_ROWS + 16) {
-        TP_REQUIRE(value >= 0 && value <= 65536, "rows per task out of range");
-        c->spmm_rows[param - TP_PARAM_SPMM_ROWS] = (int)(value + 3) / 4 * 4;
-        return TP_OK;
-      }
-      set_error("unknown parameter %d", param);
-      return TP_EINVAL;
+  if (param == TP_PARAM_WAIT_LIMIT_US) {
+    TP_REQUIRE(value >= 0, "negative wait limit");
+    c->wait_limit = value * 100;  // 100 MHz ticks
+    return TP_OK;
   }
+  if (param == TP_PARAM_GRID) {
+    TP_REQUIRE(value >= 0 && value <= (1 << 20), "grid out of range");
+    c->grid_override = (int)value;
+    return TP_OK;
+  }
+  if (param >= TP_PARAM_SPMM_ROWS && param < TP_PARAM_SPMM_ROWS + 16) {
+    TP_REQUIRE(value >= 0 && value <= 65536, "rows per task out of range");
+    c->spmm_rows[param - TP_PARAM_SPMM_ROWS] = (int)(value + 3) / 4 * 4;
+    return TP_OK;
+  }
+  if (param >= TP_PARAM_BABY_STEPS && param < TP_PARAM_BABY_STEPS + 16) {
+    const int n = param - TP_PARAM_BABY_STEPS;
+    TP_REQUIRE(value >= 0 && value <= (1 << 16), "baby steps out of range");
+    TP_REQUIRE(c->sets.count(n) == 0 || c->sets[n].pw.empty(),
+               "baby steps of n = %d are fixed once powers are resident", n);
+    c->baby[n] = (int)value;
+    return TP_OK;
+  }
+  set_error("unknown parameter %d", param);
+  return TP_EINVAL;
 }
 
 int64_t tp_ctx_resident_bytes(void *ctx) {
@@ -542,7 +754,39 @@ int64_t tp_ctx_resident_bytes(void *ctx) {
     set_error("ctx is NULL");
     return TP_EINVAL;
   }
-  return (int64_t)((Ctx *)ctx)->used;
+  Ctx *c = (Ctx *)ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  return (int64_t)c->used;
+}
+
+int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t *m) {
+  if (!ctx || count < 0 || (count > 0 && (!n || !m))) {
+    set_error("bad arguments");
+    return TP_EINVAL;
+  }
+  Ctx *c = (Ctx *)ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  std::map<int, std::vector<int64_t>> by_n;
+  for (int j = 0; j < count; ++j) {
+    if (n[j] < 1 || n[j] > 12 || m[j] < 3) {
+      set_error("instance %d out of range", j);
+      return TP_EINVAL;
+    }
+    by_n[n[j]].push_back(m[j]);
+  }
+  int64_t extra = 0;
+  for (auto &kv : by_n) {
+    const int nn = kv.first;
+    const int64_t N = word_count_host(nn), ld = (N + 63) / 64 * 64;
+    const int cc = baby_of(c, nn);
+    int top = 0;
+    std::set<int> giants;
+    batch_needs(kv.second, cc, &top, &giants);
+    auto it = c->sets.find(nn);
+    for (int e : exponents_of(top, giants, cc))
+      if (it == c->sets.end() || !it->second.pw.count(e)) extra += N * ld * 2;
+  }
+  return extra;
 }
 
 int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,

@@ -63,8 +63,9 @@ __device__ __forceinline__ void load_row_chunk(const T *__restrict__ X, int64_t 
 
 // Y[q][c0 .. c0+VE) = min over successors p of q of (z_p + X[p][c0 ..]):
 // one lane's chunk of row q of the sparse left product.  The successor list
-// is the same for every lane of the wave.
-template <typename T, bool VEC>
+// is the same for every lane of the wave; U successor rows are in flight per
+// lane.
+template <typename T, bool VEC, int U = 8>
 __device__ __forceinline__ void spmm_row_chunk(const int64_t *__restrict__ rowptr,
                                                const uint32_t *__restrict__ col,
                                                const uint8_t *__restrict__ z,
@@ -78,7 +79,6 @@ __device__ __forceinline__ void spmm_row_chunk(const int64_t *__restrict__ rowpt
 #pragma unroll
   for (int e = 0; e < P; ++e) acc[e] = splat(0xFFFFu);
   int64_t e = begin;
-  constexpr int U = 8;  // successor rows in flight per lane
   for (; e + U <= end; e += U) {
     u16x2 v[U][P];
     uint16_t lab[U];

@@ -141,3 +141,53 @@ def test_task_granularity_does_not_change_results(tp, oracle_table):
             assert got == [int(oracle_table[n][m - 1]) for n, m in inst], rows
         finally:
             tp.tp_ctx_destroy(ctx)
+
+
+@pytest.fixture(scope="module")
+def oracle_table_500(oracle_mod):
+    """gamma_2(n, m) for m <= 500, n = 1..8 (one oracle chain per n)."""
+    return {n: oracle_mod.gamma2_sweep(n, 500) for n in range(1, 9)}
+
+
+def test_giants_for_long_cycles(tp, oracle_table_500):
+    """m up to 500: answers come from chain powers and dense giant products."""
+    rng = np.random.default_rng(21)
+    inst = [(int(rng.integers(2, 9)), int(rng.integers(3, 501))) for _ in range(60)]
+    inst += [(8, 500), (8, 33), (8, 32), (8, 31), (7, 64), (7, 65), (6, 97)]
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        say("giants batch")
+        got = _run(tp, ctx, inst)
+        assert got == [int(oracle_table_500[n][m - 1]) for n, m in inst]
+        # a second batch reuses the resident giants and adds new ones
+        inst2 = [(8, m) for m in (499, 400, 257, 129, 3)] + [(5, 450), (5, 449)]
+        got2 = _run(tp, ctx, inst2)
+        assert got2 == [int(oracle_table_500[n][m - 1]) for n, m in inst2]
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("c", [2, 3, 7, 16, 40])
+def test_baby_step_length_does_not_change_results(tp, oracle_table_500, c):
+    inst = [(n, m) for n in (3, 6, 8) for m in (3, 4, 5, 2 * c, 2 * c + 1, 3 * c + 2, 199, 350)]
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        for n in (3, 6, 8):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, c)
+        need = tp.tp_ctx_need_bytes(ctx, [n for n, _ in inst], [m for _, m in inst])
+        got = _run(tp, ctx, inst)
+        assert got == [int(oracle_table_500[n][m - 1]) for n, m in inst], c
+        assert tp.tp_ctx_resident_bytes(ctx) == need
+        assert tp.tp_ctx_need_bytes(ctx, [n for n, _ in inst], [m for _, m in inst]) == 0
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_giants_at_large_n_closed_form(tp):
+    inst = [(9, 500), (9, 347), (10, 300), (10, 37), (11, 120), (11, 97)]
+    ctx = tp.tp_ctx_create(200 << 30)
+    try:
+        got = _run(tp, ctx, inst)
+        assert got == [gamma2_closed_form(n, m) for n, m in inst]
+    finally:
+        tp.tp_ctx_destroy(ctx)
