@@ -189,6 +189,10 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value);
 /* Bytes of resident powers held by the context. */
 int64_t tp_ctx_resident_bytes(void *ctx);
 
+/* Frees the resident powers of path order n (n = 0: of every n), after
+ * waiting for the work queued on `stream`. */
+int tp_ctx_release(void *ctx, int n, hipStream_t stream);
+
 /* Bytes of powers a batch of these instances would add to the context (0
  * when everything it needs is resident); for admission control. */
 int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t *m);

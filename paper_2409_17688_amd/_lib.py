@@ -67,6 +67,7 @@ _SIGS = {
     "tp_ctx_set_param": ([_p, _i, _i64], _i),
     "tp_ctx_resident_bytes": ([_p], _i64),
     "tp_ctx_need_bytes": ([_p, _i, _p, _p], _i64),
+    "tp_ctx_release": ([_p, _i, _p], _i),
     "tp_batch_power_trace": ([_p, _i, _p, _p, _p, _p], _i),
     "tp_ctx_check": ([_p, _p], _i),
 }
@@ -324,6 +325,10 @@ def tp_ctx_set_param(ctx: int, param: int, value: int) -> None:
 
 def tp_ctx_resident_bytes(ctx: int) -> int:
     return _check(int(lib.tp_ctx_resident_bytes(ctx)))
+
+
+def tp_ctx_release(ctx: int, n: int = 0, stream=None) -> None:
+    _check(lib.tp_ctx_release(ctx, int(n), _stream(stream)))
 
 
 def tp_ctx_need_bytes(ctx: int, ns, ms) -> int:

@@ -759,6 +759,29 @@ int64_t tp_ctx_resident_bytes(void *ctx) {
   return (int64_t)c->used;
 }
 
+int tp_ctx_release(void *ctx, int n, hipStream_t stream) {
+  TP_REQUIRE(ctx != nullptr, "ctx is NULL");
+  TP_REQUIRE(n >= 0 && n <= 12, "n = %d outside 0..12", n);
+  Ctx *c = (Ctx *)ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  // queued batches may still read the powers
+  TP_HIP_CHECK(hipStreamSynchronize(stream));
+  for (auto it = c->sets.begin(); it != c->sets.end();) {
+    if (n != 0 && it->first != n) {
+      ++it;
+      continue;
+    }
+    const size_t bytes = (size_t)it->second.N * (size_t)it->second.ld * sizeof(uint16_t);
+    for (auto &e : it->second.pw) {
+      TP_HIP_CHECK(hipFree(e.second));
+      c->used -= bytes;
+    }
+    c->pending_new.erase(it->first);
+    it = c->sets.erase(it);
+  }
+  return TP_OK;
+}
+
 int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t *m) {
   if (!ctx || count < 0 || (count > 0 && (!n || !m))) {
     set_error("bad arguments");
