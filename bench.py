@@ -44,8 +44,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
-    ap.add_argument("--suite", action="store_true",
-                    help="also time gamma_2 queries: plain per-query path vs batched")
+    ap.add_argument("--no-suite", action="store_true",
+                    help="skip timing gamma_2 queries (plain per-query path vs batched)")
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the serving stream (about two minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy before the product, as "
                          "the reference point for HBM byte counters")
@@ -158,11 +160,99 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
-    if args.suite:
+    if not args.no_suite or args.serve:
         del dA, dB, dC
         torch.cuda.empty_cache()
+    if not args.no_suite:
         line["queries"] = query_suite(tp, synth)
+    if args.serve:
+        line["serving"] = serve_suite(tp, synth)
     print(json.dumps(line), flush=True)
+
+
+def serve_suite(tp, synth, count=2000):
+    """Serving: a Poisson stream of `count` queries, n in 6..12 weighted by
+    2^-(n-6), m uniform in 3..500 (seed 0), on one server (resident powers in
+    HBM, memory admission, continuous batching, n = 12 in a sweep lane).
+
+    saturation: every query submitted at once (cold server, then again warm);
+    replay: the stream at 70 % of the warm saturation rate, p50/p99 latency;
+    plain: tp_tropical_power_trace one query at a time, estimated as the mean
+    time of a stratified sample per n times that n's count in the stream
+    (answers of the sample are compared with the served ones)."""
+    import torch
+
+    from paper_2409_17688_amd import serve
+    free, _ = torch.cuda.mem_get_info()
+    budget = max(8 << 30, free - (48 << 30))
+    unit = synth.serve_stream(seed=0, count=count, qps=1.0)
+    ex = serve.GpuExecutor(budget)
+    srv = serve.Server(ex, max_wave=1024)
+    out = {"queries": count, "budget_bytes": int(budget)}
+    try:
+        def burst():
+            t0 = time.perf_counter()
+            reqs = [srv.submit(n, m) for _, n, m in unit]
+            for r in reqs:
+                r.wait(600)
+            return reqs, time.perf_counter() - t0
+
+        reqs, t_cold = burst()
+        served = {(r.n, r.m): r.gamma2 for r in reqs}
+        bad = [r for r in reqs if r.status != serve.TP_OK]
+        if bad:
+            print(f"serving failed: {bad[0].n} {bad[0].m} {bad[0].error}", file=sys.stderr)
+            sys.exit(1)
+        _, t_warm = burst()
+        qps = 0.7 * count / t_warm
+        t0 = time.perf_counter()
+        reqs = []
+        for t, n, m in unit:
+            delay = t / qps - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            reqs.append(srv.submit(n, m))
+        for r in reqs:
+            r.wait(600)
+        t_replay = time.perf_counter() - t0
+        lat = [r.latency for r in reqs]
+        out.update({"saturation_qps_cold": round(count / t_cold, 1),
+                    "saturation_qps_warm": round(count / t_warm, 1),
+                    "replay_qps": round(qps, 1),
+                    "replay_p50_ms": round(serve.percentile(lat, 50) * 1e3, 2),
+                    "replay_p99_ms": round(serve.percentile(lat, 99) * 1e3, 2),
+                    "replay_seconds": round(t_replay, 1),
+                    "waves": srv.waves,
+                    "resident_bytes": ex.resident_bytes()})
+        by_n = {}
+        for r in reqs:
+            by_n.setdefault(r.n, []).append(r.latency)
+        out["p99_ms_by_n"] = {str(n): round(serve.percentile(v, 99) * 1e3, 1)
+                              for n, v in sorted(by_n.items())}
+    finally:
+        srv.close()
+        ex.close()
+    torch.cuda.empty_cache()
+    # plain path on a stratified sample
+    rng = __import__("numpy").random.default_rng(1)
+    counts, plain_total = {}, 0.0
+    for _, n, m in unit:
+        counts[n] = counts.get(n, 0) + 1
+    for n, cnt in sorted(counts.items()):
+        pool = [(nn, m) for _, nn, m in unit if nn == n]
+        k = 2 if n >= 12 else 4
+        pick = [pool[int(i)] for i in rng.choice(len(pool), size=min(k, len(pool)), replace=False)]
+        tp.tp_tropical_power_trace(n, 3)
+        t0 = time.perf_counter()
+        for nn, m in pick:
+            g = tp.tp_tropical_power_trace(nn, m)
+            if g != served[(nn, m)]:
+                print(f"MISMATCH served vs plain at ({nn},{m})", file=sys.stderr)
+                sys.exit(1)
+        plain_total += (time.perf_counter() - t0) / len(pick) * cnt
+    out["plain_qps_estimate"] = round(count / plain_total, 2)
+    out["served_vs_plain"] = round((count / t_warm) / (count / plain_total), 1)
+    return out
 
 
 def query_suite(tp, synth):

@@ -123,12 +123,16 @@ int get_state(int n, hipStream_t s, State **out) {
 
 // ---------------------------------------------------------------- planner --
 
-// Seconds per operation class; launch overhead per kernel.  Measured on an
-// MI355X (see the benchmark); only the ratios steer the plan.
-constexpr double kSpmmRate = 4.0e12;   // (min,+) ops / s of the sparse left step
-constexpr double kGemmRate = 2.0e13;   // (min,+) ops / s of the dense product
-constexpr double kHbm = 5.0e12;        // bytes / s for traces and copies
-constexpr double kLaunch = 6.0e-6;     // s per kernel launch
+// Kernel rates measured on an MI355X by path order n (rows padded to 64
+// entries): (min,+) operations per second of one sparse left step
+// (nnz * N operations) and of one dense product (N^3), plus launch overhead.
+// Only their ratios steer the plan; every plan gives the same answer.
+constexpr double kSpmmRate[13] = {0, 1e10, 1e10, 2e10, 5e10, 1e11, 5e10, 2.5e11,
+                                  1.4e12, 4.5e12, 1.19e13, 1.05e13, 1.12e13};
+constexpr double kGemmRate[13] = {0, 1e9, 1e9, 1e10, 5e10, 1e11, 3e11, 2e12,
+                                  1.45e13, 2.6e13, 3.37e13, 3.4e13, 3.4e13};
+constexpr double kHbm = 5.0e12;     // bytes / s for traces and copies
+constexpr double kLaunch = 6.0e-6;  // s per kernel launch
 
 int bit_length(int64_t v) {
   int b = 0;
@@ -148,9 +152,9 @@ struct Plan {
   double cost = 1e300;  // estimated seconds
 };
 
-double plan_cost(int64_t m, int64_t c, double N, double nnz) {
-  const double S = nnz * N / kSpmmRate + kLaunch;
-  const double G = N * N * N / kGemmRate + kLaunch;
+double plan_cost(int n, int64_t m, int64_t c, double N, double nnz) {
+  const double S = nnz * N / kSpmmRate[n] + kLaunch;
+  const double G = N * N * N / kGemmRate[n] + kLaunch;
   const double T = 4.0 * N * N / kHbm + 2 * kLaunch;  // trace of a product, u16
   const double copy = 4.0 * N * N / kHbm + kLaunch;
   const int64_t q = m / c, r = m % c;
@@ -166,10 +170,10 @@ double plan_cost(int64_t m, int64_t c, double N, double nnz) {
   return cost;
 }
 
-Plan choose_plan(int64_t m, double N, double nnz) {
+Plan choose_plan(int n, int64_t m, double N, double nnz) {
   Plan best;
   for (int64_t c = 1; c <= m; ++c) {
-    const double cst = plan_cost(m, c, N, nnz);
+    const double cst = plan_cost(n, m, c, N, nnz);
     if (cst < best.cost) {
       best.cost = cst;
       best.c = c;
@@ -217,7 +221,7 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
   // 16-byte loads whatever N is
   const int64_t ld = (N + 63) / 64 * 64;
   const size_t mat = (size_t)N * (size_t)ld * sizeof(uint16_t);
-  const Plan plan = choose_plan(m, (double)N, (double)st->nnz);
+  const Plan plan = choose_plan(n, m, (double)N, (double)st->nnz);
   const int64_t c = plan.c, q = m / c, r = m % c;
 
   TP_HIP_CHECK(ensure(ws.scalar, 64));
