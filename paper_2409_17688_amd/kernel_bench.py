@@ -1,0 +1,104 @@
+"""Microbenchmarks of the library's kernels at the shapes of path order n.
+
+    python -m paper_2409_17688_amd.kernel_bench --op spmm --n 12 --reps 5
+    python -m paper_2409_17688_amd.kernel_bench --op trace --n 12
+    python -m paper_2409_17688_amd.kernel_bench --op gemm --n 10 --config 0
+    python -m paper_2409_17688_amd.kernel_bench --op batch --instances mixed64
+
+Matrices use the library's resident layout (rows padded to 64 entries).
+Times come from HIP events on the launch stream; one JSON line per run with
+the algorithmic work of one launch:
+  spmm   nnz(A) * N (min,+) operations; bytes: X read once, Y written (4 N^2)
+  trace  2 N^2 entries read (4 N^2 bytes)
+  gemm   N^3 (min,+) operations
+  batch  one persistent launch answering the instances (cold context)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+
+def _events(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps / 1e3
+
+
+def _padded(torch, N):
+    ld = (N + 63) // 64 * 64
+    return torch.empty((N, ld), dtype=torch.uint16, device="cuda")[:, :N]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--op", choices=["spmm", "trace", "gemm", "batch"], required=True)
+    ap.add_argument("--n", type=int, default=10)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--config", type=int, default=None, help="dense product tile config")
+    ap.add_argument("--instances", default="mixed64", help="batch workload: mixed64 or n:mlist")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from . import _lib as tp
+    n = args.n
+    out = {"op": args.op}
+    if args.op in ("spmm", "trace", "gemm"):
+        N = tp.tp_state_dim(n)
+        X, Y = _padded(torch, N), _padded(torch, N)
+        tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
+        out.update({"n": n, "N": N})
+        if args.op == "spmm":
+            nnz = tp.tp_state_nnz(n)
+            rowptr, col, z = tp.tp_build_state_csr(n)
+            t = _events(torch, lambda: tp.tp_minplus_spmm(rowptr, col, z, X, Y), args.reps)
+            out.update({"nnz": nnz, "ms": t * 1e3, "Tminplus_ops": nnz * N / t / 1e12})
+        elif args.op == "trace":
+            tp.tp_minplus_spmm(*tp.tp_build_state_csr(n), X, Y)
+            t = _events(torch, lambda: tp.tp_trace_of_product(X, Y), args.reps)
+            out.update({"ms": t * 1e3, "GBs": 4.0 * N * N / t / 1e9})
+        else:
+            C = _padded(torch, N)
+            t = _events(torch, lambda: tp.tp_minplus_gemm(X, X, C, config=args.config),
+                        args.reps)
+            out.update({"config": args.config, "ms": t * 1e3, "Tminplus_ops": N ** 3 / t / 1e12})
+    else:
+        import os
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import synth
+        if args.instances == "mixed64":
+            inst = synth.batch_instances(seed=0)
+        else:
+            nn, ms = args.instances.split(":")
+            inst = [(int(nn), int(m)) for m in ms.split(",")]
+        ns, ms = [a for a, _ in inst], [b for _, b in inst]
+        for nn in sorted(set(ns)):
+            tp.tp_tropical_power_trace(nn, 3)
+        times = []
+        for _ in range(args.reps):
+            ctx = tp.tp_ctx_create(64 << 30)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tp.tp_batch_power_trace(ctx, ns, ms)
+                tp.tp_ctx_check(ctx)
+                times.append(time.perf_counter() - t0)
+            finally:
+                tp.tp_ctx_destroy(ctx)
+        out.update({"instances": len(inst), "ms": min(times) * 1e3,
+                    "ms_all": [round(t * 1e3, 2) for t in times]})
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
