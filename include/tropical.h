@@ -180,7 +180,7 @@ int tp_ctx_destroy(void *ctx);
 
 /* Tuning and test parameters of a context. */
 #define TP_PARAM_WAIT_LIMIT_US 1 /* bound on one dependency wait (default 20 s) */
-#define TP_PARAM_GRID 2          /* workgroups of the persistent kernel; 0 = fill the chip */
+#define TP_PARAM_GRID 2          /* workgroups of the persistent kernel (>= 8); 0 = fill the chip */
 #define TP_PARAM_SPMM_ROWS 16    /* TP_PARAM_SPMM_ROWS + n: rows per chain task; 0 = auto */
 #define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
                                     n >= 8, else 32); fixed once powers of n are resident */

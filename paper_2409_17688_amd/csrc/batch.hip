@@ -21,12 +21,16 @@
 //   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
 //   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
 //          instance's result with an atomic min
-// A persistent kernel pops tasks in queue order with an atomic counter.  A
-// task waits (on at most two per-power completion counters) only for tasks
-// that precede it in the queue, which were popped earlier by running
-// workgroups, so every wait ends; as a safety net each wait is bounded in
-// time, and a timed-out wait sets an abort flag that makes every workgroup
-// drain the queue without work.  A finished task publishes its rows with an
+// The tasks are dealt to 8 queues, one per XCD, each keeping the dependency
+// order of the whole list; a group of tasks (one chain level, one giant, one
+// instance's traces) goes to the queues in contiguous chunks, so that what an
+// XCD runs together shares its inputs in that XCD's L2.  A persistent kernel
+// pops tasks with one atomic counter per queue, its own XCD's queue first and
+// the others when that one is empty.  A task waits (on at most two per-power
+// completion counters) only for tasks of earlier groups; every queue hands
+// those out before any later task, to running workgroups, so every wait ends;
+// as a safety net each wait is bounded in time, and a timed-out wait sets an
+// abort flag that makes every workgroup drain the queues without work.  A finished task publishes its rows with an
 // agent-scope release (so the L2s of other XCDs see them) and a counter
 // increment; a workgroup acquires once per power it starts depending on.
 // The launch (counter reset, result reset, persistent kernel) is captured
@@ -56,7 +60,7 @@ struct Task {
   int32_t dep2, dep2_target;   //   counts they must reach
   int32_t done;                // counter bumped when finished (-1: none)
   int32_t inst;                // instance of a TRACE
-  int32_t pad;
+  int32_t queue;               // queue (XCD) the task is dealt to
 };
 
 struct Slot {
@@ -71,12 +75,15 @@ struct Slot {
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
+constexpr int kQueues = 8;  // one task queue per XCD
+
 struct Control {
-  int32_t head;  // next task to pop
-  int32_t ntasks;
-  int32_t abort;  // set when a wait exceeded the limit
+  int32_t head[kQueues];   // next task of each queue
+  int32_t qbeg[kQueues];   // first task of each queue in the task array
+  int32_t qcnt[kQueues];   // tasks in each queue
+  int32_t abort;           // set when a wait exceeded the limit
   int32_t pad;
-  int64_t wait_limit;  // in s_memrealtime ticks (100 MHz)
+  int64_t wait_limit;      // in s_memrealtime ticks (100 MHz)
 };
 
 constexpr int kMaxSlots = 16;
@@ -100,7 +107,9 @@ __device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, in
       __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return 0;
     }
-    __builtin_amdgcn_s_sleep(10);  // ~640 clocks between polls
+    // a long pause between polls: hundreds of waiting workgroups polling
+    // one counter would otherwise crowd out the task pops and increments
+    __builtin_amdgcn_s_sleep(127);  // ~8000 clocks
   }
   return 1;
 }
@@ -115,14 +124,24 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
   __shared__ int32_t part[4];
   __shared__ int32_t s_task, s_go, s_fresh;
   int acq_dep = -1, acq_dep2 = -1;  // dependencies this workgroup has acquired (thread 0)
-  const int ntasks = ctl->ntasks;
   const int64_t limit = ctl->wait_limit;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the hardware deals workgroups to the XCDs in turn, so workgroup b runs on
+  // XCD b mod 8 and serves that queue first; when it is empty it takes tasks
+  // from the others, always in each queue's own order
+  const int home = blockIdx.x % kQueues;
   while (true) {
     if (threadIdx.x == 0) {
-      const int t = atomicAdd(&ctl->head, 1);
+      int t = -1;
+      for (int i = 0; i < kQueues && t < 0; ++i) {
+        const int q = (home + i) % kQueues;
+        const int cnt = ctl->qcnt[q];
+        if (ld_relaxed(&ctl->head[q]) >= cnt) continue;
+        const int k = atomicAdd(&ctl->head[q], 1);
+        if (k < cnt) t = ctl->qbeg[q] + k;
+      }
       int go = 0, fresh = 0;
-      if (t < ntasks) {
+      if (t >= 0) {
         go = ld_relaxed(&ctl->abort) == 0;
         const int d1 = tasks[t].dep, d2 = tasks[t].dep2;
         if (go) go = wait_counter(counters, d1, tasks[t].dep_target, ctl, limit);
@@ -138,7 +157,7 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
     __syncthreads();
     const int t = s_task;
     const int go = s_go;
-    if (t >= ntasks) break;
+    if (t < 0) break;
     const Task task = tasks[t];
     if (go) {
       // the powers this task reads are final once their counters are
@@ -152,7 +171,7 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
         for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
           const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
           for (int64_t c0 = task.c0 + (int64_t)lane * 8; c0 < task.c1; c0 += kPanel)
-            spmm_row_chunk<uint16_t, true, 4>(sl.rowptr, sl.col, sl.z, X, ld, Y, ld, N, qu, c0);
+            spmm_row_chunk<uint16_t, true, 8>(sl.rowptr, sl.col, sl.z, X, ld, Y, ld, N, qu, c0);
         }
       } else if (task.type == kGemm) {
         gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
@@ -458,6 +477,14 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   };
 
+  // a group of tasks (one chain level, one giant product or one instance's
+  // traces) is dealt to the queues in contiguous chunks, so that the tasks an
+  // XCD runs together share their inputs in its L2
+  auto deal = [&](size_t first) {
+    const size_t cnt = tasks.size() - first;
+    for (size_t i = 0; i < cnt; ++i) tasks[first + i].queue = (int32_t)(i * kQueues / cnt);
+  };
+
   // every instance's pair of exponents; traces are queued right after the
   // last power they read
   std::vector<int> ta(count), tb(count);
@@ -477,6 +504,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         continue;
       }
       const int64_t N = c->sets[plans[s].n].N;
+      const size_t first = tasks.size();
       for (int64_t i0 = 0; i0 < N; i0 += 64) {
         Task t{};
         t.type = kTrace;
@@ -491,6 +519,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         t.inst = j;
         tasks.push_back(t);
       }
+      deal(first);
     }
     waiting[s].swap(rest);
   };
@@ -509,8 +538,11 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
           k == 1 ? (int)std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)))
                  : (c->spmm_rows[p.n] > 0 ? c->spmm_rows[p.n] : auto_spmm_rows(N, p.view.nnz));
       const int64_t panel = k == 1 ? N : kPanel;
-      for (int64_t r0 = 0; r0 < N; r0 += rows) {
-        for (int64_t c0 = 0; c0 < N; c0 += panel) {
+      const size_t first = tasks.size();
+      // panel by panel, rows in order: an XCD's chunk covers contiguous rows
+      // of one panel (lexicographic neighbours share many successors)
+      for (int64_t c0 = 0; c0 < N; c0 += panel) {
+        for (int64_t r0 = 0; r0 < N; r0 += rows) {
           Task t{};
           t.type = k == 1 ? kBuild : kSpmm;
           t.slot = s;
@@ -531,6 +563,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
           ++ntask[s][k];
         }
       }
+      deal(first);
     }
     for (int s = 0; s < nslots; ++s)
       if (k <= plans[s].chain_top) push_ready_traces(s, k);
@@ -552,6 +585,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         int l, rr;
         giant_split(j, &l, &rr);
         const int x = l * ps.c, y = rr * ps.c;
+        const size_t first = tasks.size();
         for (int64_t m0 = 0; m0 < ps.N; m0 += kGBM) {
           for (int64_t n0 = 0; n0 < ps.N; n0 += kGBN) {
             Task t{};
@@ -569,6 +603,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
             ++ntask[s][e];
           }
         }
+        deal(first);
       }
       push_ready_traces(s, e);
     }
@@ -579,6 +614,18 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       set_error("internal: an instance of n = %d has no plan", plans[s].n);
       return TP_EINVAL;
     }
+
+  // queues: each keeps the dependency order of the whole list
+  std::vector<Task> ordered;
+  ordered.reserve(tasks.size());
+  int32_t qbeg[kQueues], qcnt[kQueues];
+  for (int q = 0; q < kQueues; ++q) {
+    qbeg[q] = (int32_t)ordered.size();
+    for (const Task &t : tasks)
+      if (t.queue == q) ordered.push_back(t);
+    qcnt[q] = (int32_t)ordered.size() - qbeg[q];
+  }
+  tasks.swap(ordered);
 
   // staging (pinned) and device buffers
   const size_t tbytes = tasks.size() * sizeof(Task);
@@ -618,8 +665,11 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
   Control *hc = (Control *)c->h_ctl.p;
-  hc->head = 0;
-  hc->ntasks = (int32_t)tasks.size();
+  for (int q = 0; q < kQueues; ++q) {
+    hc->head[q] = 0;
+    hc->qbeg[q] = qbeg[q];
+    hc->qcnt[q] = qcnt[q];
+  }
   hc->abort = 0;
   hc->pad = 0;
   hc->wait_limit = c->wait_limit;
@@ -728,7 +778,9 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
     return TP_OK;
   }
   if (param == TP_PARAM_GRID) {
-    TP_REQUIRE(value >= 0 && value <= (1 << 20), "grid out of range");
+    // every queue needs a home workgroup (see the kernel): at least 8
+    TP_REQUIRE(value == 0 || (value >= kQueues && value <= (1 << 20)),
+               "grid must be 0 (fill the chip) or in %d..%d", kQueues, 1 << 20);
     c->grid_override = (int)value;
     return TP_OK;
   }
