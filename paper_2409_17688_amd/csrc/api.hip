@@ -74,7 +74,7 @@ void release(DevBuf &b) {
 struct State {
   int n = 0;
   int64_t N = 0, nnz = -1;
-  DevBuf masks, z, rowptr, col;
+  DevBuf masks, z, rowptr, col, colz;
   bool csr_ready = false;
 };
 
@@ -113,8 +113,10 @@ int get_state(int n, hipStream_t s, State **out) {
     TP_HIP_CHECK(hipStreamSynchronize(s));
     st.nnz = nnz;
     TP_HIP_CHECK(ensure(st.col, (size_t)nnz * sizeof(uint32_t)));
+    TP_HIP_CHECK(ensure(st.colz, (size_t)nnz * sizeof(uint32_t)));
     TP_HIP_CHECK(launch_csr_fill(N, n, (const uint32_t *)st.masks.ptr,
-                                 (const int64_t *)st.rowptr.ptr, (uint32_t *)st.col.ptr, s));
+                                 (const int64_t *)st.rowptr.ptr, (uint32_t *)st.col.ptr,
+                                 (uint32_t *)st.colz.ptr, s));
     st.csr_ready = true;
   }
   *out = &st;
@@ -292,6 +294,7 @@ int state_view(int n, hipStream_t s, StateView *out) {
   out->rowptr = (const int64_t *)st->rowptr.ptr;
   out->col = (const uint32_t *)st->col.ptr;
   out->z = (const uint8_t *)st->z.ptr;
+  out->colz = (const uint32_t *)st->colz.ptr;
   return TP_OK;
 }
 
@@ -487,6 +490,7 @@ int tp_release_cache(void) {
     release(kv.second.z);
     release(kv.second.rowptr);
     release(kv.second.col);
+    release(kv.second.colz);
   }
   g_states.clear();
   for (auto &kv : g_ws) {

@@ -8,31 +8,41 @@
 //                           using the sparse left factor (nnz * N per level);
 //   giants  A^(jc), j >= 2  by dense (min,+) products of two resident powers,
 //                           j = h + (j - h) with h the largest power of two
-//                           <= j (h = j/2 when j is one), so J giants take
-//                           about log2(J) rounds of independent products.
+//                           <= j (h = j/2 when j is a power of two itself),
+//                           so J giants take about log2(J) rounds of
+//                           independent products.
 // Instance m is answered from two resident powers: m <= 2c by
 // (ceil(m/2), floor(m/2)), otherwise m = jc + r with 1 <= r <= c by
 // (jc, r).  Memory per n is (c + m_max/c) powers instead of m_max/2, and the
 // number of sequential chain levels is c instead of m_max/2.
 //
-// The work of a batch is a queue of tasks in dependency order:
+// The work of a batch is a list of tasks in dependency order:
 //   BUILD  rows of A^1 = A(D_n)
 //   SPMM   rows x one 512-column panel of A^k = A x A^(k-1)
 //   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
 //   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
 //          instance's result with an atomic min
-// The tasks are dealt to 8 queues, one per XCD, each keeping the dependency
-// order of the whole list; a group of tasks (one chain level, one giant, one
-// instance's traces) goes to the queues in contiguous chunks, so that what an
-// XCD runs together shares its inputs in that XCD's L2.  A persistent kernel
-// pops tasks with one atomic counter per queue, its own XCD's queue first and
-// the others when that one is empty.  A task waits (on at most two per-power
-// completion counters) only for tasks of earlier groups; every queue hands
-// those out before any later task, to running workgroups, so every wait ends;
-// as a safety net each wait is bounded in time, and a timed-out wait sets an
-// abort flag that makes every workgroup drain the queues without work.  A finished task publishes its rows with an
-// agent-scope release (so the L2s of other XCDs see them) and a counter
-// increment; a workgroup acquires once per power it starts depending on.
+// Dependencies are as narrow as the arithmetic allows, each a completion
+// counter and a target count:
+//   * column panel P of A x X needs column panel P of X only, so a chain
+//     level waits for the same panel of the level before (per-panel
+//     counters); each panel's whole chain is dealt to one queue, so its XCD
+//     keeps that panel of X in its L2 from level to level;
+//   * a product tile (rows R, columns C) and a trace block (rows I) read
+//     rows R (I) of the left factor and columns C (I) of the right one, so
+//     a giant counts its finished tiles per 128-row and per 128-column block;
+//   * everything else waits for a whole power.
+// The list is split into 8 queues, one per XCD, each keeping the list's
+// order; giants and traces go to the queues in contiguous chunks.  A
+// persistent kernel pops tasks with one atomic counter per queue, its own
+// XCD's queue first and the others when that one is empty.  Every
+// dependency points to an earlier task of the list and a queue is only left
+// when empty, so the earliest unfinished task is always popped by a running
+// workgroup and every wait ends; as a safety net each wait is bounded in
+// time, and a timed-out wait sets an abort flag that makes every workgroup
+// drain the queues without work.  A finished task publishes its rows with
+// an agent-scope release (so the L2s of other XCDs see them) and counter
+// increments; a workgroup acquires once per dependency it starts waiting on.
 // The launch (counter reset, result reset, persistent kernel) is captured
 // once in a hipGraph and replayed for every batch.
 #include <string.h>
@@ -58,7 +68,7 @@ struct Task {
   int32_t row0, row1, c0, c1;  // rows and columns of the output block
   int32_t dep, dep_target;     // counters to wait for (-1: none) and the
   int32_t dep2, dep2_target;   //   counts they must reach
-  int32_t done;                // counter bumped when finished (-1: none)
+  int32_t done, done2;         // counters bumped when finished (-1: none)
   int32_t inst;                // instance of a TRACE
   int32_t queue;               // queue (XCD) the task is dealt to
 };
@@ -70,8 +80,7 @@ struct Slot {
   int32_t pad;
   const uint32_t *masks;
   const int64_t *rowptr;
-  const uint32_t *col;
-  const uint8_t *z;
+  const uint32_t *colz;     // successors with their labels in the top byte
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
@@ -90,6 +99,68 @@ constexpr int kMaxSlots = 16;
 constexpr uint16_t kInf = 0xFFFFu;
 constexpr int kPanel = 512;                       // columns of an SPMM task: 64 lanes x 8
 constexpr int kGBM = 128, kGBN = 128, kGBK = 32;  // dense product tile
+
+// The CSR is read-only for the whole launch: through constant-space views a
+// wave-uniform index into it becomes a scalar load.
+typedef const __attribute__((address_space(4))) int64_t *kconst_i64;
+typedef const __attribute__((address_space(4))) uint32_t *kconst_u32;
+
+// Row q (wave-uniform) of A^k = A x A^(k-1) over the 8 columns c0 .. c0 + 7
+// of this lane: Y[q][c] = min over successors p of z_p + X[p][c].  The loads
+// read all 8 entries even past N (rows are padded to a multiple of 64); only
+// columns < N are stored.  U successors are gathered per round.
+template <int U>
+__device__ __forceinline__ void batch_spmm_row(kconst_i64 rowptr, kconst_u32 colz,
+                                               const uint16_t *X, uint16_t *Y, int64_t ld,
+                                               int64_t N, int64_t q, int64_t c0) {
+  const int64_t b = rowptr[q], e = rowptr[q + 1];
+  // row p of X starts at uint4 p * ld / 8 (uniform); this lane's 8 columns
+  // are uint4 c0 / 8 of the row (ld and c0 are multiples of 8)
+  const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
+  const int64_t ld4 = ld / 8;
+  const uint32_t off = (uint32_t)(c0 / 8);
+  u16x2 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = splat(kInf);
+  int64_t i = b;
+  for (; i + U <= e; i += U) {
+    u32x4 v[U];
+    uint32_t pz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      pz[u] = colz[i + u];
+      v[u] = Xg[(int64_t)(pz[u] & 0xFFFFFFu) * ld4 + off];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u16x2 lab = splat((uint16_t)(pz[u] >> 24));
+      acc[0] = pk_min(acc[0], pk_add_sat(lab, as_pk(v[u].x)));
+      acc[1] = pk_min(acc[1], pk_add_sat(lab, as_pk(v[u].y)));
+      acc[2] = pk_min(acc[2], pk_add_sat(lab, as_pk(v[u].z)));
+      acc[3] = pk_min(acc[3], pk_add_sat(lab, as_pk(v[u].w)));
+    }
+  }
+  for (; i < e; ++i) {
+    const uint32_t pz = colz[i];
+    const u32x4 v = Xg[(int64_t)(pz & 0xFFFFFFu) * ld4 + off];
+    const u16x2 lab = splat((uint16_t)(pz >> 24));
+    acc[0] = pk_min(acc[0], pk_add_sat(lab, as_pk(v.x)));
+    acc[1] = pk_min(acc[1], pk_add_sat(lab, as_pk(v.y)));
+    acc[2] = pk_min(acc[2], pk_add_sat(lab, as_pk(v.z)));
+    acc[3] = pk_min(acc[3], pk_add_sat(lab, as_pk(v.w)));
+  }
+  if (c0 + 8 <= N) {
+    *(gmut<u32x4>)(to_global_mut(Y) + q * ld + c0) =
+        u32x4{as_u32(acc[0]), as_u32(acc[1]), as_u32(acc[2]), as_u32(acc[3])};
+  } else {
+    const gmut<uint16_t> y = to_global_mut(Y) + q * ld + c0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (c0 + 2 * r < N) y[2 * r] = acc[r].x;
+      if (c0 + 2 * r + 1 < N) y[2 * r + 1] = acc[r].y;
+    }
+  }
+}
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -155,8 +226,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
       s_fresh = fresh;
     }
     __syncthreads();
-    const int t = s_task;
-    const int go = s_go;
+    // uniform across the workgroup: the task record is read with scalar loads
+    const int t = __builtin_amdgcn_readfirstlane(s_task);
+    const int go = __builtin_amdgcn_readfirstlane(s_go);
     if (t < 0) break;
     const Task task = tasks[t];
     if (go) {
@@ -171,12 +243,13 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
         for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
           const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
           for (int64_t c0 = task.c0 + (int64_t)lane * 8; c0 < task.c1; c0 += kPanel)
-            spmm_row_chunk<uint16_t, true, 8>(sl.rowptr, sl.col, sl.z, X, ld, Y, ld, N, qu, c0);
+            batch_spmm_row<16>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, X, Y, ld, N, qu, c0);
         }
       } else if (task.type == kGemm) {
         gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
-            (int)N, (int)N, (int)N, sl.powers[task.x], ld, sl.powers[task.y], ld,
-            sl.powers[task.out], ld, 0, task.row0, task.c0,
+            (int)N, (int)N, (int)N, sl.powers[task.x], ld,
+            sl.powers[task.y], ld, sl.powers[task.out], ld, 0, task.row0,
+            task.c0,
             reinterpret_cast<uint16_t(*)[kGBK][kGBM]>(lds),
             reinterpret_cast<uint16_t(*)[kGBK][kGBN]>(lds + 2 * kGBK * kGBM));
       } else if (task.type == kTrace) {
@@ -184,7 +257,8 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = splat(kInf);
         for (int64_t k0 = 0; k0 < N; k0 += 64)
-          trace_tile<uint16_t, true>(sl.powers[task.x], ld, sl.powers[task.y], ld, N, task.row0,
+          trace_tile<uint16_t, true>(sl.powers[task.x], ld,
+                                     sl.powers[task.y], ld, N, task.row0,
                                      k0, lds, acc);
         const int32_t best = block_min(acc, part);
         if (threadIdx.x == 0 && best < (int32_t)kInf) atomicMin(&results[task.inst], best);
@@ -202,8 +276,12 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();  // also keeps the LDS arena from being reused too early
-    if (threadIdx.x == 0 && task.done >= 0)
+    if (threadIdx.x == 0 && task.done >= 0) {
       __hip_atomic_fetch_add(&counters[task.done], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (task.done2 >= 0)
+        __hip_atomic_fetch_add(&counters[task.done2], 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -275,13 +353,12 @@ struct Ctx {
 
 namespace {
 
-int auto_spmm_rows(int64_t N, int64_t nnz) {
-  // about 2^18 (min,+) operations per task over one panel, a multiple of 4
-  // rows (one per wave)
-  const double per_row = (double)nnz / (double)N * (double)std::min<int64_t>(N, kPanel);
-  int64_t r = (int64_t)(262144.0 / std::max(per_row, 1.0));
-  r = std::max<int64_t>(4, std::min<int64_t>(r, 64));
-  return (int)((r + 3) / 4 * 4);
+int auto_spmm_rows(int64_t N) {
+  // about 64 row blocks per panel and level: measured on MI355X, larger
+  // blocks leave workgroups idle at the end of a level, smaller ones spend
+  // more time per row (n = 9: 0.34 ms per level at 48-64 rows, 0.69 ms at 8)
+  const int64_t r = (N / 64 + 3) / 4 * 4;
+  return (int)std::max<int64_t>(8, std::min<int64_t>(r, 64));
 }
 
 int auto_baby(int n) { return n >= 8 ? 16 : 32; }
@@ -461,12 +538,42 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
   const int nslots = (int)plans.size();
+  // completion counters: one per (slot, exponent) counting every task that
+  // writes the power, then one per (slot, chain level, column panel) for the
+  // chain, whose panels are independent (column block P of A x X needs only
+  // column block P of X), so a panel's next level waits for that panel only
   auto counter = [&](int slot, int e) { return slot * (maxexp + 1) + e; };
+  std::vector<int> pbase(nslots), npan(nslots);
+  int ncounters = nslots * (maxexp + 1);
+  for (int s = 0; s < nslots; ++s) {
+    npan[s] = (int)((c->sets[plans[s].n].N + kPanel - 1) / kPanel);
+    pbase[s] = ncounters;
+    ncounters += (plans[s].chain_top + 1) * npan[s];
+  }
+  auto panel_counter = [&](int s, int e, int64_t c0) {
+    return pbase[s] + e * npan[s] + (int)(c0 / kPanel);
+  };
+  // a giant (dense product) counts its finished tiles per 128-row block and
+  // per 128-column block: a product tile or a trace block that reads rows (or
+  // columns) of it waits for those blocks only
+  std::map<std::pair<int, int>, int> gbase;
+  std::vector<int> nblk(nslots);
+  for (int s = 0; s < nslots; ++s) {
+    const PowerSet &ps = c->sets[plans[s].n];
+    nblk[s] = (int)((ps.N + kGBM - 1) / kGBM);
+    for (int j : plans[s].giants) {
+      const int e = j * ps.c;
+      if (ps.have.count(e)) continue;
+      gbase[{s, e}] = ncounters;
+      ncounters += 2 * nblk[s];
+    }
+  }
   auto computed = [&](int s, int e) { return c->sets[plans[s].n].have.count(e) == 0; };
 
   std::vector<Task> tasks;
   std::vector<std::vector<int>> ntask(nslots, std::vector<int>(maxexp + 1, 0));
-  // dependency on exponent e of slot s: none when e is resident already
+  // dependency on all of exponent e of slot s (a chain power): none when e
+  // is resident already
   auto dep_of = [&](int s, int e, int32_t *dep, int32_t *target) {
     if (!computed(s, e)) {
       *dep = -1;
@@ -474,6 +581,27 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     } else {
       *dep = counter(s, e);
       *target = ntask[s][e];
+    }
+  };
+  std::vector<int> per_panel(nslots, 0);  // SPMM tasks per panel of one chain level
+  // dependency on rows [r0, r0 + 128) (all columns) of exponent e
+  auto rows_dep = [&](int s, int e, int64_t r0, int32_t *dep, int32_t *target) {
+    auto it = gbase.find({s, e});
+    if (it == gbase.end()) return dep_of(s, e, dep, target);
+    *dep = it->second + (int)(r0 / kGBM);
+    *target = nblk[s];
+  };
+  // dependency on columns [c0, c0 + 128) (all rows) of exponent e
+  auto cols_dep = [&](int s, int e, int64_t c0, int32_t *dep, int32_t *target) {
+    auto it = gbase.find({s, e});
+    if (it != gbase.end()) {
+      *dep = it->second + nblk[s] + (int)(c0 / kGBN);
+      *target = nblk[s];
+    } else if (e >= 2 && computed(s, e)) {
+      *dep = panel_counter(s, e, c0);
+      *target = per_panel[s];
+    } else {
+      dep_of(s, e, dep, target);
     }
   };
 
@@ -513,9 +641,9 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         t.y = b;
         t.row0 = (int32_t)i0;
         t.row1 = (int32_t)std::min<int64_t>(i0 + 64, N);
-        dep_of(s, a, &t.dep, &t.dep_target);
-        dep_of(s, b, &t.dep2, &t.dep2_target);
-        t.done = -1;
+        rows_dep(s, a, i0, &t.dep, &t.dep_target);
+        cols_dep(s, b, i0, &t.dep2, &t.dep2_target);
+        t.done = t.done2 = -1;
         t.inst = j;
         tasks.push_back(t);
       }
@@ -525,6 +653,37 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   };
 
   for (int s = 0; s < nslots; ++s) push_ready_traces(s, 0);  // answered by resident powers
+
+  // Each column panel's chain goes to one queue (its XCD keeps the panel of
+  // X in its L2 from level to level); panels are spread over the queues by
+  // their work, largest first, onto the least loaded queue.
+  std::vector<std::vector<int>> pqueue(nslots);
+  {
+    struct Chain {
+      double work;
+      int s, p;
+    };
+    std::vector<Chain> chains;
+    for (int s = 0; s < nslots; ++s) {
+      const Plan &p = plans[s];
+      const int64_t N = c->sets[p.n].N;
+      pqueue[s].assign(npan[s], 0);
+      if (p.chain_top < 2) continue;
+      for (int P = 0; P < npan[s]; ++P) {
+        const int64_t width = std::min<int64_t>(kPanel, N - (int64_t)P * kPanel);
+        chains.push_back({(double)p.view.nnz * (double)width * (double)(p.chain_top - 1), s, P});
+      }
+    }
+    std::stable_sort(chains.begin(), chains.end(),
+                     [](const Chain &a, const Chain &b) { return a.work > b.work; });
+    double load[kQueues] = {0};
+    for (const Chain &ch : chains) {
+      const int q = (int)(std::min_element(load, load + kQueues) - load);
+      load[q] += ch.work;
+      pqueue[ch.s][ch.p] = q;
+    }
+  }
+
   // chain levels, level by level over all n
   int max_top = 0;
   for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
@@ -534,36 +693,58 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       const PowerSet &ps = c->sets[p.n];
       if (k > p.chain_top || !computed(s, k)) continue;
       const int64_t N = ps.N;
-      const int rows =
-          k == 1 ? (int)std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)))
-                 : (c->spmm_rows[p.n] > 0 ? c->spmm_rows[p.n] : auto_spmm_rows(N, p.view.nnz));
-      const int64_t panel = k == 1 ? N : kPanel;
       const size_t first = tasks.size();
-      // panel by panel, rows in order: an XCD's chunk covers contiguous rows
-      // of one panel (lexicographic neighbours share many successors)
-      for (int64_t c0 = 0; c0 < N; c0 += panel) {
+      if (k == 1) {
+        // A^1 row blocks over all columns
+        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)));
         for (int64_t r0 = 0; r0 < N; r0 += rows) {
           Task t{};
-          t.type = k == 1 ? kBuild : kSpmm;
+          t.type = kBuild;
           t.slot = s;
-          t.out = k;
-          t.x = k - 1;
+          t.out = 1;
           t.row0 = (int32_t)r0;
           t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
-          t.c0 = (int32_t)c0;
-          t.c1 = (int32_t)std::min<int64_t>(c0 + panel, N);
-          if (k >= 2) {
-            dep_of(s, k - 1, &t.dep, &t.dep_target);
-          } else {
-            t.dep = -1;
-          }
-          t.dep2 = -1;
-          t.done = counter(s, k);
+          t.c0 = 0;
+          t.c1 = (int32_t)N;
+          t.dep = t.dep2 = -1;
+          t.done = counter(s, 1);
+          t.done2 = -1;
           tasks.push_back(t);
-          ++ntask[s][k];
+          ++ntask[s][1];
+        }
+        deal(first);
+      } else {
+        const int rows = c->spmm_rows[p.n] > 0 ? c->spmm_rows[p.n] : auto_spmm_rows(N);
+        per_panel[s] = (int)((N + rows - 1) / rows);
+        // level k of panel P reads panel P of A^(k-1): that panel's counter
+        // when level k-1 is computed by this batch's chain, the power's
+        // counter for A^1, nothing when it is resident
+        for (int64_t c0 = 0; c0 < N; c0 += kPanel) {
+          for (int64_t r0 = 0; r0 < N; r0 += rows) {
+            Task t{};
+            t.type = kSpmm;
+            t.slot = s;
+            t.out = k;
+            t.x = k - 1;
+            t.row0 = (int32_t)r0;
+            t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
+            t.c0 = (int32_t)c0;
+            t.c1 = (int32_t)std::min<int64_t>(c0 + kPanel, N);
+            if (k - 1 >= 2 && computed(s, k - 1)) {
+              t.dep = panel_counter(s, k - 1, c0);
+              t.dep_target = per_panel[s];
+            } else {
+              dep_of(s, k - 1, &t.dep, &t.dep_target);
+            }
+            t.dep2 = -1;
+            t.done = panel_counter(s, k, c0);
+            t.done2 = counter(s, k);
+            t.queue = pqueue[s][c0 / kPanel];
+            tasks.push_back(t);
+            ++ntask[s][k];
+          }
         }
       }
-      deal(first);
     }
     for (int s = 0; s < nslots; ++s)
       if (k <= plans[s].chain_top) push_ready_traces(s, k);
@@ -596,9 +777,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
             t.y = y;
             t.row0 = (int32_t)m0;
             t.c0 = (int32_t)n0;
-            dep_of(s, x, &t.dep, &t.dep_target);
-            dep_of(s, y, &t.dep2, &t.dep2_target);
-            t.done = counter(s, e);
+            rows_dep(s, x, m0, &t.dep, &t.dep_target);
+            cols_dep(s, y, n0, &t.dep2, &t.dep2_target);
+            t.done = gbase.at({s, e}) + (int)(m0 / kGBM);
+            t.done2 = gbase.at({s, e}) + nblk[s] + (int)(n0 / kGBN);
             tasks.push_back(t);
             ++ntask[s][e];
           }
@@ -639,7 +821,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   TP_HIP_CHECK(grow(c->d_slots, kMaxSlots * sizeof(Slot)));
   TP_HIP_CHECK(grow(c->d_ptrs, nptr * sizeof(void *)));
   TP_HIP_CHECK(grow(c->d_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_counters, (size_t)nslots * (maxexp + 1) * sizeof(int32_t)));
+  TP_HIP_CHECK(grow(c->d_counters, (size_t)ncounters * sizeof(int32_t)));
   TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t)));
 
   memcpy(c->h_tasks.p, tasks.data(), tbytes);
@@ -655,8 +837,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.full = (1u << p.n) - 1u;
     sl.masks = p.view.masks;
     sl.rowptr = p.view.rowptr;
-    sl.col = p.view.col;
-    sl.z = p.view.z;
+    sl.colz = p.view.colz;
     sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
     hs[s] = sl;
     for (size_t e = 0; e < ptr_stride; ++e) {

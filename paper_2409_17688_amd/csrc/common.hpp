@@ -36,6 +36,39 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total) {
 __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ u16x2 as_pk(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 
+// Every matrix this library touches lives in global memory.  A pointer that
+// reaches a kernel through memory (a task table) is a generic one to the
+// compiler, whose loads become flat loads with per-lane 64-bit addresses and
+// waits shared with LDS traffic; reading through these views keeps them
+// global loads wherever the pointer came from.  (Index in the global space:
+// offsetting the generic pointer first lets the cast be folded away.)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+using gconst = const __attribute__((address_space(1))) T *;
+template <typename T>
+using gmut = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gconst<T> to_global(const T *p) {
+  return (gconst<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gmut<T> to_global_mut(T *p) {
+  return (gmut<T>)p;
+}
+// 16 and 8 bytes at global element address p (aligned).
+template <typename T>
+__device__ __forceinline__ uint4 gload16(gconst<T> p) {
+  const u32x4 v = *(gconst<u32x4>)p;
+  return uint4{v.x, v.y, v.z, v.w};
+}
+template <typename T>
+__device__ __forceinline__ uint2 gload8(gconst<T> p) {
+  const u32x2 v = *(gconst<u32x2>)p;
+  return uint2{v.x, v.y};
+}
+
 // Host side: status plumbing.
 void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
@@ -68,6 +101,7 @@ struct StateView {
   const int64_t *rowptr;
   const uint32_t *col;
   const uint8_t *z;
+  const uint32_t *colz;  // col with z of each successor in the top byte
 };
 int state_view(int n, hipStream_t s, StateView *out);
 
@@ -80,7 +114,7 @@ hipError_t launch_csr_count(int64_t N, int n, const uint32_t *masks, int64_t *ro
                             hipStream_t s);
 hipError_t launch_scan_rowptr(int64_t N, int64_t *rowptr, hipStream_t s);
 hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_t *rowptr,
-                           uint32_t *col, hipStream_t s);
+                           uint32_t *col, uint32_t *colz, hipStream_t s);
 
 // gemm.hip
 hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,

@@ -132,12 +132,12 @@ __device__ __forceinline__ void spmm_row_chunk(const int64_t *__restrict__ rowpt
 template <typename T, bool VEC>
 __device__ __forceinline__ uint4 load8(const T *__restrict__ M, int64_t ld, int64_t row,
                                        int64_t col, int64_t n) {
-  const T *p = M + row * ld + col;
+  const gconst<T> p = to_global(M) + row * ld + col;
   if (VEC && row < n && col + 8 <= n) {
     if constexpr (sizeof(T) == 2) {
-      return *reinterpret_cast<const uint4 *>(p);
+      return gload16<T>(p);
     } else {
-      const uint2 v = *reinterpret_cast<const uint2 *>(p);
+      const uint2 v = gload8<T>(p);
       return uint4{__builtin_amdgcn_perm(0u, v.x, 0x0c010c00u),
                    __builtin_amdgcn_perm(0u, v.x, 0x0c030c02u),
                    __builtin_amdgcn_perm(0u, v.y, 0x0c010c00u),

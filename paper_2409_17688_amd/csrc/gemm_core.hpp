@@ -47,8 +47,8 @@ template <typename T, bool VEC>
 __device__ __forceinline__ uint4 load_chunk(const T *__restrict__ base, int64_t ld, int row,
                                             int col, int rows, int cols) {
   constexpr int VE = 16 / sizeof(T);
-  const T *p = base + (int64_t)row * ld + col;
-  if (VEC && row < rows && col + VE <= cols) return *reinterpret_cast<const uint4 *>(p);
+  const gconst<T> p = to_global(base) + (int64_t)row * ld + col;
+  if (VEC && row < rows && col + VE <= cols) return gload16<T>(p);
   uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int e = 0; e < VE; ++e) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
   for (int i = 0; i < TM; ++i) {
     const int r = m0 + tm * TM + i;
     if (r >= M) continue;
-    T *crow = C + (int64_t)r * ldc;
+    const gmut<T> crow = to_global_mut(C) + (int64_t)r * ldc;
 #pragma unroll
     for (int j = 0; j < TN2; ++j) {
       const int c = n0 + tn * TN + 2 * j;
@@ -230,7 +230,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
         }
         if constexpr (sizeof(T) == 2) {
           if (VEC)
-            *reinterpret_cast<uint32_t *>(crow + c) = as_u32(v);
+            *(gmut<uint32_t>)(crow + c) = as_u32(v);
           else {
             crow[c] = v.x;
             crow[c + 1] = v.y;

@@ -167,9 +167,12 @@ __global__ void __launch_bounds__(1024) scan_kernel(int64_t N, int64_t *__restri
   }
 }
 
-// One wave per row: successor indices in increasing order.
+// One wave per row: successor indices in increasing order; colz, when not
+// NULL, gets each successor p with its label z_p (zeros of word p) in the
+// top byte (N < 2^24 for every n <= 12).
 __global__ void csr_fill_kernel(int64_t N, uint32_t full, const uint32_t *__restrict__ masks,
-                                const int64_t *__restrict__ rowptr, uint32_t *__restrict__ col) {
+                                const int64_t *__restrict__ rowptr, uint32_t *__restrict__ col,
+                                uint32_t *__restrict__ colz) {
   const int lane = threadIdx.x & 63;
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (q >= N) return;
@@ -183,6 +186,8 @@ __global__ void csr_fill_kernel(int64_t N, uint32_t full, const uint32_t *__rest
       uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
       col[pos + below] = (uint32_t)p;
+      if (colz)
+        colz[pos + below] = (uint32_t)p | ((uint32_t)__builtin_popcount(masks[p] & 0xFFFFu) << 24);
     }
     pos += __popcll(b);
   }
@@ -242,12 +247,12 @@ hipError_t launch_scan_rowptr(int64_t N, int64_t *rowptr, hipStream_t s) {
 }
 
 hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_t *rowptr,
-                           uint32_t *col, hipStream_t s) {
+                           uint32_t *col, uint32_t *colz, hipStream_t s) {
   if (N == 0) return hipSuccess;
   const uint32_t full = (1u << n) - 1u;
   const int waves = 4;
   hipLaunchKernelGGL(csr_fill_kernel, dim3((unsigned)((N + waves - 1) / waves)), dim3(64 * waves),
-                     0, s, N, full, masks, rowptr, col);
+                     0, s, N, full, masks, rowptr, col, colz);
   return hipGetLastError();
 }
 
