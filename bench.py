@@ -32,7 +32,11 @@ N_DEFAULT = 8192
 # plain 256 MiB copy: factors 2.00 and 1.00).  Valid for the kernel named
 # below only; set to None when that kernel changes until it is measured again.
 MEASURED_TRAFFIC = {"kernel": "minplus_gemm_kernel<128,256,32,8,16,3,u16,vec>",
+                    "config": 1, "ksplit": 1,
                     "bytes": (1049903 * 2.00 + 131072 * 1.00) * 1024}
+# tile configuration index -> kernel template arguments (BM, BN, BK, TM, TN, MINB)
+KERNEL_SHAPES = {0: "128,128,32,8,8,4", 1: "128,256,32,8,16,3", 2: "256,128,32,16,8,3",
+                 3: "64,64,32,4,4,4"}
 
 
 def parse():
@@ -93,6 +97,9 @@ def main():
 
     N = args.n
     A, B = synth.raw_gemm_pair(N, seed=0)
+    # the shape the default path runs for this product (tuning table or built-in rule)
+    cfg, ksplit = tp.tp_gemm_choice(tp.TP_U16, N, N, N)
+    kernel = f"minplus_gemm_kernel<{KERNEL_SHAPES[cfg]},u16,vec>"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     dA = torch.from_numpy(A).to(dev)
@@ -155,7 +162,11 @@ def main():
                      "peak": round(PEAK_MINPLUS / 1e12, 3), "unit": "Tminplus-ops/s",
                      "frac": round(achieved / PEAK_MINPLUS, 4),
                      "traffic": (round(MEASURED_TRAFFIC["bytes"])
-                                 if MEASURED_TRAFFIC and N == N_DEFAULT else None)},
+                                 if MEASURED_TRAFFIC and N == N_DEFAULT
+                                 and (cfg, ksplit) == (MEASURED_TRAFFIC["config"],
+                                                       MEASURED_TRAFFIC["ksplit"])
+                                 else None),
+                     "kernel": kernel + (f" x{ksplit} K slices" if ksplit > 1 else "")},
         "kernel_ms": round(avg_kernel_s * 1e3, 3),
     }
     if not args.no_cpu:

@@ -112,6 +112,47 @@ int tp_minplus_gemm_config(int dtype, int64_t M, int64_t N, int64_t K, const voi
                            int64_t lda, const void *d_B, int64_t ldb, void *d_C, int64_t ldc,
                            int accumulate, int config, hipStream_t stream);
 
+/* tp_minplus_gemm_config with K split into up to ksplit slices (1 <= ksplit
+ * <= 64; 1 = no split).  The slices (a multiple of 64 columns each) run as
+ * separate workgroups whose partial products go to library-owned scratch
+ * (one grow-only buffer per device and stream, allocated on first use, so
+ * not for code under graph capture); a reduction kernel then writes C as
+ * their elementwise minimum, and with accumulate != 0 the minimum with the
+ * old C.  The result equals the unsplit product: min over K is the minimum
+ * over the slices of the minimum within each.  Fills the chip when M x N
+ * has few output tiles.  TP_EINVAL on a bad config or ksplit. */
+int tp_minplus_gemm_ex(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A, int64_t lda,
+                       const void *d_B, int64_t ldb, void *d_C, int64_t ldc, int accumulate,
+                       int config, int ksplit, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning tables (filled by the autotuner; the library has built-in          */
+/* defaults).  None of them changes a result, only which kernel shape runs.  */
+/* ------------------------------------------------------------------------ */
+
+/* Default product shape: tp_minplus_gemm (and every dense product the
+ * library runs itself) uses, for max(M, N, K) <= max_dim, the entry with the
+ * smallest such max_dim: tile configuration `config` and K split `ksplit`.
+ * Setting an existing max_dim replaces it; max_dim < 0 clears the dtype's
+ * table (back to the built-in heuristic).  Process-wide, thread-safe. */
+int tp_tune_gemm(int dtype, int64_t max_dim, int config, int ksplit);
+
+/* The (config, ksplit) the default path would use for an M x N x K product
+ * of this dtype, into *config and *ksplit (host pointers). */
+int tp_gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *ksplit);
+
+/* Measured rates for the schedule planner of tp_tropical_power_trace at path
+ * order n (1..12): (min,+) operations per second of one sparse left step
+ * (nnz * N operations) and of one dense product (N^3).  Positive values, or
+ * both 0 to restore the built-in rates. */
+int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s);
+
+/* Library-wide defaults of the batch engine at path order n (1..12): rows
+ * per sparse task (rounded up to a multiple of 4) and baby steps c; 0 keeps
+ * the built-in rule.  A context's tp_ctx_set_param values take precedence;
+ * baby steps already fixed in a context do not change. */
+int tp_tune_batch(int n, int spmm_rows, int baby_steps);
+
 /* Matrix-vector products with the M x K matrix A:
  *   trans == 0:  y (M)  = A x x (x has K entries),  y_i = min_k a_ik + x_k
  *   trans == 1:  y (K)  = x x A (x has M entries),  y_k = min_i x_i + a_ik

@@ -55,6 +55,12 @@ _SIGS = {
     "tp_gemm_config_count": ([], _i),
     "tp_minplus_gemm_config": ([_i, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i, _i, _p],
                                _i),
+    "tp_minplus_gemm_ex": ([_i, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i, _i, _i,
+                            _p], _i),
+    "tp_tune_gemm": ([_i, _i64, _i, _i], _i),
+    "tp_gemm_choice": ([_i, _i64, _i64, _i64, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
+    "tp_tune_planner": ([_i, ctypes.c_double, ctypes.c_double], _i),
+    "tp_tune_batch": ([_i, _i, _i], _i),
     "tp_minplus_gemv": ([_i, _i64, _i64, _p, _i64, _p, _p, _i, _p], _i),
     "tp_minplus_spmm": ([_i, _i64, _i64, _p, _p, _p, _p, _i64, _p, _i64, _i64, _p], _i),
     "tp_trace_min": ([_i, _i64, _p, _i64, _p, _p], _i),
@@ -186,7 +192,10 @@ def tp_gemm_config_count() -> int:
 
 def tp_minplus_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
                     accumulate: bool = False, config: int | None = None,
-                    stream=None) -> torch.Tensor:
+                    ksplit: int | None = None, stream=None) -> torch.Tensor:
+    """C = A x B (min with the old C when accumulate).  config=None uses the
+    library's default (tuned) shape; config with ksplit calls
+    tp_minplus_gemm_ex, config alone tp_minplus_gemm_config."""
     dt = _dtype_code(A)
     if _dtype_code(B) != dt:
         raise TypeError("A and B must have the same dtype")
@@ -202,12 +211,42 @@ def tp_minplus_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = N
     if (M2, N2) != (M, N) or _dtype_code(C) != dt:
         raise ValueError("C has the wrong shape or dtype")
     if config is None:
+        if ksplit is not None:
+            raise ValueError("ksplit needs an explicit config")
         _check(lib.tp_minplus_gemm(dt, M, N, K, pa, lda, pb, ldb, pc, ldc, int(accumulate),
                                    _stream(stream)))
+    elif ksplit is not None:
+        _check(lib.tp_minplus_gemm_ex(dt, M, N, K, pa, lda, pb, ldb, pc, ldc, int(accumulate),
+                                      int(config), int(ksplit), _stream(stream)))
     else:
         _check(lib.tp_minplus_gemm_config(dt, M, N, K, pa, lda, pb, ldb, pc, ldc,
                                           int(accumulate), int(config), _stream(stream)))
     return C
+
+
+def tp_minplus_gemm_ex(A, B, C=None, accumulate=False, config=0, ksplit=1, stream=None):
+    return tp_minplus_gemm(A, B, C, accumulate, config=config, ksplit=ksplit, stream=stream)
+
+
+# ---------------------------------------------------------------- tuning --
+
+def tp_tune_gemm(dtype: int, max_dim: int, config: int = 0, ksplit: int = 1) -> None:
+    _check(lib.tp_tune_gemm(int(dtype), int(max_dim), int(config), int(ksplit)))
+
+
+def tp_gemm_choice(dtype: int, M: int, N: int, K: int) -> tuple[int, int]:
+    cfg, ks = ctypes.c_int(-1), ctypes.c_int(-1)
+    _check(lib.tp_gemm_choice(int(dtype), int(M), int(N), int(K), ctypes.byref(cfg),
+                              ctypes.byref(ks)))
+    return int(cfg.value), int(ks.value)
+
+
+def tp_tune_planner(n: int, spmm_ops_per_s: float, gemm_ops_per_s: float) -> None:
+    _check(lib.tp_tune_planner(int(n), float(spmm_ops_per_s), float(gemm_ops_per_s)))
+
+
+def tp_tune_batch(n: int, spmm_rows: int, baby_steps: int) -> None:
+    _check(lib.tp_tune_batch(int(n), int(spmm_rows), int(baby_steps)))
 
 
 def tp_minplus_gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False,

@@ -125,14 +125,19 @@ int get_state(int n, hipStream_t s, State **out) {
 
 // ---------------------------------------------------------------- planner --
 
-// Kernel rates measured on an MI355X by path order n (rows padded to 64
-// entries): (min,+) operations per second of one sparse left step
-// (nnz * N operations) and of one dense product (N^3), plus launch overhead.
-// Only their ratios steer the plan; every plan gives the same answer.
+// Kernel rates by path order n (rows padded to 64 entries): (min,+)
+// operations per second of one sparse left step (nnz * N operations) and of
+// one dense product (N^3), plus launch overhead.  The defaults were measured
+// on an MI355X; the autotuner replaces them (tp_tune_planner).  Only their
+// ratios steer the plan; every plan gives the same answer.  Guarded by g_mu.
 constexpr double kSpmmRate[13] = {0, 1e10, 1e10, 2e10, 5e10, 1e11, 5e10, 2.5e11,
                                   1.4e12, 4.5e12, 1.19e13, 1.05e13, 1.12e13};
 constexpr double kGemmRate[13] = {0, 1e9, 1e9, 1e10, 5e10, 1e11, 3e11, 2e12,
                                   1.45e13, 2.6e13, 3.37e13, 3.4e13, 3.4e13};
+double g_spmm_rate[13] = {0, 1e10, 1e10, 2e10, 5e10, 1e11, 5e10, 2.5e11,
+                          1.4e12, 4.5e12, 1.19e13, 1.05e13, 1.12e13};
+double g_gemm_rate[13] = {0, 1e9, 1e9, 1e10, 5e10, 1e11, 3e11, 2e12,
+                          1.45e13, 2.6e13, 3.37e13, 3.4e13, 3.4e13};
 constexpr double kHbm = 5.0e12;     // bytes / s for traces and copies
 constexpr double kLaunch = 6.0e-6;  // s per kernel launch
 
@@ -155,8 +160,8 @@ struct Plan {
 };
 
 double plan_cost(int n, int64_t m, int64_t c, double N, double nnz) {
-  const double S = nnz * N / kSpmmRate[n] + kLaunch;
-  const double G = N * N * N / kGemmRate[n] + kLaunch;
+  const double S = nnz * N / g_spmm_rate[n] + kLaunch;
+  const double G = N * N * N / g_gemm_rate[n] + kLaunch;
   const double T = 4.0 * N * N / kHbm + 2 * kLaunch;  // trace of a product, u16
   const double copy = 4.0 * N * N / kHbm + kLaunch;
   const int64_t q = m / c, r = m % c;
@@ -199,12 +204,12 @@ int power_of(uint16_t *P, int64_t q, int64_t N, int64_t ld, uint16_t *dst, uint1
   int which = 0;
   for (int b = top - 1; b >= 0; --b) {
     uint16_t *o = bufs[which];
-    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, cur, ld, o, ld, 0, -1, s));
+    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, cur, ld, o, ld, 0, -1, 1, s));
     cur = o;
     which ^= 1;
     if ((q >> b) & 1) {
       uint16_t *o2 = bufs[which];
-      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, P, ld, o2, ld, 0, -1, s));
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, P, ld, o2, ld, 0, -1, 1, s));
       cur = o2;
       which ^= 1;
     }
@@ -267,7 +272,7 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
       // H x X = P^(h+1) into a buffer that is neither H nor X
       uint16_t *o = (H == tmp_a) ? tmp_b : tmp_a;
       if (H == X) o = tmp_a;
-      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, ld, X, ld, o, ld, 0, -1, s));
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, ld, X, ld, o, ld, 0, -1, 1, s));
       TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, ld, o, ld, d_res, s));
     } else {
       TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, ld, H, ld, d_res, s));
@@ -385,7 +390,8 @@ int tp_minplus_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A,
                     hipStream_t stream) {
   int rc = check_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc);
   if (rc != TP_OK) return rc;
-  TP_HIP_CHECK(launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, -1, stream));
+  TP_HIP_CHECK(
+      launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, -1, 1, stream));
   return TP_OK;
 }
 
@@ -396,12 +402,54 @@ int tp_minplus_gemm_config(int dtype, int64_t M, int64_t N, int64_t K, const voi
   if (rc != TP_OK) return rc;
   TP_REQUIRE(config >= 0 && config < gemm_config_count(), "config %d outside 0..%d", config,
              gemm_config_count() - 1);
-  TP_HIP_CHECK(launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, config,
+  TP_HIP_CHECK(launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, config, 1,
                            stream));
   return TP_OK;
 }
 
+int tp_minplus_gemm_ex(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A, int64_t lda,
+                       const void *d_B, int64_t ldb, void *d_C, int64_t ldc, int accumulate,
+                       int config, int ksplit, hipStream_t stream) {
+  int rc = check_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc);
+  if (rc != TP_OK) return rc;
+  TP_REQUIRE(config >= 0 && config < gemm_config_count(), "config %d outside 0..%d", config,
+             gemm_config_count() - 1);
+  TP_REQUIRE(ksplit >= 1 && ksplit <= 64, "ksplit %d outside 1..64", ksplit);
+  TP_HIP_CHECK(launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, config,
+                           ksplit, stream));
+  return TP_OK;
+}
+
 int tp_gemm_config_count(void) { return gemm_config_count(); }
+
+int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s) {
+  TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
+  const bool reset = spmm_ops_per_s == 0 && gemm_ops_per_s == 0;
+  TP_REQUIRE(reset || (spmm_ops_per_s > 0 && gemm_ops_per_s > 0),
+             "rates must be positive (or both 0)");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_spmm_rate[n] = reset ? kSpmmRate[n] : spmm_ops_per_s;
+  g_gemm_rate[n] = reset ? kGemmRate[n] : gemm_ops_per_s;
+  return TP_OK;
+}
+
+int tp_tune_gemm(int dtype, int64_t max_dim, int config, int ksplit) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  if (max_dim >= 0) {
+    TP_REQUIRE(config >= 0 && config < gemm_config_count(), "config %d outside 0..%d", config,
+               gemm_config_count() - 1);
+    TP_REQUIRE(ksplit >= 1 && ksplit <= 64, "ksplit %d outside 1..64", ksplit);
+  }
+  return gemm_tune_set(dtype, max_dim, config, ksplit);
+}
+
+int tp_gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *ksplit) {
+  TP_REQUIRE(valid_dtype(dtype), "bad dtype %d", dtype);
+  TP_REQUIRE(M >= 0 && N >= 0 && K >= 0, "negative size");
+  TP_REQUIRE(config != nullptr && ksplit != nullptr, "NULL output");
+  gemm_choice(dtype, M, N, K, config, ksplit);
+  return TP_OK;
+}
 
 int tp_minplus_gemv(int dtype, int64_t M, int64_t K, const void *d_A, int64_t lda,
                     const void *d_x, void *d_y, int trans, hipStream_t stream) {

@@ -353,6 +353,12 @@ struct Ctx {
 
 namespace {
 
+// Library-wide defaults by n from the autotuner (0: none); a context's own
+// parameters take precedence.
+std::mutex g_tune_mu;
+int g_tuned_rows[16] = {0};
+int g_tuned_baby[16] = {0};
+
 int auto_spmm_rows(int64_t N) {
   // about 64 row blocks per panel and level: measured on MI355X, larger
   // blocks leave workgroups idle at the end of a level, smaller ones spend
@@ -362,6 +368,12 @@ int auto_spmm_rows(int64_t N) {
 }
 
 int auto_baby(int n) { return n >= 8 ? 16 : 32; }
+
+int rows_of(const Ctx *c, int n, int64_t N) {
+  if (c->spmm_rows[n] > 0) return c->spmm_rows[n];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tuned_rows[n] > 0 ? g_tuned_rows[n] : auto_spmm_rows(N);
+}
 
 // largest power of two <= j
 int pow2_floor(int j) {
@@ -472,7 +484,9 @@ struct Plan {
 int baby_of(Ctx *c, int n) {
   auto it = c->sets.find(n);
   if (it != c->sets.end() && it->second.c > 0) return it->second.c;
-  return c->baby[n] > 0 ? c->baby[n] : auto_baby(n);
+  if (c->baby[n] > 0) return c->baby[n];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tuned_baby[n] > 0 ? g_tuned_baby[n] : auto_baby(n);
 }
 
 std::vector<int> exponents_of(int chain_top, const std::set<int> &giants, int c) {
@@ -714,7 +728,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         }
         deal(first);
       } else {
-        const int rows = c->spmm_rows[p.n] > 0 ? c->spmm_rows[p.n] : auto_spmm_rows(N);
+        const int rows = rows_of(c, p.n, N);
         per_panel[s] = (int)((N + rows - 1) / rows);
         // level k of panel P reads panel P of A^(k-1): that panel's counter
         // when level k-1 is computed by this batch's chain, the power's
@@ -1062,6 +1076,16 @@ int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *
   Ctx *c = (Ctx *)ctx;
   std::lock_guard<std::mutex> lk(c->mu);
   return batch_run(c, count, n, m, gamma2_dev, stream);
+}
+
+int tp_tune_batch(int n, int spmm_rows, int baby_steps) {
+  TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
+  TP_REQUIRE(spmm_rows >= 0 && spmm_rows <= 65536, "rows per task out of range");
+  TP_REQUIRE(baby_steps >= 0 && baby_steps <= (1 << 16), "baby steps out of range");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned_rows[n] = (spmm_rows + 3) / 4 * 4;
+  g_tuned_baby[n] = baby_steps;
+  return TP_OK;
 }
 
 int tp_ctx_check(void *ctx, hipStream_t stream) {

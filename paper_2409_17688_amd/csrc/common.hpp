@@ -119,7 +119,10 @@ hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_
 // gemm.hip
 hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
                        const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
-                       int config, hipStream_t s);
+                       int config, int ksplit, hipStream_t s);
+// tuning table of the default (config < 0) choice; max_dim < 0 clears it
+int gemm_tune_set(int dtype, int64_t max_dim, int config, int ksplit);
+void gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *ksplit);
 int gemm_config_count();
 
 // gemv.hip
