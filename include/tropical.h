@@ -170,6 +170,29 @@ int tp_minplus_spmm(int dtype, int64_t rows, int64_t K, const int64_t *d_rowptr,
                     const uint32_t *d_col, const uint8_t *d_z, const void *d_X, int64_t ldx,
                     void *d_Y, int64_t ldy, int64_t ncols, hipStream_t stream);
 
+/* Forms of the sparse left step by the state matrix. */
+#define TP_STEP_AUTO 0    /* the tuned (or built-in) choice for n */
+#define TP_STEP_CSR 1     /* one wave per row gathering its successors' rows */
+#define TP_STEP_BLOCKED 2 /* the union of the successor lists of 16
+                           * consecutive rows, walked once per block and
+                           * applied to the rows that have each successor, so
+                           * each gathered row of X is read once per block */
+
+/* Y (N x ncols, u16) = A(D_n) x X (X: N x ncols, u16), N = tp_state_dim(n):
+ * the left multiplication of Algorithm 2's power chain by the state matrix
+ * itself, with the library's resident forms of A(D_n) (built and cached on
+ * first use per device and n).  Every form gives the result of
+ * tp_minplus_spmm with the CSR of tp_build_state_csr; TP_STEP_AUTO takes
+ * the form tp_tune_step set for n, else row blocks from n = 11 on (measured
+ * faster there) and the CSR gather below.  X and Y must not overlap.
+ * Leading dimensions in elements.  TP_EINVAL on a bad n, form or size. */
+int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, int64_t ldy,
+                      int64_t ncols, hipStream_t stream);
+
+/* The form TP_STEP_AUTO uses at path order n (TP_STEP_AUTO: the built-in
+ * rule).  The power chains of tp_tropical_power_trace use it too. */
+int tp_tune_step(int n, int form);
+
 /* ------------------------------------------------------------------------ */
 /* Traces: Theorem 2 reads gamma_2 as the minimum of the diagonal.            */
 /* ------------------------------------------------------------------------ */

@@ -31,6 +31,9 @@ TP_PARAM_WAIT_LIMIT_US = 1
 TP_PARAM_GRID = 2
 TP_PARAM_SPMM_ROWS = 16
 TP_PARAM_BABY_STEPS = 32
+TP_STEP_AUTO = 0
+TP_STEP_CSR = 1
+TP_STEP_BLOCKED = 2
 
 INF = {TP_U8: 255, TP_U16: 65535}
 
@@ -63,6 +66,8 @@ _SIGS = {
     "tp_tune_batch": ([_i, _i, _i], _i),
     "tp_minplus_gemv": ([_i, _i64, _i64, _p, _i64, _p, _p, _i, _p], _i),
     "tp_minplus_spmm": ([_i, _i64, _i64, _p, _p, _p, _p, _i64, _p, _i64, _i64, _p], _i),
+    "tp_state_left_mul": ([_i, _i, _p, _i64, _p, _i64, _i64, _p], _i),
+    "tp_tune_step": ([_i, _i], _i),
     "tp_trace_min": ([_i, _i64, _p, _i64, _p, _p], _i),
     "tp_trace_of_product": ([_i, _i64, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_sparse_trace_of_product": ([_i, _i64, _p, _p, _p, _p, _i64, _p, _p], _i),
@@ -283,6 +288,29 @@ def tp_minplus_spmm(rowptr: torch.Tensor, col: torch.Tensor, z: torch.Tensor, X:
                                col.data_ptr() if col.numel() else None, _vec(z, "z"), px, ldx,
                                py, ldy, ncols, _stream(stream)))
     return Y
+
+
+def tp_state_left_mul(n: int, X: torch.Tensor, Y: torch.Tensor | None = None,
+                      form: int = 0, stream=None) -> torch.Tensor:
+    """Y = A(D_n) x X for a u16 X with N = tp_state_dim(n) rows; form is
+    TP_STEP_AUTO, TP_STEP_CSR or TP_STEP_BLOCKED."""
+    if X.dtype != torch.uint16:
+        raise TypeError("X must be uint16")
+    N = tp_state_dim(n)
+    px, rows, ncols, ldx = _mat(X, "X")
+    if rows != N:
+        raise ValueError(f"X must have {N} rows")
+    if Y is None:
+        Y = torch.empty((N, ncols), dtype=X.dtype, device=X.device)
+    py, r2, c2, ldy = _mat(Y, "Y")
+    if (r2, c2) != (N, ncols) or Y.dtype != torch.uint16:
+        raise ValueError("Y has the wrong shape or dtype")
+    _check(lib.tp_state_left_mul(int(n), int(form), px, ldx, py, ldy, ncols, _stream(stream)))
+    return Y
+
+
+def tp_tune_step(n: int, form: int) -> None:
+    _check(lib.tp_tune_step(int(n), int(form)))
 
 
 # ---------------------------------------------------------------- traces --

@@ -7,8 +7,10 @@ What it tunes (none of it changes a result, only which kernel shape runs):
   * dense products: for the state-matrix orders N(n), n = 4..11, and each
     dtype, every tile configuration x K split; the fastest becomes the
     default for products up to that size (``tp_tune_gemm``);
+  * the sparse left step: the faster of its two forms per n, CSR gather or
+    row blocks (``tp_tune_step``);
   * the schedule planner of ``tp_tropical_power_trace``: measured (min,+)
-    rates of the sparse left step and of the tuned dense product per n
+    rates of that step and of the tuned dense product per n
     (``tp_tune_planner``);
   * the batch engine, n = 4..9: rows per sparse task and baby steps c, on a
     batch of 12 instances with m uniform in 3..200 (``tp_tune_batch``).
@@ -102,26 +104,36 @@ def tune_gemm(ns, dtypes, log):
 
 
 def tune_planner(ns, log):
-    """{n: [spmm ops/s, gemm ops/s]} with the tuned product shapes applied."""
-    out = {}
+    """({n: [sparse step ops/s, dense product ops/s]}, {n: step form}): the
+    faster form of the sparse left step by n, and the rates the planner
+    sees (tuned product shapes applied)."""
+    out, forms = {}, {}
     last_gemm = None
     for n in ns:
         N = tp.tp_state_dim(n)
         nnz = tp.tp_state_nnz(n)
         X, Y = _padded(N, torch.uint16), _padded(N, torch.uint16)
         tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
-        csr = tp.tp_build_state_csr(n)
-        ts = _events(lambda: tp.tp_minplus_spmm(*csr, X, Y), min_ms=10.0, max_reps=20)
+        ref = tp.tp_state_left_mul(n, X, _padded(N, torch.uint16), form=tp.TP_STEP_CSR).clone()
+        ts = None
+        for form in (tp.TP_STEP_CSR, tp.TP_STEP_BLOCKED):
+            tp.tp_state_left_mul(n, X, Y, form=form)
+            if not torch.equal(Y, ref):
+                raise RuntimeError(f"sparse step n={n} form={form} differs")
+            t = _events(lambda: tp.tp_state_left_mul(n, X, Y, form=form), min_ms=10.0,
+                        max_reps=20)
+            if ts is None or t < ts * (1.0 - TIE):
+                ts, forms[n] = t, form
         if n <= 11:
             C = _padded(N, torch.uint16)
             tg = _events(lambda: tp.tp_minplus_gemm(X, X, C), min_ms=10.0, max_reps=20)
             last_gemm = N ** 3 / tg
             del C
         out[n] = [nnz * N / ts, last_gemm]
-        log(f"planner n={n}: sparse step {out[n][0] / 1e12:.3f} T/s, "
+        log(f"planner n={n}: sparse step {out[n][0] / 1e12:.3f} T/s (form {forms[n]}), "
             f"dense product {out[n][1] / 1e12:.3f} T/s")
-        del X, Y, csr
-    return out
+        del X, Y, ref
+    return out, forms
 
 
 def _batch_time(ns, ms, params, reps=3):
@@ -202,6 +214,7 @@ def main(argv=None):
     for n in range(1, 13):
         tp.tp_tune_batch(n, 0, 0)
         tp.tp_tune_planner(n, 0.0, 0.0)
+        tp.tp_tune_step(n, tp.TP_STEP_AUTO)
     if args.quick:
         gemm_ns, planner_ns, batch_ns = (4, 5), (4, 5), (4,)
         rows_list, baby_list = (8, 16), (8, 16)
@@ -217,7 +230,7 @@ def main(argv=None):
     table["gemm"].update(tune_gemm(tuple(n for n in gemm_ns if n <= 10), (tp.TP_U8,), log))
     for name, rows in table["gemm"].items():
         apply_gemm_rows(tp.TP_U16 if name == "u16" else tp.TP_U8, rows)
-    table["planner"] = tune_planner(planner_ns, log)
+    table["planner"], table["step"] = tune_planner(planner_ns, log)
     table["batch"] = tune_batch(batch_ns, rows_list, baby_list, args.seed, log)
     with open(args.out, "w") as f:
         _dump(table, f)

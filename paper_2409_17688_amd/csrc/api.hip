@@ -75,6 +75,8 @@ struct State {
   int n = 0;
   int64_t N = 0, nnz = -1;
   DevBuf masks, z, rowptr, col, colz;
+  DevBuf bptr, bent;  // blocked form of A(D_n), 16 rows per block
+  int64_t nent = 0;
   bool csr_ready = false;
 };
 
@@ -117,6 +119,18 @@ int get_state(int n, hipStream_t s, State **out) {
     TP_HIP_CHECK(launch_csr_fill(N, n, (const uint32_t *)st.masks.ptr,
                                  (const int64_t *)st.rowptr.ptr, (uint32_t *)st.col.ptr,
                                  (uint32_t *)st.colz.ptr, s));
+    const int64_t nb = block_count_host(N);
+    TP_HIP_CHECK(ensure(st.bptr, (nb + 1) * sizeof(int64_t)));
+    TP_HIP_CHECK(launch_block_count(N, n, (const uint32_t *)st.masks.ptr, (int64_t *)st.bptr.ptr, s));
+    TP_HIP_CHECK(launch_scan_rowptr(nb, (int64_t *)st.bptr.ptr, s));
+    int64_t nent = 0;
+    TP_HIP_CHECK(hipMemcpyAsync(&nent, (int64_t *)st.bptr.ptr + nb, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+    TP_HIP_CHECK(hipStreamSynchronize(s));
+    st.nent = nent;
+    TP_HIP_CHECK(ensure(st.bent, (size_t)std::max<int64_t>(nent, 1) * sizeof(uint64_t)));
+    TP_HIP_CHECK(launch_block_fill(N, n, (const uint32_t *)st.masks.ptr,
+                                   (const int64_t *)st.bptr.ptr, (uint64_t *)st.bent.ptr, s));
     st.csr_ready = true;
   }
   *out = &st;
@@ -138,6 +152,29 @@ double g_spmm_rate[13] = {0, 1e10, 1e10, 2e10, 5e10, 1e11, 5e10, 2.5e11,
                           1.4e12, 4.5e12, 1.19e13, 1.05e13, 1.12e13};
 double g_gemm_rate[13] = {0, 1e9, 1e9, 1e10, 5e10, 1e11, 3e11, 2e12,
                           1.45e13, 2.6e13, 3.37e13, 3.4e13, 3.4e13};
+// Form of the sparse left step by n when TP_STEP_AUTO is asked for (0: the
+// built-in rule, row blocks from n = 11 on, where they were measured faster:
+// at n = 12 53 ms against 101 ms per step; the CSR gather wins up to n = 10).
+// Guarded by g_mu.
+int g_step_form[13] = {0};
+
+int step_form(int n, int form) {
+  if (form != TP_STEP_AUTO) return form;
+  if (g_step_form[n] != TP_STEP_AUTO) return g_step_form[n];
+  return n >= 11 ? TP_STEP_BLOCKED : TP_STEP_CSR;
+}
+
+// Y = A(D_n) x X (u16) with the state's CSR or blocked form.  Caller holds g_mu.
+hipError_t state_step(const State *st, int form, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                      int64_t ldy, int64_t ncols, hipStream_t s) {
+  if (step_form(st->n, form) == TP_STEP_BLOCKED)
+    return launch_block_step(st->N, (const int64_t *)st->bptr.ptr,
+                             (const uint64_t *)st->bent.ptr, X, ldx, Y, ldy, ncols, s);
+  return launch_spmm(TP_U16, st->N, (const int64_t *)st->rowptr.ptr,
+                     (const uint32_t *)st->col.ptr, (const uint8_t *)st->z.ptr, X, ldx, Y, ldy,
+                     ncols, s);
+}
+
 constexpr double kHbm = 5.0e12;     // bytes / s for traces and copies
 constexpr double kLaunch = 6.0e-6;  // s per kernel launch
 
@@ -244,11 +281,8 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
   const uint32_t *masks = (const uint32_t *)st->masks.ptr;
   TP_HIP_CHECK(launch_dense_state(n, N, masks, TP_U16, X, ld, s));
   if (r == 1) TP_HIP_CHECK(hipMemcpyAsync(snap, X, mat, hipMemcpyDeviceToDevice, s));
-  const int64_t *rowptr = (const int64_t *)st->rowptr.ptr;
-  const uint32_t *col = (const uint32_t *)st->col.ptr;
-  const uint8_t *z = (const uint8_t *)st->z.ptr;
   for (int64_t k = 2; k <= c; ++k) {
-    TP_HIP_CHECK(launch_spmm(TP_U16, N, rowptr, col, z, X, ld, Y, ld, N, s));
+    TP_HIP_CHECK(state_step(st, TP_STEP_AUTO, X, ld, Y, ld, N, s));
     uint16_t *t = X;
     X = Y;
     Y = t;
@@ -300,6 +334,9 @@ int state_view(int n, hipStream_t s, StateView *out) {
   out->col = (const uint32_t *)st->col.ptr;
   out->z = (const uint8_t *)st->z.ptr;
   out->colz = (const uint32_t *)st->colz.ptr;
+  out->bptr = (const int64_t *)st->bptr.ptr;
+  out->bent = (const uint64_t *)st->bent.ptr;
+  out->nent = st->nent;
   return TP_OK;
 }
 
@@ -507,6 +544,33 @@ int tp_trace_of_product(int dtype, int64_t N, const void *d_X, int64_t ldx, cons
   return TP_OK;
 }
 
+int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, int64_t ldy,
+                      int64_t ncols, hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
+  TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED,
+             "form %d is not TP_STEP_AUTO, TP_STEP_CSR or TP_STEP_BLOCKED", form);
+  TP_REQUIRE(ncols >= 0, "negative size");
+  TP_REQUIRE(ldx >= (ncols > 0 ? ncols : 1) && ldy >= (ncols > 0 ? ncols : 1),
+             "leading dimension < ncols");
+  TP_REQUIRE(ncols == 0 || (d_X != nullptr && d_Y != nullptr), "X or Y is NULL");
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  const int rc = get_state(n, stream, &st);
+  if (rc != TP_OK) return rc;
+  TP_HIP_CHECK(state_step(st, form, (const uint16_t *)d_X, ldx, (uint16_t *)d_Y, ldy, ncols,
+                          stream));
+  return TP_OK;
+}
+
+int tp_tune_step(int n, int form) {
+  TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
+  TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED,
+             "form %d is not TP_STEP_AUTO, TP_STEP_CSR or TP_STEP_BLOCKED", form);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_step_form[n] = form;
+  return TP_OK;
+}
+
 int tp_sparse_trace_of_product(int dtype, int64_t N, const int64_t *d_rowptr,
                                const uint32_t *d_col, const uint8_t *d_z, const void *d_X,
                                int64_t ldx, int32_t *d_out, hipStream_t stream) {
@@ -539,6 +603,8 @@ int tp_release_cache(void) {
     release(kv.second.rowptr);
     release(kv.second.col);
     release(kv.second.colz);
+    release(kv.second.bptr);
+    release(kv.second.bent);
   }
   g_states.clear();
   for (auto &kv : g_ws) {

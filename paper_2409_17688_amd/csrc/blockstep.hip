@@ -1,0 +1,230 @@
+// The sparse left step Y = A(D_n) x X in row blocks.
+//
+// Row q of the product is a gather: Y[q][j] = min over successors p of q of
+// (z_p + X[p][j]) (the arc label z_p, the number of zeros of word p, depends
+// on the successor only; Section 2.2).  Consecutive words differ only in
+// their last letters, so consecutive rows share most successors: over 16
+// consecutive rows of A(D_n), n = 8..10, the union of the successor lists is
+// about a quarter of their total length.  This kernel walks that union once
+// per block of 16 rows, so each gathered row of X is read once per block
+// instead of once per row, and applies it to the rows of the block that have
+// it as a successor (a 16-bit mask per entry).
+//
+// The blocked form of A(D_n): for block b (rows 16b .. 16b+15), entries
+// bptr[b] .. bptr[b+1]-1, each a 64-bit word
+//   bits  0..23  successor p        (N < 2^24 for n <= 12)
+//   bits 24..31  its label z_p
+//   bits 32..47  mask: bit r set when p is a successor of row 16b + r
+// in increasing p.  It is built from the word masks with the same "can
+// follow" test as the CSR (two passes: count, then fill after a scan).
+//
+// Launch shape of the step: one wave per (block, 512-column panel); lanes own
+// 8 consecutive columns; the 16 rows' accumulators live in registers (64
+// packed registers); entries are read with scalar loads (they are uniform in
+// the wave) and the per-row updates are skipped by uniform branches on the
+// mask, so the arithmetic is that of the plain gather.  Workgroups are
+// numbered so each XCD takes a contiguous range of blocks of one panel.
+#include "device_core.hpp"
+
+namespace tp {
+
+namespace {
+
+constexpr int kRows = 16;  // rows per block
+
+typedef const __attribute__((address_space(4))) int64_t *kconst_i64;
+typedef const __attribute__((address_space(4))) uint64_t *kconst_u64;
+
+// One wave per block: number of distinct successors of its rows.
+__global__ void block_count_kernel(int64_t N, uint32_t full, const uint32_t *__restrict__ masks,
+                                   int64_t *__restrict__ bptr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (b >= nblocks) return;
+  uint32_t mq[kRows];
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    mq[r] = q < N ? masks[q] : 0u;
+  }
+  const int rows = (int)std::min<int64_t>(kRows, N - b * kRows);
+  int64_t cnt = 0;
+  for (int64_t p0 = 0; p0 < N; p0 += 64) {
+    const int64_t p = p0 + lane;
+    bool arc = false;
+    if (p < N) {
+      const uint32_t mp = masks[p];
+      for (int r = 0; r < rows && !arc; ++r) arc = can_follow(mq[r], mp, full);
+    }
+    cnt += __popcll(__ballot(arc));
+  }
+  if (lane == 0) {
+    bptr[b + 1] = cnt;
+    if (b == 0) bptr[0] = 0;
+  }
+}
+
+// One wave per block: its entries in increasing p.
+__global__ void block_fill_kernel(int64_t N, uint32_t full, const uint32_t *__restrict__ masks,
+                                  const int64_t *__restrict__ bptr, uint64_t *__restrict__ ent) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (b >= nblocks) return;
+  uint32_t mq[kRows];
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    mq[r] = q < N ? masks[q] : 0u;
+  }
+  const int rows = (int)std::min<int64_t>(kRows, N - b * kRows);
+  int64_t pos = bptr[b];
+  for (int64_t p0 = 0; p0 < N; p0 += 64) {
+    const int64_t p = p0 + lane;
+    uint32_t m = 0, mp = 0;
+    if (p < N) {
+      mp = masks[p];
+      for (int r = 0; r < rows; ++r) m |= (uint32_t)can_follow(mq[r], mp, full) << r;
+    }
+    const uint64_t bal = __ballot(m != 0);
+    if (m != 0) {
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      const uint32_t z = (uint32_t)__builtin_popcount(mp & 0xFFFFu);
+      ent[pos + below] = ((uint64_t)m << 32) | ((uint64_t)z << 24) | (uint64_t)p;
+    }
+    pos += __popcll(bal);
+  }
+}
+
+// acc[r] = min(acc[r], lab + v) for the rows r whose bit is set in m (m is
+// wave-uniform: the skipped rows cost a scalar test and branch only).
+__device__ __forceinline__ void apply_entry(u16x2 (&acc)[kRows][4], uint32_t m, u16x2 lab,
+                                            const u16x2 (&v)[4]) {
+  u16x2 s[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = pk_add_sat(lab, v[k]);
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    if (m & (1u << r)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[r][k] = pk_min(acc[r][k], s[k]);
+    }
+  }
+}
+
+// 16-bit entries only (the power chains run in u16).
+template <bool VEC, int U>
+__global__ void __launch_bounds__(256) block_step_kernel(int64_t N, const int64_t *__restrict__ bptr,
+                                                         const uint64_t *__restrict__ ent,
+                                                         const uint16_t *__restrict__ X,
+                                                         int64_t ldx, uint16_t *__restrict__ Y,
+                                                         int64_t ldy, int64_t ncols) {
+  using T = uint16_t;
+  constexpr int VE = 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t groups = (nblocks + 3) / 4;
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t panel = t / groups;
+  const int64_t b = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (b >= nblocks) return;
+  const int64_t c0 = (panel * 64 + lane) * VE;
+  const kconst_i64 bp = (kconst_i64)bptr;
+  const kconst_u64 en = (kconst_u64)ent;
+
+  u16x2 acc[kRows][4];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[r][k] = splat(0xFFFFu);
+
+  const int64_t e0 = bp[b], e1 = bp[b + 1];
+  int64_t i = e0;
+  for (; i + U <= e1; i += U) {
+    uint64_t w[U];
+    u16x2 v[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      w[u] = en[i + u];
+      load_row_chunk<T, VEC>(X, ldx, (int64_t)(uint32_t)(w[u] & 0xFFFFFFu), c0, ncols, v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      apply_entry(acc, (uint32_t)(w[u] >> 32), splat((uint16_t)((w[u] >> 24) & 0xFFu)), v[u]);
+  }
+  for (; i < e1; ++i) {
+    const uint64_t w = en[i];
+    u16x2 v[4];
+    load_row_chunk<T, VEC>(X, ldx, (int64_t)(uint32_t)(w & 0xFFFFFFu), c0, ncols, v);
+    apply_entry(acc, (uint32_t)(w >> 32), splat((uint16_t)((w >> 24) & 0xFFu)), v);
+  }
+  if (c0 >= ncols) return;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    if (q >= N) break;
+    T *yrow = Y + q * ldy + c0;
+    const u16x2 *a = acc[r];
+    if (VEC && c0 + VE <= ncols) {
+      *reinterpret_cast<uint4 *>(yrow) = uint4{as_u32(a[0]), as_u32(a[1]), as_u32(a[2]),
+                                               as_u32(a[3])};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (c0 + 2 * k < ncols) yrow[2 * k] = (T)a[k].x;
+        if (c0 + 2 * k + 1 < ncols) yrow[2 * k + 1] = (T)a[k].y;
+      }
+    }
+  }
+}
+
+hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t *ent,
+                                 const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
+                                 int64_t ncols, hipStream_t s) {
+  constexpr int VE = 8;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t panels = (ncols + 64 * VE - 1) / (64 * VE);
+  const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
+  const bool vec = (ldx % VE == 0) && (ldy % VE == 0) && ((uintptr_t)X % 16 == 0) &&
+                   ((uintptr_t)Y % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((block_step_kernel<true, 4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
+                       Y, ldy, ncols);
+  else
+    hipLaunchKernelGGL((block_step_kernel<false, 4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
+                       Y, ldy, ncols);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t block_count_host(int64_t N) { return (N + kRows - 1) / kRows; }
+
+hipError_t launch_block_count(int64_t N, int n, const uint32_t *masks, int64_t *bptr,
+                              hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  const uint32_t full = (1u << n) - 1u;
+  const int64_t nb = block_count_host(N);
+  hipLaunchKernelGGL(block_count_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, N, full,
+                     masks, bptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int64_t *bptr,
+                             uint64_t *ent, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  const uint32_t full = (1u << n) - 1u;
+  const int64_t nb = block_count_host(N);
+  hipLaunchKernelGGL(block_fill_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, N, full,
+                     masks, bptr, ent);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
+                             const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
+                             int64_t ncols, hipStream_t s) {
+  if (N == 0 || ncols == 0) return hipSuccess;
+  return launch_block_step_u16(N, bptr, ent, X, ldx, Y, ldy, ncols, s);
+}
+
+}  // namespace tp

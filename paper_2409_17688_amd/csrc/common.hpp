@@ -102,6 +102,10 @@ struct StateView {
   const uint32_t *col;
   const uint8_t *z;
   const uint32_t *colz;  // col with z of each successor in the top byte
+  // blocked form (16 rows per block): entries bptr[b] .. bptr[b+1]-1 of ent
+  const int64_t *bptr;
+  const uint64_t *bent;
+  int64_t nent;
 };
 int state_view(int n, hipStream_t s, StateView *out);
 
@@ -115,6 +119,16 @@ hipError_t launch_csr_count(int64_t N, int n, const uint32_t *masks, int64_t *ro
 hipError_t launch_scan_rowptr(int64_t N, int64_t *rowptr, hipStream_t s);
 hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_t *rowptr,
                            uint32_t *col, uint32_t *colz, hipStream_t s);
+
+// blockstep.hip: the sparse left step over blocks of 16 rows
+int64_t block_count_host(int64_t N);
+hipError_t launch_block_count(int64_t N, int n, const uint32_t *masks, int64_t *bptr,
+                              hipStream_t s);
+hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int64_t *bptr,
+                             uint64_t *ent, hipStream_t s);
+hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
+                             const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
+                             int64_t ncols, hipStream_t s);
 
 // gemm.hip
 hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,

@@ -131,7 +131,7 @@ class SweepLane:
         with torch.cuda.stream(self.stream):
             self.bufs = [torch.empty((self.N, ld), dtype=torch.uint16, device="cuda")[:, :self.N]
                          for _ in range(3)]
-            self.csr = tp.tp_build_state_csr(n, stream=self.stream)
+        tp.tp_state_nnz(n)  # builds (and caches) the state's sparse forms
         self.lock = threading.Condition()
         self.pending = collections.defaultdict(list)  # level a -> requests
         self.stop = False
@@ -196,7 +196,7 @@ class SweepLane:
                         if not ahead:
                             break
                         Y = self.bufs[(k + 1) % 3]
-                        tp.tp_minplus_spmm(*self.csr, X[k], Y, stream=self.stream)
+                        tp.tp_state_left_mul(self.n, X[k], Y, stream=self.stream)
                         k += 1
                         self.levels += 1
                         X[k] = Y

@@ -35,6 +35,8 @@ def apply_tuning(path: str | None = None, table: dict | None = None) -> bool:
         apply_gemm_rows(tp.TP_U16 if name == "u16" else tp.TP_U8, rows)
     for n, (spmm, gemm) in table.get("planner", {}).items():
         tp.tp_tune_planner(int(n), float(spmm), float(gemm))
+    for n, form in table.get("step", {}).items():
+        tp.tp_tune_step(int(n), int(form))
     for n, vals in table.get("batch", {}).items():
         tp.tp_tune_batch(int(n), int(vals[0]), int(vals[1]))
     return True

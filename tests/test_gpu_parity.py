@@ -251,6 +251,68 @@ def test_spmm_chain_gives_powers(tp, oracle_mod):
         assert np.array_equal(host(X).astype(np.int32), oracle_mod.power(n, 6))
 
 
+def test_state_left_mul_matches_oracle(tp, oracle_mod):
+    # the blocked sparse step: every n up to 9, ragged column counts (partial
+    # lanes, partial panels), padded and unpadded leading dimensions, a last
+    # block with fewer than 16 rows (N mod 16 != 0 for most n)
+    import torch
+    for n in range(1, 10):
+        A = oracle_mod.state_matrix(n)
+        N = A.shape[0]
+        for ncols in (1, 9, 64, 513, N):
+            for dist in [(0, 24, 0.3), (0, 30000, 0.6), (65000, 65534, 0.0)]:
+                lo, hi, frac = dist
+                X = synth.stress_matrix(N, ncols, n * 1000 + ncols, lo, hi, frac, np.uint16)
+                ref = oracle_mod.minplus(A, X.astype(np.int32))
+                say("state_left_mul", n, ncols, dist)
+                for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_CSR, tp.TP_STEP_AUTO):
+                    got = host(tp.tp_state_left_mul(n, dev(X), form=form)).astype(np.int32)
+                    assert np.array_equal(got, ref), (n, ncols, dist, form)
+                # padded rows (16-byte aligned) and a Y view inside a larger buffer
+                ld = (ncols + 63) // 64 * 64 + 64
+                Xp = torch.zeros((N, ld), dtype=torch.uint16, device="cuda")
+                Xp[:, :ncols] = dev(X)
+                Yp = torch.full((N, ld), 7, dtype=torch.uint16, device="cuda")
+                tp.tp_state_left_mul(n, Xp[:, :ncols], Yp[:, :ncols], form=tp.TP_STEP_BLOCKED)
+                got = host(Yp).astype(np.int32)
+                assert np.array_equal(got[:, :ncols], ref), (n, ncols, dist, "padded")
+                assert (got[:, ncols:] == 7).all(), "wrote outside Y"
+
+
+def test_state_left_mul_large_n_sampled(tp, oracle_mod):
+    # n = 10 against the oracle on sampled rows; n = 11, 12 against the CSR
+    # sparse step (itself checked against the oracle above) on a column block
+    rng = np.random.default_rng(5)
+    A10 = oracle_mod.state_matrix(10)
+    N = A10.shape[0]
+    X = synth.stress_matrix(N, 300, 10, 0, 30000, 0.3, np.uint16)
+    rows = np.sort(rng.choice(N, 64, replace=False))
+    ref = oracle_mod.minplus(A10[rows], X.astype(np.int32))
+    for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_CSR):
+        got = host(tp.tp_state_left_mul(10, dev(X), form=form)).astype(np.int32)
+        assert np.array_equal(got[rows], ref), form
+    for n in (11, 12):
+        N = tp.tp_state_dim(n)
+        X = dev(synth.stress_matrix(N, 520, n, 0, 30000, 0.3, np.uint16))
+        say("state_left_mul vs CSR step", n)
+        a = host(tp.tp_state_left_mul(n, X, form=tp.TP_STEP_BLOCKED))
+        b = host(tp.tp_minplus_spmm(*tp.tp_build_state_csr(n), X))
+        assert np.array_equal(a, b), n
+
+
+def test_state_left_mul_rejects_bad_arguments(tp):
+    import torch
+    X = torch.zeros((36, 5), dtype=torch.uint16, device="cuda")
+    with pytest.raises(ValueError):
+        tp.tp_state_left_mul(4, X[:35])
+    with pytest.raises(TypeError):
+        tp.tp_state_left_mul(4, X.to(torch.uint8))
+    p = X.data_ptr()
+    assert tp.lib.tp_state_left_mul(13, 0, p, 5, p, 5, 5, None) == tp.TP_EINVAL
+    assert tp.lib.tp_state_left_mul(4, 0, p, 4, p, 5, 5, None) == tp.TP_EINVAL
+    assert tp.lib.tp_state_left_mul(4, 3, p, 5, p, 5, 5, None) == tp.TP_EINVAL
+
+
 # ----------------------------------------------------------------- traces --
 
 @pytest.mark.parametrize("dtype", [2, 1])

@@ -50,6 +50,7 @@ def _reset_tables(tp):
     for n in range(1, 13):
         tp.tp_tune_batch(n, 0, 0)
         tp.tp_tune_planner(n, 0.0, 0.0)
+        tp.tp_tune_step(n, tp.TP_STEP_AUTO)
     tp.apply_tuning()
 
 
@@ -152,6 +153,7 @@ def test_tuned_defaults_do_not_change_results(tp, oracle_mod):
         for n in range(4, 9):
             tp.tp_tune_planner(n, 1e9, 1e14)  # dense products look cheap: more of them
             tp.tp_tune_batch(n, 4, 5)
+            tp.tp_tune_step(n, tp.TP_STEP_BLOCKED if n % 2 else tp.TP_STEP_CSR)
         A = synth.stress_matrix(300, 900, 21, 0, 1000, 0.4, np.uint16)
         B = synth.stress_matrix(900, 200, 22, 0, 1000, 0.4, np.uint16)
         got = host(tp.tp_minplus_gemm(dev(A), dev(B))).astype(np.int32)
