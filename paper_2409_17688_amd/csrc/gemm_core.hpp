@@ -197,8 +197,15 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const u16x2 av = splat((i & 1) ? a_cur[i >> 1].y : a_cur[i >> 1].x);
+        // all adds of the row first, then the mins: an add whose a_ik comes
+        // from the high half (op_sel) followed at once by the min reading its
+        // result costs a hazard wait state on gfx950; grouped, the results
+        // are consumed TN/2 instructions later and no waits are inserted
+        u16x2 sum[TN2];
 #pragma unroll
-        for (int j = 0; j < TN2; ++j) acc[i][j] = pk_min(acc[i][j], pk_add_sat(av, b_cur[j]));
+        for (int j = 0; j < TN2; ++j) sum[j] = pk_add_sat(av, b_cur[j]);
+#pragma unroll
+        for (int j = 0; j < TN2; ++j) acc[i][j] = pk_min(acc[i][j], sum[j]);
       }
       if (k + 1 < BK) {
 #pragma unroll
