@@ -147,11 +147,10 @@ int tp_gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int 
  * both 0 to restore the built-in rates. */
 int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s);
 
-/* Library-wide defaults of the batch engine at path order n (1..12): rows
- * per sparse task (rounded up to a multiple of 4) and baby steps c; 0 keeps
- * the built-in rule.  A context's tp_ctx_set_param values take precedence;
- * baby steps already fixed in a context do not change. */
-int tp_tune_batch(int n, int spmm_rows, int baby_steps);
+/* Library-wide default of the batch engine's baby steps c at path order n
+ * (1..12); 0 keeps the built-in rule.  A context's TP_PARAM_BABY_STEPS takes
+ * precedence; baby steps already fixed in a context do not change. */
+int tp_tune_batch(int n, int baby_steps);
 
 /* Matrix-vector products with the M x K matrix A:
  *   trans == 0:  y (M)  = A x x (x has K entries),  y_i = min_k a_ik + x_k
@@ -228,7 +227,7 @@ int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t 
 int tp_release_cache(void);
 
 /* ------------------------------------------------------------------------ */
-/* Batching: many (n, m) instances in one persistent launch.                  */
+/* Batching: many (n, m) instances per call, one persistent launch each.     */
 /* ------------------------------------------------------------------------ */
 
 /* A context keeps powers of A = A(D_n) resident in device memory (u16, rows
@@ -245,7 +244,6 @@ int tp_ctx_destroy(void *ctx);
 /* Tuning and test parameters of a context. */
 #define TP_PARAM_WAIT_LIMIT_US 1 /* bound on one dependency wait (default 20 s) */
 #define TP_PARAM_GRID 2          /* workgroups of the persistent kernel (>= 8); 0 = fill the chip */
-#define TP_PARAM_SPMM_ROWS 16    /* TP_PARAM_SPMM_ROWS + n: rows per chain task; 0 = auto */
 #define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
                                     n >= 8, else 32); fixed once powers of n are resident */
 int tp_ctx_set_param(void *ctx, int param, int64_t value);
@@ -263,10 +261,11 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
 
 /* gamma2_dev[j] (device int32) = gamma_2(P_{n[j]} x C_{m[j]}) for j < count,
  * with n (host int32) in 1..12 and m (host int64) >= 3, n*m < 65535.  Queues
- * the missing powers of every distinct n (first power, chain levels, giant
- * products) and one trace per instance as one dependency-ordered task queue,
- * run by one persistent kernel launch from a captured hipGraph on `stream`;
- * returns without waiting.
+ * the missing chain levels of every distinct n (A^1 and the sparse left
+ * steps, one context-owned stream per n, ordered after the work already on
+ * `stream`), then, on `stream`, the missing giant products and one trace per
+ * instance as one dependency-ordered task list run by one persistent kernel
+ * launch from a captured hipGraph; returns without waiting.
  * TP_ENOMEM when the needed powers exceed the context's budget (nothing is
  * queued).  Results of a batch are valid after tp_ctx_check returns TP_OK. */
 int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,

@@ -12,8 +12,8 @@ What it tunes (none of it changes a result, only which kernel shape runs):
   * the schedule planner of ``tp_tropical_power_trace``: measured (min,+)
     rates of that step and of the tuned dense product per n
     (``tp_tune_planner``);
-  * the batch engine, n = 4..9: rows per sparse task and baby steps c, on a
-    batch of 12 instances with m uniform in 3..200 (``tp_tune_batch``).
+  * the batch engine, n = 4..9: baby steps c, on a batch of 12 instances
+    with m uniform in 3..200 (``tp_tune_batch``).
 
 Every candidate is checked against the reference shape (tile configuration
 0 without a split for products, the built-in batch parameters for batches):
@@ -155,8 +155,8 @@ def _batch_time(ns, ms, params, reps=3):
     return best, res
 
 
-def tune_batch(ns, rows_list, baby_list, seed, log):
-    """{n: [rows, baby steps, seconds]}: fastest cold batch of 12 instances."""
+def tune_batch(ns, baby_list, seed, log):
+    """{n: [baby steps, seconds]}: fastest cold batch of 12 instances."""
     rng = np.random.default_rng(seed)
     out = {}
     # load the batch kernel once so that the first candidate is not charged for it
@@ -167,15 +167,13 @@ def tune_batch(ns, rows_list, baby_list, seed, log):
         tp.tp_tropical_power_trace(n, 3)  # state in the cache
         _, ref = _batch_time(nl, ms, {}, reps=1)
         best = None
-        for rows in rows_list:
-            for c in baby_list:
-                t, res = _batch_time(nl, ms, {tp.TP_PARAM_SPMM_ROWS + n: rows,
-                                              tp.TP_PARAM_BABY_STEPS + n: c})
-                if res != ref:
-                    raise RuntimeError(f"batch n={n} rows={rows} c={c} differs")
-                if best is None or t < best[2] * (1.0 - TIE):
-                    best = [rows, c, t]
-        log(f"batch n={n}: rows {best[0]} baby steps {best[1]} {best[2] * 1e3:.2f} ms")
+        for c in baby_list:
+            t, res = _batch_time(nl, ms, {tp.TP_PARAM_BABY_STEPS + n: c})
+            if res != ref:
+                raise RuntimeError(f"batch n={n} c={c} differs")
+            if best is None or t < best[1] * (1.0 - TIE):
+                best = [c, t]
+        log(f"batch n={n}: baby steps {best[0]} {best[1] * 1e3:.2f} ms")
         out[n] = best
     return out
 
@@ -212,15 +210,15 @@ def main(argv=None):
     for dt in (tp.TP_U16, tp.TP_U8):
         tp.tp_tune_gemm(dt, -1)
     for n in range(1, 13):
-        tp.tp_tune_batch(n, 0, 0)
+        tp.tp_tune_batch(n, 0)
         tp.tp_tune_planner(n, 0.0, 0.0)
         tp.tp_tune_step(n, tp.TP_STEP_AUTO)
     if args.quick:
         gemm_ns, planner_ns, batch_ns = (4, 5), (4, 5), (4,)
-        rows_list, baby_list = (8, 16), (8, 16)
+        baby_list = (8, 16)
     else:
         gemm_ns, planner_ns, batch_ns = tuple(range(4, 12)), tuple(range(1, 13)), tuple(range(4, 10))
-        rows_list, baby_list = (8, 16, 32, 48, 64), (4, 6, 8, 12, 16, 24, 32, 48)
+        baby_list = (4, 6, 8, 12, 16, 24, 32, 48, 64)
     table = {"arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
              "device": torch.cuda.get_device_name(0),
              "date": time.strftime("%Y-%m-%d"),
@@ -231,7 +229,7 @@ def main(argv=None):
     for name, rows in table["gemm"].items():
         apply_gemm_rows(tp.TP_U16 if name == "u16" else tp.TP_U8, rows)
     table["planner"], table["step"] = tune_planner(planner_ns, log)
-    table["batch"] = tune_batch(batch_ns, rows_list, baby_list, args.seed, log)
+    table["batch"] = tune_batch(batch_ns, baby_list, args.seed, log)
     with open(args.out, "w") as f:
         _dump(table, f)
     log(f"wrote {args.out}")

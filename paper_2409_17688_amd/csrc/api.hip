@@ -170,6 +170,9 @@ hipError_t state_step(const State *st, int form, const uint16_t *X, int64_t ldx,
   if (step_form(st->n, form) == TP_STEP_BLOCKED)
     return launch_block_step(st->N, (const int64_t *)st->bptr.ptr,
                              (const uint64_t *)st->bent.ptr, X, ldx, Y, ldy, ncols, s);
+  if (state_gather_fits(X, ldx, Y, ldy, ncols))
+    return launch_state_gather(st->N, (const int64_t *)st->rowptr.ptr,
+                               (const uint32_t *)st->colz.ptr, X, ldx, Y, ldy, ncols, s);
   return launch_spmm(TP_U16, st->N, (const int64_t *)st->rowptr.ptr,
                      (const uint32_t *)st->col.ptr, (const uint8_t *)st->z.ptr, X, ldx, Y, ldy,
                      ncols, s);
@@ -320,6 +323,20 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                           int64_t ldy, int64_t ncols, hipStream_t s) {
+  int form;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    form = step_form(v.n, TP_STEP_AUTO);
+  }
+  if (form == TP_STEP_BLOCKED)
+    return launch_block_step(v.N, v.bptr, v.bent, X, ldx, Y, ldy, ncols, s);
+  if (state_gather_fits(X, ldx, Y, ldy, ncols))
+    return launch_state_gather(v.N, v.rowptr, v.colz, X, ldx, Y, ldy, ncols, s);
+  return launch_spmm(TP_U16, v.N, v.rowptr, v.col, v.z, X, ldx, Y, ldy, ncols, s);
+}
 
 int state_view(int n, hipStream_t s, StateView *out) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -16,35 +16,35 @@
 // (jc, r).  Memory per n is (c + m_max/c) powers instead of m_max/2, and the
 // number of sequential chain levels is c instead of m_max/2.
 //
-// The work of a batch is a list of tasks in dependency order:
-//   BUILD  rows of A^1 = A(D_n)
-//   SPMM   rows x one 512-column panel of A^k = A x A^(k-1)
-//   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
-//   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
-//          instance's result with an atomic min
-// Dependencies are as narrow as the arithmetic allows, each a completion
-// counter and a target count:
-//   * column panel P of A x X needs column panel P of X only, so a chain
-//     level waits for the same panel of the level before (per-panel
-//     counters); each panel's whole chain is dealt to one queue, so its XCD
-//     keeps that panel of X in its L2 from level to level;
-//   * a product tile (rows R, columns C) and a trace block (rows I) read
-//     rows R (I) of the left factor and columns C (I) of the right one, so
-//     a giant counts its finished tiles per 128-row and per 128-column block;
-//   * everything else waits for a whole power.
+// A batch runs in two parts on the caller's stream:
+//   1. the chain levels A^1 .. A^c of every path order that lacks them, as
+//      plain launches of the library's sparse left step on one stream per n
+//      (the steps of one n are sequential; different n run side by side);
+//      a chain level fills the chip on its own, which a share of a persistent
+//      kernel does not (each level depends on the whole level before it);
+//   2. one persistent kernel for the dense products and the traces, over a
+//      list of tasks in dependency order:
+//        GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
+//        TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
+//               instance's result with an atomic min
+//      A product tile (rows R, columns C) and a trace block (rows I) read rows
+//      R (I) of the left factor and columns C (I) of the right one, so a giant
+//      counts its finished tiles per 128-row and per 128-column block and a
+//      task waits (on at most two counters) for the blocks it reads only;
+//      chain powers are complete before the kernel starts.
 // The list is split into 8 queues, one per XCD, each keeping the list's
-// order; giants and traces go to the queues in contiguous chunks.  A
-// persistent kernel pops tasks with one atomic counter per queue, its own
-// XCD's queue first and the others when that one is empty.  Every
-// dependency points to an earlier task of the list and a queue is only left
-// when empty, so the earliest unfinished task is always popped by a running
-// workgroup and every wait ends; as a safety net each wait is bounded in
-// time, and a timed-out wait sets an abort flag that makes every workgroup
-// drain the queues without work.  A finished task publishes its rows with
-// an agent-scope release (so the L2s of other XCDs see them) and counter
-// increments; a workgroup acquires once per dependency it starts waiting on.
-// The launch (counter reset, result reset, persistent kernel) is captured
-// once in a hipGraph and replayed for every batch.
+// order; a giant's tiles and an instance's trace blocks go to the queues in
+// contiguous chunks.  Workgroups pop their own XCD's queue first (one atomic
+// head per queue) and the others when it is empty.  Every dependency points
+// to an earlier task of the list and a queue is only left when empty, so the
+// earliest unfinished task is always held by a running workgroup and every
+// wait ends; as a safety net each wait is bounded in time, and a timed-out
+// wait sets an abort flag that makes every workgroup drain the queues
+// without work.  A finished task publishes its rows with an agent-scope
+// release (so the L2s of other XCDs see them) and counter increments; a
+// workgroup acquires once per dependency it starts waiting on.  The kernel
+// launch (counter reset, result reset, persistent kernel) is captured once
+// in a hipGraph and replayed for every batch.
 #include <string.h>
 
 #include <algorithm>
@@ -60,7 +60,7 @@ namespace tp {
 
 namespace {
 
-enum : int32_t { kBuild = 0, kSpmm = 1, kGemm = 2, kTrace = 3 };
+enum : int32_t { kGemm = 2, kTrace = 3 };
 
 struct Task {
   int32_t type, slot;
@@ -76,11 +76,6 @@ struct Task {
 struct Slot {
   int32_t n, N;
   int64_t ld;
-  uint32_t full;
-  int32_t pad;
-  const uint32_t *masks;
-  const int64_t *rowptr;
-  const uint32_t *colz;     // successors with their labels in the top byte
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
@@ -97,70 +92,7 @@ struct Control {
 
 constexpr int kMaxSlots = 16;
 constexpr uint16_t kInf = 0xFFFFu;
-constexpr int kPanel = 512;                       // columns of an SPMM task: 64 lanes x 8
 constexpr int kGBM = 128, kGBN = 128, kGBK = 32;  // dense product tile
-
-// The CSR is read-only for the whole launch: through constant-space views a
-// wave-uniform index into it becomes a scalar load.
-typedef const __attribute__((address_space(4))) int64_t *kconst_i64;
-typedef const __attribute__((address_space(4))) uint32_t *kconst_u32;
-
-// Row q (wave-uniform) of A^k = A x A^(k-1) over the 8 columns c0 .. c0 + 7
-// of this lane: Y[q][c] = min over successors p of z_p + X[p][c].  The loads
-// read all 8 entries even past N (rows are padded to a multiple of 64); only
-// columns < N are stored.  U successors are gathered per round.
-template <int U>
-__device__ __forceinline__ void batch_spmm_row(kconst_i64 rowptr, kconst_u32 colz,
-                                               const uint16_t *X, uint16_t *Y, int64_t ld,
-                                               int64_t N, int64_t q, int64_t c0) {
-  const int64_t b = rowptr[q], e = rowptr[q + 1];
-  // row p of X starts at uint4 p * ld / 8 (uniform); this lane's 8 columns
-  // are uint4 c0 / 8 of the row (ld and c0 are multiples of 8)
-  const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
-  const int64_t ld4 = ld / 8;
-  const uint32_t off = (uint32_t)(c0 / 8);
-  u16x2 acc[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = splat(kInf);
-  int64_t i = b;
-  for (; i + U <= e; i += U) {
-    u32x4 v[U];
-    uint32_t pz[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      pz[u] = colz[i + u];
-      v[u] = Xg[(int64_t)(pz[u] & 0xFFFFFFu) * ld4 + off];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const u16x2 lab = splat((uint16_t)(pz[u] >> 24));
-      acc[0] = pk_min(acc[0], pk_add_sat(lab, as_pk(v[u].x)));
-      acc[1] = pk_min(acc[1], pk_add_sat(lab, as_pk(v[u].y)));
-      acc[2] = pk_min(acc[2], pk_add_sat(lab, as_pk(v[u].z)));
-      acc[3] = pk_min(acc[3], pk_add_sat(lab, as_pk(v[u].w)));
-    }
-  }
-  for (; i < e; ++i) {
-    const uint32_t pz = colz[i];
-    const u32x4 v = Xg[(int64_t)(pz & 0xFFFFFFu) * ld4 + off];
-    const u16x2 lab = splat((uint16_t)(pz >> 24));
-    acc[0] = pk_min(acc[0], pk_add_sat(lab, as_pk(v.x)));
-    acc[1] = pk_min(acc[1], pk_add_sat(lab, as_pk(v.y)));
-    acc[2] = pk_min(acc[2], pk_add_sat(lab, as_pk(v.z)));
-    acc[3] = pk_min(acc[3], pk_add_sat(lab, as_pk(v.w)));
-  }
-  if (c0 + 8 <= N) {
-    *(gmut<u32x4>)(to_global_mut(Y) + q * ld + c0) =
-        u32x4{as_u32(acc[0]), as_u32(acc[1]), as_u32(acc[2]), as_u32(acc[3])};
-  } else {
-    const gmut<uint16_t> y = to_global_mut(Y) + q * ld + c0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (c0 + 2 * r < N) y[2 * r] = acc[r].x;
-      if (c0 + 2 * r + 1 < N) y[2 * r + 1] = acc[r].y;
-    }
-  }
-}
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -196,7 +128,6 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
   __shared__ int32_t s_task, s_go, s_fresh;
   int acq_dep = -1, acq_dep2 = -1;  // dependencies this workgroup has acquired (thread 0)
   const int64_t limit = ctl->wait_limit;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // the hardware deals workgroups to the XCDs in turn, so workgroup b runs on
   // XCD b mod 8 and serves that queue first; when it is empty it takes tasks
   // from the others, always in each queue's own order
@@ -237,22 +168,14 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
       if (s_fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const Slot sl = slots[task.slot];
       const int64_t N = sl.N, ld = sl.ld;
-      if (task.type == kSpmm) {
-        const uint16_t *X = sl.powers[task.x];
-        uint16_t *Y = sl.powers[task.out];
-        for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
-          const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
-          for (int64_t c0 = task.c0 + (int64_t)lane * 8; c0 < task.c1; c0 += kPanel)
-            batch_spmm_row<16>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, X, Y, ld, N, qu, c0);
-        }
-      } else if (task.type == kGemm) {
+      if (task.type == kGemm) {
         gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
             (int)N, (int)N, (int)N, sl.powers[task.x], ld,
             sl.powers[task.y], ld, sl.powers[task.out], ld, 0, task.row0,
             task.c0,
             reinterpret_cast<uint16_t(*)[kGBK][kGBM]>(lds),
             reinterpret_cast<uint16_t(*)[kGBK][kGBN]>(lds + 2 * kGBK * kGBM));
-      } else if (task.type == kTrace) {
+      } else {
         u16x2 acc[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = splat(kInf);
@@ -262,16 +185,6 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
                                      k0, lds, acc);
         const int32_t best = block_min(acc, part);
         if (threadIdx.x == 0 && best < (int32_t)kInf) atomicMin(&results[task.inst], best);
-      } else {
-        uint16_t *out = sl.powers[1];
-        const int64_t rows = task.row1 - task.row0;
-        for (int64_t idx = threadIdx.x; idx < rows * N; idx += blockDim.x) {
-          const int64_t q = task.row0 + idx / N, p = idx - (idx / N) * N;
-          const uint32_t mp = sl.masks[p];
-          out[q * ld + p] = can_follow(sl.masks[q], mp, sl.full)
-                                ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
-                                : kInf;
-        }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
@@ -342,8 +255,10 @@ struct Ctx {
   size_t g_counter_cap = 0, g_result_cap = 0;
   int g_grid = 0;
   hipEvent_t staged = nullptr;
+  // chain levels run on one stream per slot, between two events on the caller's stream
+  hipStream_t chain_stream[16] = {nullptr};
+  hipEvent_t chain_start = nullptr, chain_done[16] = {nullptr};
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
-  int spmm_rows[16] = {0};          // rows per SPMM task by n; 0 = automatic
   int baby[16] = {0};               // baby steps by n; 0 = automatic
   int grid_override = 0;
   bool pending = false;                      // a batch was queued and not yet checked
@@ -353,27 +268,12 @@ struct Ctx {
 
 namespace {
 
-// Library-wide defaults by n from the autotuner (0: none); a context's own
-// parameters take precedence.
+// Library-wide baby steps by n from the autotuner (0: none); a context's
+// own parameter takes precedence.
 std::mutex g_tune_mu;
-int g_tuned_rows[16] = {0};
 int g_tuned_baby[16] = {0};
 
-int auto_spmm_rows(int64_t N) {
-  // about 64 row blocks per panel and level: measured on MI355X, larger
-  // blocks leave workgroups idle at the end of a level, smaller ones spend
-  // more time per row (n = 9: 0.34 ms per level at 48-64 rows, 0.69 ms at 8)
-  const int64_t r = (N / 64 + 3) / 4 * 4;
-  return (int)std::max<int64_t>(8, std::min<int64_t>(r, 64));
-}
-
 int auto_baby(int n) { return n >= 8 ? 16 : 32; }
-
-int rows_of(const Ctx *c, int n, int64_t N) {
-  if (c->spmm_rows[n] > 0) return c->spmm_rows[n];
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  return g_tuned_rows[n] > 0 ? g_tuned_rows[n] : auto_spmm_rows(N);
-}
 
 // largest power of two <= j
 int pow2_floor(int j) {
@@ -552,24 +452,50 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
   const int nslots = (int)plans.size();
-  // completion counters: one per (slot, exponent) counting every task that
-  // writes the power, then one per (slot, chain level, column panel) for the
-  // chain, whose panels are independent (column block P of A x X needs only
-  // column block P of X), so a panel's next level waits for that panel only
-  auto counter = [&](int slot, int e) { return slot * (maxexp + 1) + e; };
-  std::vector<int> pbase(nslots), npan(nslots);
-  int ncounters = nslots * (maxexp + 1);
-  for (int s = 0; s < nslots; ++s) {
-    npan[s] = (int)((c->sets[plans[s].n].N + kPanel - 1) / kPanel);
-    pbase[s] = ncounters;
-    ncounters += (plans[s].chain_top + 1) * npan[s];
+
+  // 1. chain levels: from the lowest missing level of each n up to its top,
+  // plain launches on the slot's own stream, after what the caller's stream
+  // has queued so far; the caller's stream waits for all of them
+  {
+    bool any = false;
+    for (int s = 0; s < nslots; ++s) {
+      const PowerSet &ps = c->sets[plans[s].n];
+      for (int k = 1; k <= plans[s].chain_top && !any; ++k) any = !ps.have.count(k);
+    }
+    if (any) {
+      if (!c->chain_start)
+        TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_start, hipEventDisableTiming));
+      TP_HIP_CHECK(hipEventRecord(c->chain_start, stream));
+    }
+    for (int s = 0; s < nslots && any; ++s) {
+      const Plan &p = plans[s];
+      PowerSet &ps = c->sets[p.n];
+      int k0 = 1;
+      while (k0 <= p.chain_top && ps.have.count(k0)) ++k0;
+      if (k0 > p.chain_top) continue;
+      if (!c->chain_stream[s]) {
+        TP_HIP_CHECK(hipStreamCreateWithFlags(&c->chain_stream[s], hipStreamNonBlocking));
+        TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_done[s], hipEventDisableTiming));
+      }
+      hipStream_t cs = c->chain_stream[s];
+      TP_HIP_CHECK(hipStreamWaitEvent(cs, c->chain_start, 0));
+      for (int k = k0; k <= p.chain_top; ++k) {
+        uint16_t *Y = (uint16_t *)ps.pw.at(k);
+        if (k == 1)
+          TP_HIP_CHECK(launch_dense_state(p.n, ps.N, p.view.masks, TP_U16, Y, ps.ld, cs));
+        else
+          TP_HIP_CHECK(state_step_view(p.view, (const uint16_t *)ps.pw.at(k - 1), ps.ld, Y,
+                                       ps.ld, ps.N, cs));
+      }
+      TP_HIP_CHECK(hipEventRecord(c->chain_done[s], cs));
+      TP_HIP_CHECK(hipStreamWaitEvent(stream, c->chain_done[s], 0));
+    }
   }
-  auto panel_counter = [&](int s, int e, int64_t c0) {
-    return pbase[s] + e * npan[s] + (int)(c0 / kPanel);
-  };
-  // a giant (dense product) counts its finished tiles per 128-row block and
-  // per 128-column block: a product tile or a trace block that reads rows (or
-  // columns) of it waits for those blocks only
+
+  // 2. the persistent kernel's tasks.  Chain powers and resident powers are
+  // complete when it starts; a giant computed by this batch counts its
+  // finished tiles per 128-row block and per 128-column block
+  int ncounters = 0;
   std::map<std::pair<int, int>, int> gbase;
   std::vector<int> nblk(nslots);
   for (int s = 0; s < nslots; ++s) {
@@ -582,46 +508,25 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       ncounters += 2 * nblk[s];
     }
   }
-  auto computed = [&](int s, int e) { return c->sets[plans[s].n].have.count(e) == 0; };
+  auto is_new_giant = [&](int s, int e) { return gbase.count({s, e}) != 0; };
 
   std::vector<Task> tasks;
-  std::vector<std::vector<int>> ntask(nslots, std::vector<int>(maxexp + 1, 0));
-  // dependency on all of exponent e of slot s (a chain power): none when e
-  // is resident already
-  auto dep_of = [&](int s, int e, int32_t *dep, int32_t *target) {
-    if (!computed(s, e)) {
-      *dep = -1;
-      *target = 0;
-    } else {
-      *dep = counter(s, e);
-      *target = ntask[s][e];
-    }
-  };
-  std::vector<int> per_panel(nslots, 0);  // SPMM tasks per panel of one chain level
   // dependency on rows [r0, r0 + 128) (all columns) of exponent e
   auto rows_dep = [&](int s, int e, int64_t r0, int32_t *dep, int32_t *target) {
     auto it = gbase.find({s, e});
-    if (it == gbase.end()) return dep_of(s, e, dep, target);
-    *dep = it->second + (int)(r0 / kGBM);
-    *target = nblk[s];
+    *dep = it == gbase.end() ? -1 : it->second + (int)(r0 / kGBM);
+    *target = it == gbase.end() ? 0 : nblk[s];
   };
   // dependency on columns [c0, c0 + 128) (all rows) of exponent e
   auto cols_dep = [&](int s, int e, int64_t c0, int32_t *dep, int32_t *target) {
     auto it = gbase.find({s, e});
-    if (it != gbase.end()) {
-      *dep = it->second + nblk[s] + (int)(c0 / kGBN);
-      *target = nblk[s];
-    } else if (e >= 2 && computed(s, e)) {
-      *dep = panel_counter(s, e, c0);
-      *target = per_panel[s];
-    } else {
-      dep_of(s, e, dep, target);
-    }
+    *dep = it == gbase.end() ? -1 : it->second + nblk[s] + (int)(c0 / kGBN);
+    *target = it == gbase.end() ? 0 : nblk[s];
   };
 
-  // a group of tasks (one chain level, one giant product or one instance's
-  // traces) is dealt to the queues in contiguous chunks, so that the tasks an
-  // XCD runs together share their inputs in its L2
+  // a group of tasks (one giant product or one instance's traces) is dealt to
+  // the queues in contiguous chunks, so that the tasks an XCD runs together
+  // share their inputs in its L2
   auto deal = [&](size_t first) {
     const size_t cnt = tasks.size() - first;
     for (size_t i = 0; i < cnt; ++i) tasks[first + i].queue = (int32_t)(i * kQueues / cnt);
@@ -640,7 +545,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     std::vector<int> rest;
     for (int j : waiting[s]) {
       const int a = ta[j], b = tb[j];
-      const bool ready = (!computed(s, a) || a <= upto) && (!computed(s, b) || b <= upto);
+      const bool ready = (!is_new_giant(s, a) || a <= upto) && (!is_new_giant(s, b) || b <= upto);
       if (!ready) {
         rest.push_back(j);
         continue;
@@ -666,103 +571,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     waiting[s].swap(rest);
   };
 
-  for (int s = 0; s < nslots; ++s) push_ready_traces(s, 0);  // answered by resident powers
-
-  // Each column panel's chain goes to one queue (its XCD keeps the panel of
-  // X in its L2 from level to level); panels are spread over the queues by
-  // their work, largest first, onto the least loaded queue.
-  std::vector<std::vector<int>> pqueue(nslots);
-  {
-    struct Chain {
-      double work;
-      int s, p;
-    };
-    std::vector<Chain> chains;
-    for (int s = 0; s < nslots; ++s) {
-      const Plan &p = plans[s];
-      const int64_t N = c->sets[p.n].N;
-      pqueue[s].assign(npan[s], 0);
-      if (p.chain_top < 2) continue;
-      for (int P = 0; P < npan[s]; ++P) {
-        const int64_t width = std::min<int64_t>(kPanel, N - (int64_t)P * kPanel);
-        chains.push_back({(double)p.view.nnz * (double)width * (double)(p.chain_top - 1), s, P});
-      }
-    }
-    std::stable_sort(chains.begin(), chains.end(),
-                     [](const Chain &a, const Chain &b) { return a.work > b.work; });
-    double load[kQueues] = {0};
-    for (const Chain &ch : chains) {
-      const int q = (int)(std::min_element(load, load + kQueues) - load);
-      load[q] += ch.work;
-      pqueue[ch.s][ch.p] = q;
-    }
-  }
-
-  // chain levels, level by level over all n
-  int max_top = 0;
-  for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
-  for (int k = 1; k <= max_top; ++k) {
-    for (int s = 0; s < nslots; ++s) {
-      const Plan &p = plans[s];
-      const PowerSet &ps = c->sets[p.n];
-      if (k > p.chain_top || !computed(s, k)) continue;
-      const int64_t N = ps.N;
-      const size_t first = tasks.size();
-      if (k == 1) {
-        // A^1 row blocks over all columns
-        const int64_t rows = std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)));
-        for (int64_t r0 = 0; r0 < N; r0 += rows) {
-          Task t{};
-          t.type = kBuild;
-          t.slot = s;
-          t.out = 1;
-          t.row0 = (int32_t)r0;
-          t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
-          t.c0 = 0;
-          t.c1 = (int32_t)N;
-          t.dep = t.dep2 = -1;
-          t.done = counter(s, 1);
-          t.done2 = -1;
-          tasks.push_back(t);
-          ++ntask[s][1];
-        }
-        deal(first);
-      } else {
-        const int rows = rows_of(c, p.n, N);
-        per_panel[s] = (int)((N + rows - 1) / rows);
-        // level k of panel P reads panel P of A^(k-1): that panel's counter
-        // when level k-1 is computed by this batch's chain, the power's
-        // counter for A^1, nothing when it is resident
-        for (int64_t c0 = 0; c0 < N; c0 += kPanel) {
-          for (int64_t r0 = 0; r0 < N; r0 += rows) {
-            Task t{};
-            t.type = kSpmm;
-            t.slot = s;
-            t.out = k;
-            t.x = k - 1;
-            t.row0 = (int32_t)r0;
-            t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
-            t.c0 = (int32_t)c0;
-            t.c1 = (int32_t)std::min<int64_t>(c0 + kPanel, N);
-            if (k - 1 >= 2 && computed(s, k - 1)) {
-              t.dep = panel_counter(s, k - 1, c0);
-              t.dep_target = per_panel[s];
-            } else {
-              dep_of(s, k - 1, &t.dep, &t.dep_target);
-            }
-            t.dep2 = -1;
-            t.done = panel_counter(s, k, c0);
-            t.done2 = counter(s, k);
-            t.queue = pqueue[s][c0 / kPanel];
-            tasks.push_back(t);
-            ++ntask[s][k];
-          }
-        }
-      }
-    }
-    for (int s = 0; s < nslots; ++s)
-      if (k <= plans[s].chain_top) push_ready_traces(s, k);
-  }
+  // instances answered by chain or resident powers first
+  for (int s = 0; s < nslots; ++s) push_ready_traces(s, 0);
   // giants in increasing exponent, interleaved over n; a giant's two factors
   // have smaller exponents and are queued before it
   std::vector<std::vector<int>> gl(nslots);
@@ -776,7 +586,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       if (r >= gl[s].size()) continue;
       const PowerSet &ps = c->sets[plans[s].n];
       const int j = gl[s][r], e = j * ps.c;
-      if (computed(s, e)) {
+      if (is_new_giant(s, e)) {
         int l, rr;
         giant_split(j, &l, &rr);
         const int x = l * ps.c, y = rr * ps.c;
@@ -796,7 +606,6 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
             t.done = gbase.at({s, e}) + (int)(m0 / kGBM);
             t.done2 = gbase.at({s, e}) + nblk[s] + (int)(n0 / kGBN);
             tasks.push_back(t);
-            ++ntask[s][e];
           }
         }
         deal(first);
@@ -835,7 +644,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   TP_HIP_CHECK(grow(c->d_slots, kMaxSlots * sizeof(Slot)));
   TP_HIP_CHECK(grow(c->d_ptrs, nptr * sizeof(void *)));
   TP_HIP_CHECK(grow(c->d_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_counters, (size_t)ncounters * sizeof(int32_t)));
+  TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max(ncounters, 1) * sizeof(int32_t)));
   TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t)));
 
   memcpy(c->h_tasks.p, tasks.data(), tbytes);
@@ -848,10 +657,6 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.n = p.n;
     sl.N = (int32_t)ps.N;
     sl.ld = ps.ld;
-    sl.full = (1u << p.n) - 1u;
-    sl.masks = p.view.masks;
-    sl.rowptr = p.view.rowptr;
-    sl.colz = p.view.colz;
     sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
     hs[s] = sl;
     for (size_t e = 0; e < ptr_stride; ++e) {
@@ -979,11 +784,6 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
     c->grid_override = (int)value;
     return TP_OK;
   }
-  if (param >= TP_PARAM_SPMM_ROWS && param < TP_PARAM_SPMM_ROWS + 16) {
-    TP_REQUIRE(value >= 0 && value <= 65536, "rows per task out of range");
-    c->spmm_rows[param - TP_PARAM_SPMM_ROWS] = (int)(value + 3) / 4 * 4;
-    return TP_OK;
-  }
   if (param >= TP_PARAM_BABY_STEPS && param < TP_PARAM_BABY_STEPS + 16) {
     const int n = param - TP_PARAM_BABY_STEPS;
     TP_REQUIRE(value >= 0 && value <= (1 << 16), "baby steps out of range");
@@ -1078,12 +878,10 @@ int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *
   return batch_run(c, count, n, m, gamma2_dev, stream);
 }
 
-int tp_tune_batch(int n, int spmm_rows, int baby_steps) {
+int tp_tune_batch(int n, int baby_steps) {
   TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
-  TP_REQUIRE(spmm_rows >= 0 && spmm_rows <= 65536, "rows per task out of range");
   TP_REQUIRE(baby_steps >= 0 && baby_steps <= (1 << 16), "baby steps out of range");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned_rows[n] = (spmm_rows + 3) / 4 * 4;
   g_tuned_baby[n] = baby_steps;
   return TP_OK;
 }

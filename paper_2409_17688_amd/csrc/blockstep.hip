@@ -32,9 +32,6 @@ namespace {
 
 constexpr int kRows = 16;  // rows per block
 
-typedef const __attribute__((address_space(4))) int64_t *kconst_i64;
-typedef const __attribute__((address_space(4))) uint64_t *kconst_u64;
-
 // One wave per block: number of distinct successors of its rows.
 __global__ void block_count_kernel(int64_t N, uint32_t full, const uint32_t *__restrict__ masks,
                                    int64_t *__restrict__ bptr) {

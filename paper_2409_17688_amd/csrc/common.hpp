@@ -49,6 +49,12 @@ using gconst = const __attribute__((address_space(1))) T *;
 template <typename T>
 using gmut = __attribute__((address_space(1))) T *;
 
+// Read-only tables (the resident CSR): through constant-space views a
+// wave-uniform index becomes a scalar load.
+typedef const __attribute__((address_space(4))) int64_t *kconst_i64;
+typedef const __attribute__((address_space(4))) uint32_t *kconst_u32;
+typedef const __attribute__((address_space(4))) uint64_t *kconst_u64;
+
 template <typename T>
 __device__ __forceinline__ gconst<T> to_global(const T *p) {
   return (gconst<T>)p;
@@ -108,6 +114,9 @@ struct StateView {
   int64_t nent;
 };
 int state_view(int n, hipStream_t s, StateView *out);
+// Y = A(D_n) x X (u16) in the form the library picks for n (tp_tune_step).
+hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                           int64_t ldy, int64_t ncols, hipStream_t s);
 
 // state.hip
 int64_t word_count_host(int n);
@@ -119,6 +128,12 @@ hipError_t launch_csr_count(int64_t N, int n, const uint32_t *masks, int64_t *ro
 hipError_t launch_scan_rowptr(int64_t N, int64_t *rowptr, hipStream_t s);
 hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_t *rowptr,
                            uint32_t *col, uint32_t *colz, hipStream_t s);
+
+// spmm.hip: the state matrix's own step from its packed successor list
+hipError_t launch_state_gather(int64_t rows, const int64_t *rowptr, const uint32_t *colz,
+                               const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
+                               int64_t ncols, hipStream_t s);
+bool state_gather_fits(const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t ncols);
 
 // blockstep.hip: the sparse left step over blocks of 16 rows
 int64_t block_count_host(int64_t N);

@@ -127,6 +127,79 @@ __device__ __forceinline__ void spmm_row_chunk(const int64_t *__restrict__ rowpt
   }
 }
 
+// Row q (wave-uniform) of Y = A(D_n) x X over this lane's 8 columns
+// c0 .. c0 + 7 (u16; ldx, ldy and c0 multiples of 8, X 16-byte aligned, X's
+// rows at least ncols rounded up to 8 long, so the 8 entries exist even past
+// ncols; only columns < ncols are stored), from the
+// packed successor list colz (successor in bits 0..23, its label z_p in bits
+// 24..31), read with scalar loads.  Software-pipelined: the next U
+// successors' indices and rows are requested before the current U are
+// combined, so two rounds of gathers are in flight.  A last partial round
+// repeats the row's last successor with an INF label, which never wins.
+template <int U>
+__device__ __forceinline__ void gather_row_colz(kconst_i64 rowptr, kconst_u32 colz,
+                                                const uint16_t *X, int64_t ldx, uint16_t *Y,
+                                                int64_t ldy, int64_t ncols, int64_t q,
+                                                int64_t c0) {
+  const int64_t b = rowptr[q], e = rowptr[q + 1];
+  const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
+  const int64_t ld4 = ldx / 8;
+  const uint32_t off = (uint32_t)(c0 / 8);
+  u16x2 acc[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = splat(0xFFFFu);
+  if (b < e) {
+    const int64_t last = e - 1;
+    auto fetch = [&](int64_t i, uint32_t (&pz)[U], u32x4 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = i + u;
+        const uint32_t w = colz[k < last ? k : last];
+        pz[u] = k <= last ? w : (w | 0xFF000000u);
+        v[u] = Xg[(int64_t)(pz[u] & 0xFFFFFFu) * ld4 + off];
+      }
+    };
+    auto combine = [&](const uint32_t (&pz)[U], const u32x4 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t z = pz[u] >> 24;
+        const u16x2 lab = splat((uint16_t)(z == 0xFFu ? 0xFFFFu : z));
+        acc[0] = pk_min(acc[0], pk_add_sat(lab, as_pk(v[u].x)));
+        acc[1] = pk_min(acc[1], pk_add_sat(lab, as_pk(v[u].y)));
+        acc[2] = pk_min(acc[2], pk_add_sat(lab, as_pk(v[u].z)));
+        acc[3] = pk_min(acc[3], pk_add_sat(lab, as_pk(v[u].w)));
+      }
+    };
+    uint32_t pa[U], pb[U];
+    u32x4 va[U], vb[U];
+    fetch(b, pa, va);
+    for (int64_t i = b;;) {
+      bool more = i + U <= last;
+      if (more) fetch(i + U, pb, vb);
+      combine(pa, va);
+      i += U;
+      if (!more) break;
+      more = i + U <= last;
+      if (more) fetch(i + U, pa, va);
+      combine(pb, vb);
+      i += U;
+      if (!more) break;
+    }
+  }
+  if (c0 >= ncols) return;
+  if (c0 + 8 <= ncols) {
+    *(gmut<u32x4>)(to_global_mut(Y) + q * ldy + c0) =
+        u32x4{as_u32(acc[0]), as_u32(acc[1]), as_u32(acc[2]), as_u32(acc[3])};
+  } else {
+    const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (c0 + 2 * r < ncols) y[2 * r] = acc[r].x;
+      if (c0 + 2 * r + 1 < ncols) y[2 * r + 1] = acc[r].y;
+    }
+  }
+}
+
 // Eight consecutive entries of row `row` from column `col`, widened to 16
 // bits; entries outside [0, n) x [0, n) read as 0xFFFF.
 template <typename T, bool VEC>

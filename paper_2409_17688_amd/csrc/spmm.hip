@@ -38,6 +38,26 @@ __global__ void __launch_bounds__(256) spmm_kernel(int64_t rows, const int64_t *
   if (c0 < ncols) spmm_row_chunk<T, VEC>(rowptr, col, z, X, ldx, Y, ldy, ncols, q, c0);
 }
 
+// The same product for the state matrix itself, from its packed successor
+// list (successor and label in one word, scalar loads) with two rounds of
+// gathers in flight (gather_row_colz); same launch shape as spmm_kernel.
+template <int U>
+__global__ void __launch_bounds__(256) state_gather_kernel(int64_t rows,
+                                                           const int64_t *__restrict__ rowptr,
+                                                           const uint32_t *__restrict__ colz,
+                                                           const uint16_t *__restrict__ X,
+                                                           int64_t ldx, uint16_t *__restrict__ Y,
+                                                           int64_t ldy, int64_t ncols) {
+  const int lane = threadIdx.x & 63;
+  const int64_t groups = (rows + 3) / 4;
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t panel = t / groups;
+  const int64_t q = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (q >= rows) return;
+  const int64_t c0 = (panel * 64 + lane) * 8;
+  gather_row_colz<U>((kconst_i64)rowptr, (kconst_u32)colz, X, ldx, Y, ldy, ncols, q, c0);
+}
+
 // min over arcs q -> p of z_p + X[p][q], one wave per row q, reduced into *out.
 template <typename T>
 __global__ void __launch_bounds__(256) sparse_trace_kernel(int64_t N,
@@ -90,6 +110,23 @@ hipError_t launch_spmm(int dtype, int64_t rows, const int64_t *rowptr, const uin
                                    ldy, ncols, s);
   return launch_spmm_t<uint8_t>(rows, rowptr, col, z, (const uint8_t *)X, ldx, (uint8_t *)Y, ldy,
                                 ncols, s);
+}
+
+hipError_t launch_state_gather(int64_t rows, const int64_t *rowptr, const uint32_t *colz,
+                               const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
+                               int64_t ncols, hipStream_t s) {
+  if (rows == 0 || ncols == 0) return hipSuccess;
+  const int64_t panels = (ncols + 511) / 512;
+  dim3 grid((unsigned)(((rows + 3) / 4) * panels));
+  hipLaunchKernelGGL(state_gather_kernel<8>, grid, dim3(256), 0, s, rows, rowptr, colz, X, ldx,
+                     Y, ldy, ncols);
+  return hipGetLastError();
+}
+
+bool state_gather_fits(const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t ncols) {
+  // 16-byte rows and chunks, and rows long enough for the last 8-entry chunk
+  return ldx % 8 == 0 && ldy % 8 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)Y % 16 == 0 &&
+         ldx >= (ncols + 7) / 8 * 8;
 }
 
 hipError_t launch_sparse_trace(int dtype, int64_t N, const int64_t *rowptr, const uint32_t *col,

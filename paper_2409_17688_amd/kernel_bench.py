@@ -2,6 +2,7 @@
 
     python -m paper_2409_17688_amd.kernel_bench --op spmm --n 12 --reps 5
     python -m paper_2409_17688_amd.kernel_bench --op bstep --n 12 --reps 5
+    python -m paper_2409_17688_amd.kernel_bench --op gather --n 9 --reps 5
     python -m paper_2409_17688_amd.kernel_bench --op trace --n 12
     python -m paper_2409_17688_amd.kernel_bench --op gemm --n 10 --config 0
     python -m paper_2409_17688_amd.kernel_bench --op batch --instances mixed64
@@ -11,6 +12,7 @@ Times come from HIP events on the launch stream; one JSON line per run with
 the algorithmic work of one launch:
   spmm   nnz(A) * N (min,+) operations; bytes: X read once, Y written (4 N^2)
   bstep  the same product by the blocked sparse step (tp_state_left_mul)
+  gather the same product by the packed per-row gather (tp_state_left_mul)
   trace  2 N^2 entries read (4 N^2 bytes)
   gemm   N^3 (min,+) operations
   batch  one persistent launch answering the instances (cold context)
@@ -43,7 +45,7 @@ def _padded(torch, N):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=["spmm", "bstep", "trace", "gemm", "batch"], required=True)
+    ap.add_argument("--op", choices=["spmm", "bstep", "gather", "trace", "gemm", "batch"], required=True)
     ap.add_argument("--n", type=int, default=10)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--config", type=int, default=None, help="dense product tile config")
@@ -55,7 +57,7 @@ def main(argv=None):
     from . import _lib as tp
     n = args.n
     out = {"op": args.op}
-    if args.op in ("spmm", "bstep", "trace", "gemm"):
+    if args.op in ("spmm", "bstep", "gather", "trace", "gemm"):
         N = tp.tp_state_dim(n)
         X, Y = _padded(torch, N), _padded(torch, N)
         tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
@@ -65,10 +67,10 @@ def main(argv=None):
             rowptr, col, z = tp.tp_build_state_csr(n)
             t = _events(torch, lambda: tp.tp_minplus_spmm(rowptr, col, z, X, Y), args.reps)
             out.update({"nnz": nnz, "ms": t * 1e3, "Tminplus_ops": nnz * N / t / 1e12})
-        elif args.op == "bstep":
+        elif args.op in ("bstep", "gather"):
             nnz = tp.tp_state_nnz(n)
-            t = _events(torch, lambda: tp.tp_state_left_mul(n, X, Y, form=tp.TP_STEP_BLOCKED),
-                        args.reps)
+            form = tp.TP_STEP_BLOCKED if args.op == "bstep" else tp.TP_STEP_CSR
+            t = _events(torch, lambda: tp.tp_state_left_mul(n, X, Y, form=form), args.reps)
             out.update({"nnz": nnz, "ms": t * 1e3, "Tminplus_ops": nnz * N / t / 1e12})
         elif args.op == "trace":
             tp.tp_minplus_spmm(*tp.tp_build_state_csr(n), X, Y)

@@ -1,7 +1,7 @@
 """Loads a tuning table (written by ``autotune``) into the library.
 
 A table maps problem sizes to kernel shapes (tile configuration and K split
-of dense products, rows per task and baby steps of the batch engine) and
+of dense products, the sparse step's form, baby steps of the batch engine) and
 records measured kernel rates for the schedule planner.  None of it changes a
 result.  The package applies ``tuning_gfx950.json`` on import.
 """
@@ -38,5 +38,5 @@ def apply_tuning(path: str | None = None, table: dict | None = None) -> bool:
     for n, form in table.get("step", {}).items():
         tp.tp_tune_step(int(n), int(form))
     for n, vals in table.get("batch", {}).items():
-        tp.tp_tune_batch(int(n), int(vals[0]), int(vals[1]))
+        tp.tp_tune_batch(int(n), int(vals[0]))
     return True

@@ -129,18 +129,26 @@ def test_abort_path_forced_from_host(tp, oracle_table):
         tp.tp_ctx_destroy(ctx)
 
 
-def test_task_granularity_does_not_change_results(tp, oracle_table):
+def test_grid_and_step_form_do_not_change_results(tp, oracle_table):
+    # persistent grids from the minimum (one workgroup per queue) to the
+    # whole chip, and both forms of the chain's sparse step
     inst = synth.batch_instances(seed=11, count=20)
-    for rows in (4, 16, 100):
-        ctx = tp.tp_ctx_create(64 << 30)
-        try:
+    want = [int(oracle_table[n][m - 1]) for n, m in inst]
+    try:
+        for grid, form in ((8, tp.TP_STEP_CSR), (37, tp.TP_STEP_BLOCKED), (0, tp.TP_STEP_AUTO)):
             for n in range(4, 10):
-                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_SPMM_ROWS + n, rows)
-            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_GRID, 37)
-            got = _run(tp, ctx, inst)
-            assert got == [int(oracle_table[n][m - 1]) for n, m in inst], rows
-        finally:
-            tp.tp_ctx_destroy(ctx)
+                tp.tp_tune_step(n, form)
+            ctx = tp.tp_ctx_create(64 << 30)
+            try:
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_GRID, grid)
+                got = _run(tp, ctx, inst)
+                assert got == want, (grid, form)
+            finally:
+                tp.tp_ctx_destroy(ctx)
+    finally:
+        for n in range(4, 10):
+            tp.tp_tune_step(n, tp.TP_STEP_AUTO)
+        tp.apply_tuning()
 
 
 @pytest.fixture(scope="module")
