@@ -97,8 +97,10 @@ def main():
 
     N = args.n
     A, B = synth.raw_gemm_pair(N, seed=0)
-    # the shape the default path runs for this product (tuning table or built-in rule)
-    cfg, ksplit = tp.tp_gemm_choice(tp.TP_U16, N, N, N)
+    # the tile configuration the default path runs for this product (tuning
+    # table or built-in rule); tp_minplus_gemm never splits K
+    cfg, _ = tp.tp_gemm_choice(tp.TP_U16, N, N, N)
+    ksplit = 1
     kernel = f"minplus_gemm_kernel<{KERNEL_SHAPES[cfg]},u16,vec>"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

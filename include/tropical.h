@@ -97,7 +97,10 @@ int tp_build_state_csr(int n, int64_t *d_rowptr, uint32_t *d_col, uint8_t *d_z,
 /* ------------------------------------------------------------------------ */
 
 /* C (M x N) = A (M x K) x B (K x N); with accumulate != 0,
- * C = min(C, A x B) elementwise.  Device pointers of the given dtype. */
+ * C = min(C, A x B) elementwise.  Device pointers of the given dtype.  Runs
+ * the tile configuration the tuning table gives for max(M, N, K), never with
+ * a K split: it allocates nothing (the library's own products, and
+ * tp_minplus_gemm_ex, may split K into scratch). */
 int tp_minplus_gemm(int dtype, int64_t M, int64_t N, int64_t K,
                     const void *d_A, int64_t lda, const void *d_B, int64_t ldb,
                     void *d_C, int64_t ldc, int accumulate, hipStream_t stream);
@@ -137,8 +140,9 @@ int tp_minplus_gemm_ex(int dtype, int64_t M, int64_t N, int64_t K, const void *d
  * table (back to the built-in heuristic).  Process-wide, thread-safe. */
 int tp_tune_gemm(int dtype, int64_t max_dim, int config, int ksplit);
 
-/* The (config, ksplit) the default path would use for an M x N x K product
- * of this dtype, into *config and *ksplit (host pointers). */
+/* The tuned (config, ksplit) for an M x N x K product of this dtype, into
+ * *config and *ksplit (host pointers): the shape of the library's own
+ * products; tp_minplus_gemm runs that config with ksplit 1. */
 int tp_gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *ksplit);
 
 /* Measured rates for the schedule planner of tp_tropical_power_trace at path

@@ -244,12 +244,12 @@ int power_of(uint16_t *P, int64_t q, int64_t N, int64_t ld, uint16_t *dst, uint1
   int which = 0;
   for (int b = top - 1; b >= 0; --b) {
     uint16_t *o = bufs[which];
-    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, cur, ld, o, ld, 0, -1, 1, s));
+    TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, cur, ld, o, ld, 0, -1, -1, s));
     cur = o;
     which ^= 1;
     if ((q >> b) & 1) {
       uint16_t *o2 = bufs[which];
-      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, P, ld, o2, ld, 0, -1, 1, s));
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, cur, ld, P, ld, o2, ld, 0, -1, -1, s));
       cur = o2;
       which ^= 1;
     }
@@ -309,7 +309,7 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
       // H x X = P^(h+1) into a buffer that is neither H nor X
       uint16_t *o = (H == tmp_a) ? tmp_b : tmp_a;
       if (H == X) o = tmp_a;
-      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, ld, X, ld, o, ld, 0, -1, 1, s));
+      TP_HIP_CHECK(launch_gemm(TP_U16, N, N, N, H, ld, X, ld, o, ld, 0, -1, -1, s));
       TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, ld, o, ld, d_res, s));
     } else {
       TP_HIP_CHECK(launch_trace_of_product(TP_U16, N, H, ld, H, ld, d_res, s));
@@ -445,7 +445,7 @@ int tp_minplus_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A,
   int rc = check_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc);
   if (rc != TP_OK) return rc;
   TP_HIP_CHECK(
-      launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, -1, 1, stream));
+      launch_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, -1, 0, stream));
   return TP_OK;
 }
 

@@ -237,8 +237,9 @@ hipError_t grow_host(Buf &b, size_t bytes) {
 struct PowerSet {
   int64_t N = 0, ld = 0;
   int c = 0;                 // baby steps (fixed at first use)
-  std::map<int, void *> pw;  // exponent -> device buffer
+  std::map<int, void *> pw;  // exponent -> device buffer (inside a slab)
   std::set<int> have;        // exponents known complete on the device
+  std::vector<void *> slabs;  // one allocation per batch that added powers
 };
 
 }  // namespace
@@ -438,17 +439,20 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
                 c->used, c->budget);
       return TP_ENOMEM;
     }
+    // the new powers of one n in one allocation (a slab), cut in order
     for (const Plan &p : plans) {
       PowerSet &ps = c->sets[p.n];
       const size_t bytes = (size_t)ps.N * (size_t)ps.ld * sizeof(uint16_t);
-      for (int e : p.exps) {
-        if (ps.pw.count(e)) continue;
-        void *ptr = nullptr;
-        hipError_t err = hipMalloc(&ptr, bytes);
-        if (err != hipSuccess) return hip_fail(err, "hipMalloc (resident power)");
-        c->used += bytes;
-        ps.pw[e] = ptr;
-      }
+      std::vector<int> missing;
+      for (int e : p.exps)
+        if (!ps.pw.count(e)) missing.push_back(e);
+      if (missing.empty()) continue;
+      void *slab = nullptr;
+      hipError_t err = hipMalloc(&slab, bytes * missing.size());
+      if (err != hipSuccess) return hip_fail(err, "hipMalloc (resident powers)");
+      ps.slabs.push_back(slab);
+      c->used += bytes * missing.size();
+      for (size_t i = 0; i < missing.size(); ++i) ps.pw[missing[i]] = (char *)slab + i * bytes;
     }
   }
   const int nslots = (int)plans.size();
@@ -732,7 +736,7 @@ void ctx_free(Ctx *c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->staged) (void)hipEventDestroy(c->staged);
   for (auto &kv : c->sets)
-    for (auto &e : kv.second.pw) (void)hipFree(e.second);
+    for (void *slab : kv.second.slabs) (void)hipFree(slab);
   Buf *dev[] = {&c->d_tasks, &c->d_slots, &c->d_ptrs, &c->d_counters, &c->d_results, &c->d_ctl};
   for (Buf *b : dev)
     if (b->p) (void)hipFree(b->p);
@@ -819,10 +823,8 @@ int tp_ctx_release(void *ctx, int n, hipStream_t stream) {
       continue;
     }
     const size_t bytes = (size_t)it->second.N * (size_t)it->second.ld * sizeof(uint16_t);
-    for (auto &e : it->second.pw) {
-      TP_HIP_CHECK(hipFree(e.second));
-      c->used -= bytes;
-    }
+    for (void *slab : it->second.slabs) TP_HIP_CHECK(hipFree(slab));
+    c->used -= bytes * it->second.pw.size();
     c->pending_new.erase(it->first);
     it = c->sets.erase(it);
   }

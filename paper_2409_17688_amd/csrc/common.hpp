@@ -146,6 +146,9 @@ hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent
                              int64_t ncols, hipStream_t s);
 
 // gemm.hip
+// config >= 0: that tile configuration with ksplit slices (>= 1); config < 0:
+// the tuned shape, with its K split when ksplit < 0 and unsplit (so without
+// scratch) when ksplit == 0
 hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
                        const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
                        int config, int ksplit, hipStream_t s);

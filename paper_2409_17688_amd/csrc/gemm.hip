@@ -237,7 +237,12 @@ hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A
                        const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
                        int config, int ksplit, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
-  if (config < 0) gemm_choice(dtype, M, N, K, &config, &ksplit);
+  if (config < 0) {
+    // tuned shape; ksplit 0 keeps it unsplit (no scratch: nothing allocated)
+    int tuned_split = 1;
+    gemm_choice(dtype, M, N, K, &config, &tuned_split);
+    ksplit = ksplit == 0 ? 1 : tuned_split;
+  }
   // slices of a multiple of 64 columns (keeps the slices' 16-byte alignment)
   int S = 1;
   int64_t kslice = K;
