@@ -1,0 +1,84 @@
+"""Host logic of the batch engine, on the CPU: which powers a batch needs.
+
+tp_ctx_need_bytes runs the engine's planning on the host only (no device
+call): per path order, the chain up to the largest baby step an instance
+needs and the giants A^(jc) with their closure under j = h + (j - h), h the
+largest power of two <= j (j/2 + j/2 when j is a power of two).  The model
+below restates those rules independently; the byte counts must agree."""
+import numpy as np
+import pytest
+
+import paper_2409_17688_amd as tp
+
+
+def _closure(j, out):
+    if j <= 1 or j in out:
+        return
+    h = 1
+    while h * 2 <= j:
+        h *= 2
+    left, right = (j // 2, j // 2) if h == j else (h, j - h)
+    _closure(left, out)
+    _closure(right, out)
+    out.add(j)
+
+
+def model_bytes(n, ms, c):
+    N = tp.tp_state_dim(n)
+    ld = (N + 63) // 64 * 64
+    top, giants = 1, set()
+    for m in ms:
+        if m <= 2 * c:
+            top = max(top, (m + 1) // 2)
+        else:
+            top = max(top, c)
+            _closure((m - 1) // c, giants)
+    exps = set(range(1, top + 1)) | {j * c for j in giants}
+    return len(exps) * N * ld * 2
+
+
+@pytest.fixture
+def ctx():
+    h = tp.tp_ctx_create(1 << 40)
+    yield h
+    tp.tp_ctx_destroy(h)
+
+
+@pytest.mark.parametrize("c", [2, 3, 5, 8, 16, 48])
+def test_need_bytes_matches_the_planning_rules(ctx, c):
+    rng = np.random.default_rng(c)
+    for n in (1, 3, 5, 7, 9, 11):
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, c)
+    for trial in range(20):
+        n = int(rng.choice([1, 3, 5, 7, 9, 11]))
+        ms = [int(m) for m in rng.integers(3, 400, int(rng.integers(1, 12)))]
+        if n * max(ms) >= 65535:
+            continue
+        got = tp.tp_ctx_need_bytes(ctx, [n] * len(ms), ms)
+        assert got == model_bytes(n, ms, c), (n, ms, c)
+
+
+def test_need_bytes_adds_over_path_orders(ctx):
+    for n in (4, 6, 8):
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 10)
+    inst = [(4, 7), (6, 100), (8, 33), (4, 90), (8, 201)]
+    ns, ms = [a for a, _ in inst], [b for _, b in inst]
+    want = sum(model_bytes(n, [m for a, m in inst if a == n], 10) for n in (4, 6, 8))
+    assert tp.tp_ctx_need_bytes(ctx, ns, ms) == want
+
+
+def test_need_bytes_rejects_bad_instances(ctx):
+    with pytest.raises(tp.TropicalError):
+        tp.tp_ctx_need_bytes(ctx, [13], [5])
+    with pytest.raises(tp.TropicalError):
+        tp.tp_ctx_need_bytes(ctx, [4], [2])
+    assert tp.tp_ctx_need_bytes(ctx, [], []) == 0
+
+
+def test_baby_steps_parameter_bounds(ctx):
+    with pytest.raises(tp.TropicalError):
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + 4, -1)
+    with pytest.raises(tp.TropicalError):
+        tp.tp_ctx_set_param(ctx, 999, 1)
+    with pytest.raises(tp.TropicalError):
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_GRID, 3)  # fewer workgroups than queues
