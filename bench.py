@@ -276,9 +276,11 @@ def query_suite(tp, synth):
     'plain' calls tp_tropical_power_trace once per instance (state matrices
     cached, every chain recomputed); 'batched cold' answers all instances in
     one batch on a fresh context (every power allocated and computed inside
-    the batch; median of three fresh contexts); 'batched warm' repeats the
-    batch on the same context (powers resident, only the traces run).  Every
-    batched answer is compared with the plain one."""
+    the batch; median of three fresh contexts); 'fused cold' the same with
+    the chain levels inside the one persistent launch (TP_PARAM_FUSED_CHAIN);
+    'batched warm' repeats the batch on the same context (powers resident,
+    only the traces run).  Every batched answer is compared with the plain
+    one."""
     import torch
     out = {}
     for name, inst in (("mixed64", synth.batch_instances(seed=0)),
@@ -321,7 +323,22 @@ def query_suite(tp, synth):
             finally:
                 tp.tp_ctx_destroy(ctx)
         t_cold = sorted(t_colds)[1]
-        if not (cold == warm == plain):
+        # the same, with the chain levels inside the one persistent launch
+        t_fused = []
+        for rep in range(3):
+            ctx = tp.tp_ctx_create(64 << 30)
+            try:
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = tp.tp_batch_power_trace(ctx, ns, ms)
+                tp.tp_ctx_check(ctx)
+                t_fused.append(time.perf_counter() - t0)
+                fused = res.cpu().numpy().tolist()
+            finally:
+                tp.tp_ctx_destroy(ctx)
+        t_fused = sorted(t_fused)[1]
+        if not (cold == warm == fused == plain):
             print(f"MISMATCH in {name}: batched and plain answers differ", file=sys.stderr)
             sys.exit(1)
         k = len(inst)
@@ -329,7 +346,9 @@ def query_suite(tp, synth):
                      "plain_qps": round(k / t_plain, 1),
                      "batched_cold_qps": round(k / t_cold, 1),
                      "batched_warm_qps": round(k / t_warm, 1),
+                     "fused_cold_qps": round(k / t_fused, 1),
                      "cold_speedup": round(t_plain / t_cold, 2),
+                     "fused_cold_speedup": round(t_plain / t_fused, 2),
                      "warm_speedup": round(t_plain / t_warm, 2)}
     return out
 

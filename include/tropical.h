@@ -151,10 +151,12 @@ int tp_gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int 
  * both 0 to restore the built-in rates. */
 int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s);
 
-/* Library-wide default of the batch engine's baby steps c at path order n
- * (1..12); 0 keeps the built-in rule.  A context's TP_PARAM_BABY_STEPS takes
- * precedence; baby steps already fixed in a context do not change. */
-int tp_tune_batch(int n, int baby_steps);
+/* Library-wide defaults of the batch engine's baby steps c at path order n
+ * (1..12), for the default mode and for TP_PARAM_FUSED_CHAIN (where chain
+ * levels cost more, so fewer pay); 0 keeps the built-in rule.  A context's
+ * TP_PARAM_BABY_STEPS takes precedence; baby steps already fixed in a context
+ * do not change. */
+int tp_tune_batch(int n, int baby_steps, int fused_baby_steps);
 
 /* Matrix-vector products with the M x K matrix A:
  *   trans == 0:  y (M)  = A x x (x has K entries),  y_i = min_k a_ik + x_k
@@ -248,6 +250,11 @@ int tp_ctx_destroy(void *ctx);
 /* Tuning and test parameters of a context. */
 #define TP_PARAM_WAIT_LIMIT_US 1 /* bound on one dependency wait (default 20 s) */
 #define TP_PARAM_GRID 2          /* workgroups of the persistent kernel (>= 8); 0 = fill the chip */
+#define TP_PARAM_FUSED_CHAIN 3   /* 1: chain levels run inside the persistent launch too (one
+                                    launch per batch); 0 (default): as full-chip launches on
+                                    one stream per n ahead of it, which is faster */
+#define TP_PARAM_SPMM_ROWS 16    /* TP_PARAM_SPMM_ROWS + n: fused mode, rows per chain task;
+                                    0 = about 64 row blocks per panel */
 #define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
                                     n >= 8, else 32); fixed once powers of n are resident */
 int tp_ctx_set_param(void *ctx, int param, int64_t value);
@@ -269,7 +276,8 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
  * steps, one context-owned stream per n, ordered after the work already on
  * `stream`), then, on `stream`, the missing giant products and one trace per
  * instance as one dependency-ordered task list run by one persistent kernel
- * launch from a captured hipGraph; returns without waiting.
+ * launch from a captured hipGraph; with TP_PARAM_FUSED_CHAIN the chain levels
+ * are tasks of that one launch too.  Returns without waiting.
  * TP_ENOMEM when the needed powers exceed the context's budget (nothing is
  * queued).  Results of a batch are valid after tp_ctx_check returns TP_OK. */
 int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,

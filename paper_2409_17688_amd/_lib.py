@@ -29,6 +29,8 @@ TP_EBUSY = -5
 TP_ECANCELED = -6
 TP_PARAM_WAIT_LIMIT_US = 1
 TP_PARAM_GRID = 2
+TP_PARAM_FUSED_CHAIN = 3
+TP_PARAM_SPMM_ROWS = 16
 TP_PARAM_BABY_STEPS = 32
 TP_STEP_AUTO = 0
 TP_STEP_CSR = 1
@@ -62,7 +64,7 @@ _SIGS = {
     "tp_tune_gemm": ([_i, _i64, _i, _i], _i),
     "tp_gemm_choice": ([_i, _i64, _i64, _i64, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "tp_tune_planner": ([_i, ctypes.c_double, ctypes.c_double], _i),
-    "tp_tune_batch": ([_i, _i], _i),
+    "tp_tune_batch": ([_i, _i, _i], _i),
     "tp_minplus_gemv": ([_i, _i64, _i64, _p, _i64, _p, _p, _i, _p], _i),
     "tp_minplus_spmm": ([_i, _i64, _i64, _p, _p, _p, _p, _i64, _p, _i64, _i64, _p], _i),
     "tp_state_left_mul": ([_i, _i, _p, _i64, _p, _i64, _i64, _p], _i),
@@ -249,8 +251,8 @@ def tp_tune_planner(n: int, spmm_ops_per_s: float, gemm_ops_per_s: float) -> Non
     _check(lib.tp_tune_planner(int(n), float(spmm_ops_per_s), float(gemm_ops_per_s)))
 
 
-def tp_tune_batch(n: int, baby_steps: int) -> None:
-    _check(lib.tp_tune_batch(int(n), int(baby_steps)))
+def tp_tune_batch(n: int, baby_steps: int, fused_baby_steps: int = 0) -> None:
+    _check(lib.tp_tune_batch(int(n), int(baby_steps), int(fused_baby_steps)))
 
 
 def tp_minplus_gemv(A: torch.Tensor, x: torch.Tensor, trans: bool = False,

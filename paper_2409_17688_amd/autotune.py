@@ -12,8 +12,9 @@ What it tunes (none of it changes a result, only which kernel shape runs):
   * the schedule planner of ``tp_tropical_power_trace``: measured (min,+)
     rates of that step and of the tuned dense product per n
     (``tp_tune_planner``);
-  * the batch engine, n = 4..9: baby steps c, on a batch of 12 instances
-    with m uniform in 3..200 (``tp_tune_batch``).
+  * the batch engine, n = 4..9: baby steps c for the default mode and for
+    the fused mode, on a batch of 12 instances with m uniform in 3..200
+    (``tp_tune_batch``).
 
 Every candidate is checked against the reference shape (tile configuration
 0 without a split for products, the built-in batch parameters for batches):
@@ -156,7 +157,8 @@ def _batch_time(ns, ms, params, reps=3):
 
 
 def tune_batch(ns, baby_list, seed, log):
-    """{n: [baby steps, seconds]}: fastest cold batch of 12 instances."""
+    """{n: [baby steps, seconds, fused baby steps, seconds]}: fastest cold
+    batch of 12 instances in each mode."""
     rng = np.random.default_rng(seed)
     out = {}
     # load the batch kernel once so that the first candidate is not charged for it
@@ -166,15 +168,19 @@ def tune_batch(ns, baby_list, seed, log):
         nl = [n] * len(ms)
         tp.tp_tropical_power_trace(n, 3)  # state in the cache
         _, ref = _batch_time(nl, ms, {}, reps=1)
-        best = None
-        for c in baby_list:
-            t, res = _batch_time(nl, ms, {tp.TP_PARAM_BABY_STEPS + n: c})
-            if res != ref:
-                raise RuntimeError(f"batch n={n} c={c} differs")
-            if best is None or t < best[1] * (1.0 - TIE):
-                best = [c, t]
-        log(f"batch n={n}: baby steps {best[0]} {best[1] * 1e3:.2f} ms")
-        out[n] = best
+        row = []
+        for fused in (0, 1):
+            best = None
+            for c in baby_list:
+                t, res = _batch_time(nl, ms, {tp.TP_PARAM_BABY_STEPS + n: c,
+                                              tp.TP_PARAM_FUSED_CHAIN: fused})
+                if res != ref:
+                    raise RuntimeError(f"batch n={n} c={c} fused={fused} differs")
+                if best is None or t < best[1] * (1.0 - TIE):
+                    best = [c, t]
+            log(f"batch n={n} fused={fused}: baby steps {best[0]} {best[1] * 1e3:.2f} ms")
+            row += best
+        out[n] = row
     return out
 
 
@@ -210,7 +216,7 @@ def main(argv=None):
     for dt in (tp.TP_U16, tp.TP_U8):
         tp.tp_tune_gemm(dt, -1)
     for n in range(1, 13):
-        tp.tp_tune_batch(n, 0)
+        tp.tp_tune_batch(n, 0, 0)
         tp.tp_tune_planner(n, 0.0, 0.0)
         tp.tp_tune_step(n, tp.TP_STEP_AUTO)
     if args.quick:

@@ -16,22 +16,30 @@
 // (jc, r).  Memory per n is (c + m_max/c) powers instead of m_max/2, and the
 // number of sequential chain levels is c instead of m_max/2.
 //
-// A batch runs in two parts on the caller's stream:
-//   1. the chain levels A^1 .. A^c of every path order that lacks them, as
-//      plain launches of the library's sparse left step on one stream per n
-//      (the steps of one n are sequential; different n run side by side);
-//      a chain level fills the chip on its own, which a share of a persistent
-//      kernel does not (each level depends on the whole level before it);
-//   2. one persistent kernel for the dense products and the traces, over a
-//      list of tasks in dependency order:
-//        GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
-//        TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
-//               instance's result with an atomic min
-//      A product tile (rows R, columns C) and a trace block (rows I) read rows
-//      R (I) of the left factor and columns C (I) of the right one, so a giant
-//      counts its finished tiles per 128-row and per 128-column block and a
-//      task waits (on at most two counters) for the blocks it reads only;
-//      chain powers are complete before the kernel starts.
+// A batch runs on the caller's stream in one of two modes:
+//   split (default)  the chain levels A^1 .. A^c of every path order that
+//      lacks them run first as plain launches of the library's sparse left
+//      step, one stream per n (the steps of one n are sequential; different
+//      n run side by side), then one persistent kernel runs the dense
+//      products and the traces.  A chain level depends on the whole level
+//      before it and fills the chip on its own, which a share of a
+//      persistent kernel does not.
+//   fused (TP_PARAM_FUSED_CHAIN)  everything, chain levels included, runs
+//      in the one persistent launch.
+// The persistent kernel runs a list of tasks in dependency order:
+//   BUILD  rows of A^1 = A(D_n)                          (fused mode)
+//   SPMM   rows x one 512-column panel of A^k = A x A^(k-1)  (fused mode)
+//   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
+//   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
+//          instance's result with an atomic min
+// Dependencies are as narrow as the arithmetic allows, each a completion
+// counter and a target count: column panel P of A x X needs column panel P
+// of X only, so a chain level waits for the same panel of the level before
+// (and a panel's whole chain is dealt to one queue, whose XCD keeps that
+// panel of X in its L2); a product tile (rows R, columns C) and a trace block
+// (rows I) read rows R (I) of the left factor and columns C (I) of the right
+// one, so a giant counts its finished tiles per 128-row and per 128-column
+// block; the rest waits for whole powers.
 // The list is split into 8 queues, one per XCD, each keeping the list's
 // order; a giant's tiles and an instance's trace blocks go to the queues in
 // contiguous chunks.  Workgroups pop their own XCD's queue first (one atomic
@@ -60,7 +68,7 @@ namespace tp {
 
 namespace {
 
-enum : int32_t { kGemm = 2, kTrace = 3 };
+enum : int32_t { kBuild = 0, kSpmm = 1, kGemm = 2, kTrace = 3 };
 
 struct Task {
   int32_t type, slot;
@@ -76,6 +84,11 @@ struct Task {
 struct Slot {
   int32_t n, N;
   int64_t ld;
+  uint32_t full;
+  int32_t pad;
+  const uint32_t *masks;
+  const int64_t *rowptr;
+  const uint32_t *colz;     // successors with their labels in the top byte
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
@@ -92,6 +105,7 @@ struct Control {
 
 constexpr int kMaxSlots = 16;
 constexpr uint16_t kInf = 0xFFFFu;
+constexpr int kPanel = 512;                       // columns of an SPMM task: 64 lanes x 8
 constexpr int kGBM = 128, kGBN = 128, kGBK = 32;  // dense product tile
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
@@ -128,6 +142,7 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
   __shared__ int32_t s_task, s_go, s_fresh;
   int acq_dep = -1, acq_dep2 = -1;  // dependencies this workgroup has acquired (thread 0)
   const int64_t limit = ctl->wait_limit;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // the hardware deals workgroups to the XCDs in turn, so workgroup b runs on
   // XCD b mod 8 and serves that queue first; when it is empty it takes tasks
   // from the others, always in each queue's own order
@@ -168,7 +183,26 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
       if (s_fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const Slot sl = slots[task.slot];
       const int64_t N = sl.N, ld = sl.ld;
-      if (task.type == kGemm) {
+      if (task.type == kSpmm) {
+        const uint16_t *X = sl.powers[task.x];
+        uint16_t *Y = sl.powers[task.out];
+        for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
+          const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
+          for (int64_t c0 = task.c0 + (int64_t)lane * 8; c0 < task.c1; c0 += kPanel)
+            gather_row_colz<6>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, X, ld, Y, ld, N, qu,
+                               c0);
+        }
+      } else if (task.type == kBuild) {
+        uint16_t *out = sl.powers[1];
+        const int64_t rows = task.row1 - task.row0;
+        for (int64_t idx = threadIdx.x; idx < rows * N; idx += blockDim.x) {
+          const int64_t q = task.row0 + idx / N, p = idx - (idx / N) * N;
+          const uint32_t mp = sl.masks[p];
+          out[q * ld + p] = can_follow(sl.masks[q], mp, sl.full)
+                                ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
+                                : kInf;
+        }
+      } else if (task.type == kGemm) {
         gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
             (int)N, (int)N, (int)N, sl.powers[task.x], ld,
             sl.powers[task.y], ld, sl.powers[task.out], ld, 0, task.row0,
@@ -261,6 +295,8 @@ struct Ctx {
   hipEvent_t chain_start = nullptr, chain_done[16] = {nullptr};
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
   int baby[16] = {0};               // baby steps by n; 0 = automatic
+  int fused = 0;                    // chain levels inside the persistent launch
+  int spmm_rows[16] = {0};          // fused mode: rows per chain task by n; 0 = automatic
   int grid_override = 0;
   bool pending = false;                      // a batch was queued and not yet checked
   std::map<int, std::set<int>> pending_new;  // exponents that batch computes, by n
@@ -272,9 +308,18 @@ namespace {
 // Library-wide baby steps by n from the autotuner (0: none); a context's
 // own parameter takes precedence.
 std::mutex g_tune_mu;
-int g_tuned_baby[16] = {0};
+int g_tuned_baby[2][16] = {{0}};  // [fused mode][n]
 
 int auto_baby(int n) { return n >= 8 ? 16 : 32; }
+
+// Fused mode: rows per chain task, about 64 row blocks per panel and level
+// (measured: larger blocks leave workgroups idle at the end of a level,
+// smaller ones spend more of each task on its pop, wait and release).
+int rows_of(const Ctx *c, int n, int64_t N) {
+  if (c->spmm_rows[n] > 0) return c->spmm_rows[n];
+  const int64_t r = (N / 64 + 3) / 4 * 4;
+  return (int)std::max<int64_t>(8, std::min<int64_t>(r, 64));
+}
 
 // largest power of two <= j
 int pow2_floor(int j) {
@@ -387,7 +432,8 @@ int baby_of(Ctx *c, int n) {
   if (it != c->sets.end() && it->second.c > 0) return it->second.c;
   if (c->baby[n] > 0) return c->baby[n];
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  return g_tuned_baby[n] > 0 ? g_tuned_baby[n] : auto_baby(n);
+  const int t = g_tuned_baby[c->fused ? 1 : 0][n];
+  return t > 0 ? t : auto_baby(n);
 }
 
 std::vector<int> exponents_of(int chain_top, const std::set<int> &giants, int c) {
@@ -456,34 +502,37 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
   const int nslots = (int)plans.size();
+  const bool fused = c->fused != 0;
+  // missing chain levels of each slot: k0[s] .. chain_top (none if beyond)
+  std::vector<int> k0(nslots);
+  for (int s = 0; s < nslots; ++s) {
+    const PowerSet &ps = c->sets[plans[s].n];
+    k0[s] = 1;
+    while (k0[s] <= plans[s].chain_top && ps.have.count(k0[s])) ++k0[s];
+  }
 
-  // 1. chain levels: from the lowest missing level of each n up to its top,
-  // plain launches on the slot's own stream, after what the caller's stream
-  // has queued so far; the caller's stream waits for all of them
-  {
+  // split mode: the chain levels as plain launches, from the lowest missing
+  // level of each n up to its top, on the slot's own stream after what the
+  // caller's stream has queued so far; the caller's stream waits for them
+  if (!fused) {
     bool any = false;
-    for (int s = 0; s < nslots; ++s) {
-      const PowerSet &ps = c->sets[plans[s].n];
-      for (int k = 1; k <= plans[s].chain_top && !any; ++k) any = !ps.have.count(k);
-    }
+    for (int s = 0; s < nslots; ++s) any = any || k0[s] <= plans[s].chain_top;
     if (any) {
       if (!c->chain_start)
         TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_start, hipEventDisableTiming));
       TP_HIP_CHECK(hipEventRecord(c->chain_start, stream));
     }
-    for (int s = 0; s < nslots && any; ++s) {
+    for (int s = 0; s < nslots; ++s) {
       const Plan &p = plans[s];
       PowerSet &ps = c->sets[p.n];
-      int k0 = 1;
-      while (k0 <= p.chain_top && ps.have.count(k0)) ++k0;
-      if (k0 > p.chain_top) continue;
+      if (k0[s] > p.chain_top) continue;
       if (!c->chain_stream[s]) {
         TP_HIP_CHECK(hipStreamCreateWithFlags(&c->chain_stream[s], hipStreamNonBlocking));
         TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_done[s], hipEventDisableTiming));
       }
       hipStream_t cs = c->chain_stream[s];
       TP_HIP_CHECK(hipStreamWaitEvent(cs, c->chain_start, 0));
-      for (int k = k0; k <= p.chain_top; ++k) {
+      for (int k = k0[s]; k <= p.chain_top; ++k) {
         uint16_t *Y = (uint16_t *)ps.pw.at(k);
         if (k == 1)
           TP_HIP_CHECK(launch_dense_state(p.n, ps.N, p.view.masks, TP_U16, Y, ps.ld, cs));
@@ -496,10 +545,29 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
 
-  // 2. the persistent kernel's tasks.  Chain powers and resident powers are
-  // complete when it starts; a giant computed by this batch counts its
-  // finished tiles per 128-row block and per 128-column block
+  // completion counters of the powers the persistent kernel computes:
+  // fused chain levels (one per level, all tasks, and one per level and
+  // column panel), giants (one per 128-row block and one per 128-column block)
   int ncounters = 0;
+  std::vector<int> cbase(nslots, 0), pbase(nslots, 0), npan(nslots, 0), per_panel(nslots, 0);
+  std::vector<std::vector<int>> nchain(nslots);
+  if (fused) {
+    for (int s = 0; s < nslots; ++s) {
+      const int top = plans[s].chain_top;
+      npan[s] = (int)((c->sets[plans[s].n].N + kPanel - 1) / kPanel);
+      cbase[s] = ncounters;
+      ncounters += top + 1;
+      pbase[s] = ncounters;
+      ncounters += (top + 1) * npan[s];
+      nchain[s].assign(top + 1, 0);
+    }
+  }
+  auto chain_pending = [&](int s, int e) {
+    return fused && e >= k0[s] && e <= plans[s].chain_top;
+  };
+  auto panel_counter = [&](int s, int e, int64_t c0) {
+    return pbase[s] + e * npan[s] + (int)(c0 / kPanel);
+  };
   std::map<std::pair<int, int>, int> gbase;
   std::vector<int> nblk(nslots);
   for (int s = 0; s < nslots; ++s) {
@@ -513,19 +581,35 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
   auto is_new_giant = [&](int s, int e) { return gbase.count({s, e}) != 0; };
+  auto pending = [&](int s, int e) { return is_new_giant(s, e) || chain_pending(s, e); };
 
   std::vector<Task> tasks;
   // dependency on rows [r0, r0 + 128) (all columns) of exponent e
   auto rows_dep = [&](int s, int e, int64_t r0, int32_t *dep, int32_t *target) {
     auto it = gbase.find({s, e});
-    *dep = it == gbase.end() ? -1 : it->second + (int)(r0 / kGBM);
-    *target = it == gbase.end() ? 0 : nblk[s];
+    if (it != gbase.end()) {
+      *dep = it->second + (int)(r0 / kGBM);
+      *target = nblk[s];
+    } else if (chain_pending(s, e)) {
+      *dep = cbase[s] + e;
+      *target = nchain[s][e];
+    } else {
+      *dep = -1;
+      *target = 0;
+    }
   };
   // dependency on columns [c0, c0 + 128) (all rows) of exponent e
   auto cols_dep = [&](int s, int e, int64_t c0, int32_t *dep, int32_t *target) {
     auto it = gbase.find({s, e});
-    *dep = it == gbase.end() ? -1 : it->second + nblk[s] + (int)(c0 / kGBN);
-    *target = it == gbase.end() ? 0 : nblk[s];
+    if (it != gbase.end()) {
+      *dep = it->second + nblk[s] + (int)(c0 / kGBN);
+      *target = nblk[s];
+    } else if (chain_pending(s, e) && e >= 2) {
+      *dep = panel_counter(s, e, c0);
+      *target = per_panel[s];
+    } else {
+      rows_dep(s, e, 0, dep, target);
+    }
   };
 
   // a group of tasks (one giant product or one instance's traces) is dealt to
@@ -549,7 +633,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     std::vector<int> rest;
     for (int j : waiting[s]) {
       const int a = ta[j], b = tb[j];
-      const bool ready = (!is_new_giant(s, a) || a <= upto) && (!is_new_giant(s, b) || b <= upto);
+      const bool ready = (!pending(s, a) || a <= upto) && (!pending(s, b) || b <= upto);
       if (!ready) {
         rest.push_back(j);
         continue;
@@ -575,8 +659,100 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     waiting[s].swap(rest);
   };
 
-  // instances answered by chain or resident powers first
+  // instances answered by powers complete before the launch first
   for (int s = 0; s < nslots; ++s) push_ready_traces(s, 0);
+
+  if (fused) {
+    // each column panel's chain goes to one queue (its XCD keeps the panel
+    // of X in its L2 from level to level); panels are spread over the queues
+    // by their work, largest first, onto the least loaded queue
+    std::vector<std::vector<int>> pqueue(nslots);
+    {
+      struct Chain {
+        double work;
+        int s, p;
+      };
+      std::vector<Chain> chains;
+      for (int s = 0; s < nslots; ++s) {
+        const Plan &p = plans[s];
+        const int64_t N = c->sets[p.n].N;
+        pqueue[s].assign(npan[s], 0);
+        for (int P = 0; P < npan[s] && p.chain_top >= 2; ++P) {
+          const int64_t width = std::min<int64_t>(kPanel, N - (int64_t)P * kPanel);
+          chains.push_back({(double)p.view.nnz * (double)width * (double)(p.chain_top - 1), s, P});
+        }
+      }
+      std::stable_sort(chains.begin(), chains.end(),
+                       [](const Chain &a, const Chain &b) { return a.work > b.work; });
+      double load[kQueues] = {0};
+      for (const Chain &ch : chains) {
+        const int q = (int)(std::min_element(load, load + kQueues) - load);
+        load[q] += ch.work;
+        pqueue[ch.s][ch.p] = q;
+      }
+    }
+    // chain levels, level by level over all n
+    int max_top = 0;
+    for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
+    for (int k = 1; k <= max_top; ++k) {
+      for (int s = 0; s < nslots; ++s) {
+        const Plan &p = plans[s];
+        if (!chain_pending(s, k)) continue;
+        const int64_t N = c->sets[p.n].N;
+        const size_t first = tasks.size();
+        if (k == 1) {
+          // A^1 in row blocks over all columns
+          const int64_t rows =
+              std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)));
+          for (int64_t r0 = 0; r0 < N; r0 += rows) {
+            Task t{};
+            t.type = kBuild;
+            t.slot = s;
+            t.out = 1;
+            t.row0 = (int32_t)r0;
+            t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
+            t.c0 = 0;
+            t.c1 = (int32_t)N;
+            t.dep = t.dep2 = -1;
+            t.done = cbase[s] + 1;
+            t.done2 = -1;
+            tasks.push_back(t);
+            ++nchain[s][1];
+          }
+          deal(first);
+        } else {
+          const int rows = rows_of(c, p.n, N);
+          per_panel[s] = (int)((N + rows - 1) / rows);
+          // level k of panel P reads panel P of A^(k-1): that panel's counter
+          // when level k-1 is computed in this launch, the power's counter
+          // for A^1, nothing when it is resident
+          for (int64_t c0 = 0; c0 < N; c0 += kPanel) {
+            for (int64_t r0 = 0; r0 < N; r0 += rows) {
+              Task t{};
+              t.type = kSpmm;
+              t.slot = s;
+              t.out = k;
+              t.x = k - 1;
+              t.row0 = (int32_t)r0;
+              t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
+              t.c0 = (int32_t)c0;
+              t.c1 = (int32_t)std::min<int64_t>(c0 + kPanel, N);
+              cols_dep(s, k - 1, c0, &t.dep, &t.dep_target);
+              t.dep2 = -1;
+              t.done = panel_counter(s, k, c0);
+              t.done2 = cbase[s] + k;
+              t.queue = pqueue[s][c0 / kPanel];
+              tasks.push_back(t);
+              ++nchain[s][k];
+            }
+          }
+        }
+      }
+      for (int s = 0; s < nslots; ++s)
+        if (k <= plans[s].chain_top) push_ready_traces(s, k);
+    }
+  }
+
   // giants in increasing exponent, interleaved over n; a giant's two factors
   // have smaller exponents and are queued before it
   std::vector<std::vector<int>> gl(nslots);
@@ -661,6 +837,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.n = p.n;
     sl.N = (int32_t)ps.N;
     sl.ld = ps.ld;
+    sl.full = (1u << p.n) - 1u;
+    sl.masks = p.view.masks;
+    sl.rowptr = p.view.rowptr;
+    sl.colz = p.view.colz;
     sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
     hs[s] = sl;
     for (size_t e = 0; e < ptr_stride; ++e) {
@@ -788,6 +968,16 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
     c->grid_override = (int)value;
     return TP_OK;
   }
+  if (param == TP_PARAM_FUSED_CHAIN) {
+    TP_REQUIRE(value == 0 || value == 1, "TP_PARAM_FUSED_CHAIN is 0 or 1");
+    c->fused = (int)value;
+    return TP_OK;
+  }
+  if (param >= TP_PARAM_SPMM_ROWS && param < TP_PARAM_SPMM_ROWS + 16) {
+    TP_REQUIRE(value >= 0 && value <= 65536, "rows per task out of range");
+    c->spmm_rows[param - TP_PARAM_SPMM_ROWS] = (int)(value + 3) / 4 * 4;
+    return TP_OK;
+  }
   if (param >= TP_PARAM_BABY_STEPS && param < TP_PARAM_BABY_STEPS + 16) {
     const int n = param - TP_PARAM_BABY_STEPS;
     TP_REQUIRE(value >= 0 && value <= (1 << 16), "baby steps out of range");
@@ -880,11 +1070,14 @@ int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *
   return batch_run(c, count, n, m, gamma2_dev, stream);
 }
 
-int tp_tune_batch(int n, int baby_steps) {
+int tp_tune_batch(int n, int baby_steps, int fused_baby_steps) {
   TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
-  TP_REQUIRE(baby_steps >= 0 && baby_steps <= (1 << 16), "baby steps out of range");
+  TP_REQUIRE(baby_steps >= 0 && baby_steps <= (1 << 16) && fused_baby_steps >= 0 &&
+                 fused_baby_steps <= (1 << 16),
+             "baby steps out of range");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned_baby[n] = baby_steps;
+  g_tuned_baby[0][n] = baby_steps;
+  g_tuned_baby[1][n] = fused_baby_steps;
   return TP_OK;
 }
 

@@ -38,5 +38,6 @@ def apply_tuning(path: str | None = None, table: dict | None = None) -> bool:
     for n, form in table.get("step", {}).items():
         tp.tp_tune_step(int(n), int(form))
     for n, vals in table.get("batch", {}).items():
-        tp.tp_tune_batch(int(n), int(vals[0]))
+        # [baby steps, seconds] or [baby steps, seconds, fused baby steps, seconds]
+        tp.tp_tune_batch(int(n), int(vals[0]), int(vals[2]) if len(vals) >= 4 else 0)
     return True

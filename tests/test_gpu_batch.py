@@ -129,6 +129,54 @@ def test_abort_path_forced_from_host(tp, oracle_table):
         tp.tp_ctx_destroy(ctx)
 
 
+def test_fused_mode_any_task_grain(tp, oracle_table):
+    # chain levels as tasks of the one persistent launch, at several task
+    # sizes and a small grid, and the abort path in that mode
+    inst = synth.batch_instances(seed=12, count=24)
+    want = [int(oracle_table[n][m - 1]) for n, m in inst]
+    for rows, grid in ((4, 37), (16, 0), (100, 8)):
+        ctx = tp.tp_ctx_create(64 << 30)
+        try:
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_GRID, grid)
+            for n in range(4, 10):
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_SPMM_ROWS + n, rows)
+            assert _run(tp, ctx, inst) == want, (rows, grid)
+            # a second batch on the same context: everything resident
+            assert _run(tp, ctx, inst) == want, (rows, grid, "warm")
+        finally:
+            tp.tp_ctx_destroy(ctx)
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_WAIT_LIMIT_US, 0)
+        few = [(9, 60), (8, 41), (6, 30)]
+        tp.tp_batch_power_trace(ctx, [n for n, _ in few], [m for _, m in few])
+        with pytest.raises(tp.TropicalError) as e:
+            tp.tp_ctx_check(ctx)
+        assert e.value.status == tp.TP_ECANCELED
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_WAIT_LIMIT_US, 20_000_000)
+        assert _run(tp, ctx, few) == [int(oracle_table[n][m - 1]) for n, m in few]
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_fused_and_split_modes_share_resident_powers(tp, oracle_table):
+    # powers computed in one mode answer the next batch in the other
+    inst = synth.batch_instances(seed=13, count=16)
+    want = [int(oracle_table[n][m - 1]) for n, m in inst]
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
+        assert _run(tp, ctx, inst[:8]) == want[:8]
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 0)
+        assert _run(tp, ctx, inst) == want
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
+        assert _run(tp, ctx, inst[::-1]) == want[::-1]
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
 def test_grid_and_step_form_do_not_change_results(tp, oracle_table):
     # persistent grids from the minimum (one workgroup per queue) to the
     # whole chip, and both forms of the chain's sparse step

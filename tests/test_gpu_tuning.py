@@ -48,7 +48,7 @@ def _reset_tables(tp):
     tp.tp_tune_gemm(tp.TP_U16, -1)
     tp.tp_tune_gemm(tp.TP_U8, -1)
     for n in range(1, 13):
-        tp.tp_tune_batch(n, 0)
+        tp.tp_tune_batch(n, 0, 0)
         tp.tp_tune_planner(n, 0.0, 0.0)
         tp.tp_tune_step(n, tp.TP_STEP_AUTO)
     tp.apply_tuning()
@@ -137,7 +137,7 @@ def test_tuning_table_choice_and_clear(tp):
         with pytest.raises(tp.TropicalError):
             tp.tp_tune_planner(4, 0.0, 1.0)
         with pytest.raises(tp.TropicalError):
-            tp.tp_tune_batch(13, 8)
+            tp.tp_tune_batch(13, 8, 8)
     finally:
         tp.tp_tune_gemm(tp.TP_U16, -1)
         tp.apply_tuning()
@@ -152,7 +152,7 @@ def test_tuned_defaults_do_not_change_results(tp, oracle_mod):
         tp.tp_tune_gemm(tp.TP_U16, 1 << 40, 3, 8)
         for n in range(4, 9):
             tp.tp_tune_planner(n, 1e9, 1e14)  # dense products look cheap: more of them
-            tp.tp_tune_batch(n, 5)
+            tp.tp_tune_batch(n, 5, 3)
             tp.tp_tune_step(n, tp.TP_STEP_BLOCKED if n % 2 else tp.TP_STEP_CSR)
         A = synth.stress_matrix(300, 900, 21, 0, 1000, 0.4, np.uint16)
         B = synth.stress_matrix(900, 200, 22, 0, 1000, 0.4, np.uint16)

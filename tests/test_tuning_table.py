@@ -32,8 +32,11 @@ def test_table_is_well_formed(table):
         assert 1 <= int(n) <= 12 and spmm > 0 and gemm > 0
     for n, form in table["step"].items():
         assert 1 <= int(n) <= 12 and form in (tp.TP_STEP_CSR, tp.TP_STEP_BLOCKED)
-    for n, (baby, t) in table["batch"].items():
-        assert 1 <= int(n) <= 12 and baby >= 1 and t > 0
+    for n, vals in table["batch"].items():
+        assert 1 <= int(n) <= 12 and len(vals) in (2, 4)
+        assert vals[0] >= 1 and vals[1] > 0
+        if len(vals) == 4:
+            assert vals[2] >= 1 and vals[3] > 0
 
 
 def test_loaded_table_drives_the_default_choice(table):
@@ -52,7 +55,7 @@ def test_loaded_table_drives_the_default_choice(table):
         tp.tp_tune_gemm(tp.TP_U16, -1)
         tp.tp_tune_gemm(tp.TP_U8, -1)
         for n in range(1, 13):
-            tp.tp_tune_batch(n, 0)
+            tp.tp_tune_batch(n, 0, 0)
             tp.tp_tune_planner(n, 0.0, 0.0)
             tp.tp_tune_step(n, tp.TP_STEP_AUTO)
         tuning.apply_tuning()
