@@ -175,6 +175,92 @@ __global__ void __launch_bounds__(256) block_step_kernel(int64_t N, const int64_
   }
 }
 
+// The same step for 16-byte aligned rows at least ncols rounded up to 8 long
+// (the library's own padded powers): rows are read as whole 16-byte chunks
+// and the next U entries' rows are requested before the current U are
+// applied, so two rounds of gathers are in flight.  A last partial round
+// repeats the block's last entry with an empty row mask, which changes
+// nothing.
+template <int U>
+__global__ void __launch_bounds__(256) block_step_pipe_kernel(
+    int64_t N, const int64_t *__restrict__ bptr, const uint64_t *__restrict__ ent,
+    const uint16_t *__restrict__ X, int64_t ldx, uint16_t *__restrict__ Y, int64_t ldy,
+    int64_t ncols) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t groups = (nblocks + 3) / 4;
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t panel = t / groups;
+  const int64_t b = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (b >= nblocks) return;
+  const int64_t c0 = (panel * 64 + lane) * 8;
+  const kconst_i64 bp = (kconst_i64)bptr;
+  const kconst_u64 en = (kconst_u64)ent;
+  const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
+  const int64_t ld4 = ldx / 8;
+  const uint32_t off = (uint32_t)(c0 / 8);
+
+  u16x2 acc[kRows][4];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[r][k] = splat(0xFFFFu);
+
+  const int64_t e0 = bp[b], e1 = bp[b + 1];
+  if (e0 < e1) {
+    const int64_t last = e1 - 1;
+    auto fetch = [&](int64_t i, uint64_t (&w)[U], u32x4 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = i + u;
+        const uint64_t x = en[k < last ? k : last];
+        w[u] = k <= last ? x : (x & 0xFFFFFFFFull);  // past the end: no rows
+        v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ld4 + off];
+      }
+    };
+    auto apply = [&](const uint64_t (&w)[U], const u32x4 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const u16x2 row[4] = {as_pk(v[u].x), as_pk(v[u].y), as_pk(v[u].z), as_pk(v[u].w)};
+        apply_entry(acc, (uint32_t)(w[u] >> 32), splat((uint16_t)((w[u] >> 24) & 0xFFu)), row);
+      }
+    };
+    uint64_t wa[U], wb[U];
+    u32x4 va[U], vb[U];
+    fetch(e0, wa, va);
+    for (int64_t i = e0;;) {
+      bool more = i + U <= last;
+      if (more) fetch(i + U, wb, vb);
+      apply(wa, va);
+      i += U;
+      if (!more) break;
+      more = i + U <= last;
+      if (more) fetch(i + U, wa, va);
+      apply(wb, vb);
+      i += U;
+      if (!more) break;
+    }
+  }
+  if (c0 >= ncols) return;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    if (q >= N) break;
+    const u16x2 *a = acc[r];
+    if (c0 + 8 <= ncols) {
+      *(gmut<u32x4>)(to_global_mut(Y) + q * ldy + c0) =
+          u32x4{as_u32(a[0]), as_u32(a[1]), as_u32(a[2]), as_u32(a[3])};
+    } else {
+      const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (c0 + 2 * k < ncols) y[2 * k] = a[k].x;
+        if (c0 + 2 * k + 1 < ncols) y[2 * k + 1] = a[k].y;
+      }
+    }
+  }
+}
+
 hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t *ent,
                                  const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
                                  int64_t ncols, hipStream_t s) {
@@ -184,7 +270,10 @@ hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t 
   const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
   const bool vec = (ldx % VE == 0) && (ldy % VE == 0) && ((uintptr_t)X % 16 == 0) &&
                    ((uintptr_t)Y % 16 == 0);
-  if (vec)
+  if (vec && ldx >= (ncols + 7) / 8 * 8)
+    hipLaunchKernelGGL((block_step_pipe_kernel<4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
+                       Y, ldy, ncols);
+  else if (vec)
     hipLaunchKernelGGL((block_step_kernel<true, 4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
                        Y, ldy, ncols);
   else
