@@ -291,8 +291,8 @@ struct Ctx {
   int g_grid = 0;
   hipEvent_t staged = nullptr;
   // chain levels run on one stream per slot, between two events on the caller's stream
-  hipStream_t chain_stream[16] = {nullptr};
-  hipEvent_t chain_start = nullptr, chain_done[16] = {nullptr};
+  hipStream_t chain_stream[kMaxSlots] = {nullptr};
+  hipEvent_t chain_start = nullptr, chain_done[kMaxSlots] = {nullptr};
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
   int baby[16] = {0};               // baby steps by n; 0 = automatic
   int fused = 0;                    // chain levels inside the persistent launch
@@ -915,6 +915,11 @@ void ctx_free(Ctx *c) {
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->staged) (void)hipEventDestroy(c->staged);
+  if (c->chain_start) (void)hipEventDestroy(c->chain_start);
+  for (int s = 0; s < kMaxSlots; ++s) {
+    if (c->chain_done[s]) (void)hipEventDestroy(c->chain_done[s]);
+    if (c->chain_stream[s]) (void)hipStreamDestroy(c->chain_stream[s]);
+  }
   for (auto &kv : c->sets)
     for (void *slab : kv.second.slabs) (void)hipFree(slab);
   Buf *dev[] = {&c->d_tasks, &c->d_slots, &c->d_ptrs, &c->d_counters, &c->d_results, &c->d_ctl};
