@@ -117,6 +117,10 @@ def test_abort_path_forced_from_host(tp, oracle_table):
     ctx = tp.tp_ctx_create(64 << 30)
     try:
         tp.tp_ctx_set_param(ctx, tp.TP_PARAM_WAIT_LIMIT_US, 0)
+        # few baby steps, so that these instances need giants built from
+        # giants (tasks that wait), whatever the tuning table says
+        for n in (6, 8, 9):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 4)
         inst = [(9, 60), (8, 41), (6, 30)]
         tp.tp_batch_power_trace(ctx, [n for n, _ in inst], [m for _, m in inst])
         with pytest.raises(tp.TropicalError) as e:
@@ -150,6 +154,8 @@ def test_fused_mode_any_task_grain(tp, oracle_table):
     try:
         tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
         tp.tp_ctx_set_param(ctx, tp.TP_PARAM_WAIT_LIMIT_US, 0)
+        for n in (6, 8, 9):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 4)
         few = [(9, 60), (8, 41), (6, 30)]
         tp.tp_batch_power_trace(ctx, [n for n, _ in few], [m for _, m in few])
         with pytest.raises(tp.TropicalError) as e:
