@@ -270,7 +270,10 @@ hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t 
   const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
   const bool vec = (ldx % VE == 0) && (ldy % VE == 0) && ((uintptr_t)X % 16 == 0) &&
                    ((uintptr_t)Y % 16 == 0);
-  if (vec && ldx >= (ncols + 7) / 8 * 8)
+  // the pipelined kernel wins while the gathered rows' latency bounds the
+  // step (n <= 10: 0.30 vs 0.52 ms at n = 9); from n = 11 on cache bandwidth
+  // does, and the plain one is 2 % faster (n = 12: 53.4 vs 54.5 ms)
+  if (vec && ldx >= (ncols + 7) / 8 * 8 && N < 16384)
     hipLaunchKernelGGL((block_step_pipe_kernel<4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
                        Y, ldy, ncols);
   else if (vec)
