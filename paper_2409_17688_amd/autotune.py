@@ -44,7 +44,7 @@ from .tuning import DEFAULT_TABLE, apply_gemm_rows, apply_tuning  # noqa: F401
 KSPLITS = (1, 2, 4, 8, 16)
 # candidates in this order; a later one must be faster by more than TIE to
 # replace the best so far (large tiles first: they win near-ties at large N)
-CONFIG_ORDER = (1, 2, 0, 3)
+CONFIG_ORDER = (4, 1, 2, 0, 3)
 TIE = 0.01
 
 

@@ -87,7 +87,7 @@ struct Config {
 };
 
 // Tile configurations, in the order the autotuner and the parity tests see them.
-constexpr Config kConfigs[] = {{128, 128}, {128, 256}, {256, 128}, {64, 64}};
+constexpr Config kConfigs[] = {{128, 128}, {128, 256}, {256, 128}, {64, 64}, {256, 256}};
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 // Launches the product with S K-slices of kslice columns each (S = 1: no
@@ -140,6 +140,9 @@ hipError_t launch_typed(int64_t M, int64_t N, int64_t K, const T *A, int64_t lda
     case 2:
       return launch_one<256, 128, 32, 16, 8, 3, T>(M, N, K, A, lda, B, ldb, C, ldc, accumulate, S,
                                                    kslice, W, ldw, stride, s);
+    case 4:
+      return launch_one<256, 256, 32, 16, 16, 2, T>(M, N, K, A, lda, B, ldb, C, ldc, accumulate,
+                                                    S, kslice, W, ldw, stride, s);
     default:
       return launch_one<64, 64, 32, 4, 4, 4, T>(M, N, K, A, lda, B, ldb, C, ldc, accumulate, S,
                                                 kslice, W, ldw, stride, s);
