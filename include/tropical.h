@@ -251,10 +251,10 @@ int tp_ctx_destroy(void *ctx);
 #define TP_PARAM_WAIT_LIMIT_US 1 /* bound on one dependency wait (default 20 s) */
 #define TP_PARAM_GRID 2          /* workgroups of the persistent kernel (>= 8); 0 = fill the chip */
 #define TP_PARAM_FUSED_CHAIN 3   /* 1: chain levels run inside the persistent launch too (one
-                                    launch per batch); 0 (default): as full-chip launches on
-                                    one stream per n ahead of it, which is faster */
-#define TP_PARAM_SPMM_ROWS 16    /* TP_PARAM_SPMM_ROWS + n: fused mode, rows per chain task;
-                                    0 = about 64 row blocks per panel */
+                                    launch per batch, levels separated by barriers over the
+                                    grid, which then never exceeds what the chip holds);
+                                    0 (default): as full-chip launches on one stream per n
+                                    ahead of it */
 #define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
                                     n >= 8, else 32); fixed once powers of n are resident */
 int tp_ctx_set_param(void *ctx, int param, int64_t value);
@@ -277,7 +277,8 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
  * `stream`), then, on `stream`, the missing giant products and one trace per
  * instance as one dependency-ordered task list run by one persistent kernel
  * launch from a captured hipGraph; with TP_PARAM_FUSED_CHAIN the chain levels
- * are tasks of that one launch too.  Returns without waiting.
+ * run first inside that one launch, level by level with a barrier over the
+ * grid between levels.  Returns without waiting.
  * TP_ENOMEM when the needed powers exceed the context's budget (nothing is
  * queued).  Results of a batch are valid after tp_ctx_check returns TP_OK. */
 int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,

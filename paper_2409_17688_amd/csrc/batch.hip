@@ -25,21 +25,23 @@
 //      before it and fills the chip on its own, which a share of a
 //      persistent kernel does not.
 //   fused (TP_PARAM_FUSED_CHAIN)  everything, chain levels included, runs
-//      in the one persistent launch.
+//      in the one persistent launch: it first runs the chain level by level
+//      (level k of every n that lacks A^k together), each level spread over
+//      the whole grid one (row, 512-column panel) item per wave, with a
+//      barrier over the grid between levels; then the task list below.  The
+//      barrier needs every workgroup resident at once, so this mode never
+//      launches more workgroups than the chip holds; a batch that cannot get
+//      them all (the chip shared with other work that waits too) ends at
+//      the wait limit like any other stuck wait.
 // The persistent kernel runs a list of tasks in dependency order:
-//   BUILD  rows of A^1 = A(D_n)                          (fused mode)
-//   SPMM   rows x one 512-column panel of A^k = A x A^(k-1)  (fused mode)
 //   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
 //   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
 //          instance's result with an atomic min
 // Dependencies are as narrow as the arithmetic allows, each a completion
-// counter and a target count: column panel P of A x X needs column panel P
-// of X only, so a chain level waits for the same panel of the level before
-// (and a panel's whole chain is dealt to one queue, whose XCD keeps that
-// panel of X in its L2); a product tile (rows R, columns C) and a trace block
-// (rows I) read rows R (I) of the left factor and columns C (I) of the right
-// one, so a giant counts its finished tiles per 128-row and per 128-column
-// block; the rest waits for whole powers.
+// counter and a target count: a product tile (rows R, columns C) and a trace
+// block (rows I) read rows R (I) of the left factor and columns C (I) of the
+// right one, so a giant counts its finished tiles per 128-row and per
+// 128-column block; chain powers are complete before the first task.
 // The list is split into 8 queues, one per XCD, each keeping the list's
 // order; a giant's tiles and an instance's trace blocks go to the queues in
 // contiguous chunks.  Workgroups pop their own XCD's queue first (one atomic
@@ -68,7 +70,7 @@ namespace tp {
 
 namespace {
 
-enum : int32_t { kBuild = 0, kSpmm = 1, kGemm = 2, kTrace = 3 };
+enum : int32_t { kGemm = 2, kTrace = 3 };
 
 struct Task {
   int32_t type, slot;
@@ -99,11 +101,30 @@ struct Control {
   int32_t qbeg[kQueues];   // first task of each queue in the task array
   int32_t qcnt[kQueues];   // tasks in each queue
   int32_t abort;           // set when a wait exceeded the limit
-  int32_t pad;
+  int32_t nlevels;         // fused mode: chain levels run before the tasks
   int64_t wait_limit;      // in s_memrealtime ticks (100 MHz)
 };
 
 constexpr int kMaxSlots = 16;
+
+// Fused mode: one chain level (exponent k) of every slot that needs it; its
+// work items are (row, 512-column panel) pairs, panel-major per slot, the
+// i-th slot's being [begin[i], begin[i+1]).
+struct Level {
+  int32_t count, k;
+  int32_t slot[kMaxSlots];
+  int64_t begin[kMaxSlots + 1];
+};
+// Level barrier counters at the start of the counter array, each on a
+// 256-byte line of its own (atomics on one line serialize): workgroups per
+// XCC, then the registrations, then arrivals per XCC and the XCCs done.  The
+// arrival counters only grow: level L is complete at (L + 1) x the count.
+constexpr int kLine = 64;  // int32 per line
+constexpr int kMaxXcc = 16;
+constexpr int kRegTotal = kMaxXcc, kArrive = kMaxXcc + 1, kXccDone = 2 * kMaxXcc + 1;
+constexpr int kLevelCounters = (2 * kMaxXcc + 2) * kLine;
+// XCC_ID hardware register (bits 3:0): which XCD, and so which L2, a wave is on
+constexpr int kHwRegXccId = (3 << 11) | 20;
 constexpr uint16_t kInf = 0xFFFFu;
 constexpr int kPanel = 512;                       // columns of an SPMM task: 64 lanes x 8
 constexpr int kGBM = 128, kGBN = 128, kGBK = 32;  // dense product tile
@@ -113,7 +134,11 @@ __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
 }
 
 // Thread 0: wait until counters[dep] >= target.  Returns 0 when the batch
-// was aborted (by this wait timing out or by another workgroup).
+// was aborted (by this wait timing out or by another workgroup).  Task waits
+// pause long between polls (hundreds of waiting workgroups polling one
+// counter would otherwise crowd out the task pops and increments); barrier
+// waits, which every workgroup enters at about the same time, poll often.
+template <bool kBarrier = false>
 __device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, int target,
                                            Control *ctl, int64_t limit) {
   if (dep < 0) return 1;
@@ -124,9 +149,10 @@ __device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, in
       __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return 0;
     }
-    // a long pause between polls: hundreds of waiting workgroups polling
-    // one counter would otherwise crowd out the task pops and increments
-    __builtin_amdgcn_s_sleep(127);  // ~8000 clocks
+    if (kBarrier)
+      __builtin_amdgcn_s_sleep(4);  // ~256 clocks
+    else
+      __builtin_amdgcn_s_sleep(127);  // ~8000 clocks
   }
   return 1;
 }
@@ -134,12 +160,13 @@ __device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, in
 __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl,
                                                        const Task *__restrict__ tasks,
                                                        const Slot *__restrict__ slots,
+                                                       const Level *__restrict__ levels,
                                                        int32_t *__restrict__ counters,
                                                        int32_t *__restrict__ results) {
   // one LDS arena: the dense product's A and B slabs, or a trace's Y tile
   __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kGBK * kGBM + 2 * kGBK * kGBN];
   __shared__ int32_t part[4];
-  __shared__ int32_t s_task, s_go, s_fresh;
+  __shared__ int32_t s_task, s_go;
   int acq_dep = -1, acq_dep2 = -1;  // dependencies this workgroup has acquired (thread 0)
   const int64_t limit = ctl->wait_limit;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -147,6 +174,91 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
   // XCD b mod 8 and serves that queue first; when it is empty it takes tasks
   // from the others, always in each queue's own order
   const int home = blockIdx.x % kQueues;
+
+  // Fused mode: the chain levels first, level by level over all slots, every
+  // workgroup taking a share of each level's (row, panel) items (one per
+  // wave), with a barrier over the grid after each level.  Making a level's
+  // rows visible to the other XCDs takes a write-back of the L2 holding
+  // them; one per XCC and level is enough: every wave waits for its own
+  // stores to reach its L2, the workgroup counts itself on its XCC's
+  // arrival counter, and the last arrival of an XCC (the workgroups per XCC
+  // are counted once at the start) writes that L2 back and counts the XCC.
+  // Every workgroup then waits (bounded) until all XCCs are in and acquires.
+  const int nlev = ctl->nlevels;
+  if (nlev > 0) {
+    __shared__ int32_t s_on_xcc, s_xccs;
+    const int xcc = (int)(__builtin_amdgcn_s_getreg(kHwRegXccId) & (kMaxXcc - 1));
+    if (threadIdx.x == 0) {
+      __hip_atomic_fetch_add(&counters[xcc * kLine], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&counters[kRegTotal * kLine], 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      (void)wait_counter<true>(counters, kRegTotal * kLine, (int)gridDim.x, ctl, limit);
+      int xccs = 0;
+      for (int x = 0; x < kMaxXcc; ++x) xccs += ld_relaxed(&counters[x * kLine]) > 0;
+      s_on_xcc = ld_relaxed(&counters[xcc * kLine]);
+      s_xccs = xccs;
+    }
+    __syncthreads();
+    const int on_xcc = s_on_xcc, xccs = s_xccs;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    for (int L = 0; L < nlev; ++L) {
+      if (ld_relaxed(&ctl->abort) == 0) {
+        const Level &lv = levels[L];
+        const int64_t total = lv.begin[lv.count];
+        for (int64_t item = (int64_t)blockIdx.x * 4 + wv; item < total;
+             item += (int64_t)gridDim.x * 4) {
+          int i = 0;
+          while (i + 1 < lv.count && item >= lv.begin[i + 1]) ++i;
+          const Slot sl = slots[lv.slot[i]];
+          const int64_t N = sl.N, ld = sl.ld;
+          const int64_t l = item - lv.begin[i];
+          const int64_t panel = l / N, q = l - panel * N;
+          const int64_t c0 = panel * kPanel + (int64_t)lane * 8;
+          if (c0 >= N) {
+            // lanes past the last column of the last panel (their loads
+            // would leave X's rows)
+          } else if (lv.k >= 2) {
+            gather_row_colz<6>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, sl.powers[lv.k - 1],
+                               ld, sl.powers[lv.k], ld, N, q, c0);
+          } else {
+            // A^1: row q, this lane's 8 columns
+            const uint32_t mq = sl.masks[q];
+            uint16_t e[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int64_t p = c0 + j;
+              const uint32_t mp = p < N ? sl.masks[p] : 0u;
+              e[j] = (p < N && can_follow(mq, mp, sl.full))
+                         ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
+                         : kInf;
+            }
+            uint16_t *row = sl.powers[1] + q * ld + c0;
+            if (c0 + 8 <= N) {
+              *(gmut<u32x4>)to_global_mut(row) = u32x4{
+                  (uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                  (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+            } else {
+              for (int j = 0; j < 8 && c0 + j < N; ++j) row[j] = e[j];
+            }
+          }
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are in its L2
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int before = __hip_atomic_fetch_add(&counters[(kArrive + xcc) * kLine], 1,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (before + 1 == on_xcc * (L + 1)) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_fetch_add(&counters[kXccDone * kLine], 1, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+        (void)wait_counter<true>(counters, kXccDone * kLine, xccs * (L + 1), ctl, limit);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+    }
+  }
   while (true) {
     if (threadIdx.x == 0) {
       int t = -1;
@@ -166,10 +278,13 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
         fresh = (d1 != acq_dep || d2 != acq_dep2);
         acq_dep = d1;
         acq_dep2 = d2;
+        // the powers this task reads are final once its counters are
+        // complete; one acquire per new dependency makes them visible (it
+        // invalidates the CU's L1, which the workgroup's waves share)
+        if (go && fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       s_task = t;
       s_go = go;
-      s_fresh = fresh;
     }
     __syncthreads();
     // uniform across the workgroup: the task record is read with scalar loads
@@ -178,31 +293,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
     if (t < 0) break;
     const Task task = tasks[t];
     if (go) {
-      // the powers this task reads are final once their counters are
-      // complete; acquiring once per new dependency makes them visible
-      if (s_fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const Slot sl = slots[task.slot];
       const int64_t N = sl.N, ld = sl.ld;
-      if (task.type == kSpmm) {
-        const uint16_t *X = sl.powers[task.x];
-        uint16_t *Y = sl.powers[task.out];
-        for (int64_t q = task.row0 + wave; q < task.row1; q += 4) {
-          const int64_t qu = __builtin_amdgcn_readfirstlane((int)q);
-          for (int64_t c0 = task.c0 + (int64_t)lane * 8; c0 < task.c1; c0 += kPanel)
-            gather_row_colz<6>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, X, ld, Y, ld, N, qu,
-                               c0);
-        }
-      } else if (task.type == kBuild) {
-        uint16_t *out = sl.powers[1];
-        const int64_t rows = task.row1 - task.row0;
-        for (int64_t idx = threadIdx.x; idx < rows * N; idx += blockDim.x) {
-          const int64_t q = task.row0 + idx / N, p = idx - (idx / N) * N;
-          const uint32_t mp = sl.masks[p];
-          out[q * ld + p] = can_follow(sl.masks[q], mp, sl.full)
-                                ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
-                                : kInf;
-        }
-      } else if (task.type == kGemm) {
+      if (task.type == kGemm) {
         gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
             (int)N, (int)N, (int)N, sl.powers[task.x], ld,
             sl.powers[task.y], ld, sl.powers[task.out], ld, 0, task.row0,
@@ -220,7 +313,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
         const int32_t best = block_min(acc, part);
         if (threadIdx.x == 0 && best < (int32_t)kInf) atomicMin(&results[task.inst], best);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // a task others wait for: every wave's stores reach its L2 before the
+      // workgroup's one release (an L2 write-back) and count
+      if (task.done >= 0) __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();  // also keeps the LDS arena from being reused too early
     if (threadIdx.x == 0 && task.done >= 0) {
@@ -282,11 +377,11 @@ struct Ctx {
   int device = 0;
   size_t budget = 0, used = 0;
   std::map<int, PowerSet> sets;
-  Buf d_tasks, d_slots, d_ptrs, d_counters, d_results, d_ctl;
-  Buf h_tasks, h_slots, h_ptrs, h_ctl;
+  Buf d_tasks, d_slots, d_ptrs, d_counters, d_results, d_ctl, d_levels;
+  Buf h_tasks, h_slots, h_ptrs, h_ctl, h_levels;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
-  void *g_key[3] = {nullptr, nullptr, nullptr};
+  void *g_key[4] = {nullptr, nullptr, nullptr, nullptr};
   size_t g_counter_cap = 0, g_result_cap = 0;
   int g_grid = 0;
   hipEvent_t staged = nullptr;
@@ -296,7 +391,6 @@ struct Ctx {
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
   int baby[16] = {0};               // baby steps by n; 0 = automatic
   int fused = 0;                    // chain levels inside the persistent launch
-  int spmm_rows[16] = {0};          // fused mode: rows per chain task by n; 0 = automatic
   int grid_override = 0;
   bool pending = false;                      // a batch was queued and not yet checked
   std::map<int, std::set<int>> pending_new;  // exponents that batch computes, by n
@@ -311,15 +405,6 @@ std::mutex g_tune_mu;
 int g_tuned_baby[2][16] = {{0}};  // [fused mode][n]
 
 int auto_baby(int n) { return n >= 8 ? 16 : 32; }
-
-// Fused mode: rows per chain task, about 64 row blocks per panel and level
-// (measured: larger blocks leave workgroups idle at the end of a level,
-// smaller ones spend more of each task on its pop, wait and release).
-int rows_of(const Ctx *c, int n, int64_t N) {
-  if (c->spmm_rows[n] > 0) return c->spmm_rows[n];
-  const int64_t r = (N / 64 + 3) / 4 * 4;
-  return (int)std::max<int64_t>(8, std::min<int64_t>(r, 64));
-}
 
 // largest power of two <= j
 int pow2_floor(int j) {
@@ -393,7 +478,8 @@ int capture_graph(Ctx *c, int grid) {
                      (int32_t *)c->d_results.p, nr, (int32_t)kInf);
   hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(256), 0, c->cap_stream, (Control *)c->d_ctl.p,
                      (const Task *)c->d_tasks.p, (const Slot *)c->d_slots.p,
-                     (int32_t *)c->d_counters.p, (int32_t *)c->d_results.p);
+                     (const Level *)c->d_levels.p, (int32_t *)c->d_counters.p,
+                     (int32_t *)c->d_results.p);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -403,6 +489,7 @@ int capture_graph(Ctx *c, int grid) {
   c->g_key[0] = c->d_tasks.p;
   c->g_key[1] = c->d_counters.p;
   c->g_key[2] = c->d_results.p;
+  c->g_key[3] = c->d_levels.p;
   c->g_counter_cap = c->d_counters.bytes;
   c->g_result_cap = c->d_results.bytes;
   c->g_grid = grid;
@@ -545,29 +632,31 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
 
-  // completion counters of the powers the persistent kernel computes:
-  // fused chain levels (one per level, all tasks, and one per level and
-  // column panel), giants (one per 128-row block and one per 128-column block)
-  int ncounters = 0;
-  std::vector<int> cbase(nslots, 0), pbase(nslots, 0), npan(nslots, 0), per_panel(nslots, 0);
-  std::vector<std::vector<int>> nchain(nslots);
+  // fused mode: the missing chain levels as a level table the persistent
+  // kernel runs first, level k over every slot that lacks A^k; each level
+  // ends in a barrier over the grid, so the tasks below see complete powers
+  // in both modes
+  std::vector<Level> levels;
   if (fused) {
-    for (int s = 0; s < nslots; ++s) {
-      const int top = plans[s].chain_top;
-      npan[s] = (int)((c->sets[plans[s].n].N + kPanel - 1) / kPanel);
-      cbase[s] = ncounters;
-      ncounters += top + 1;
-      pbase[s] = ncounters;
-      ncounters += (top + 1) * npan[s];
-      nchain[s].assign(top + 1, 0);
+    int max_top = 0;
+    for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
+    for (int k = 1; k <= max_top; ++k) {
+      Level lv{};
+      lv.k = k;
+      for (int s = 0; s < nslots; ++s) {
+        if (k < k0[s] || k > plans[s].chain_top) continue;
+        const int64_t N = c->sets[plans[s].n].N;
+        lv.slot[lv.count] = s;
+        lv.begin[lv.count + 1] = lv.begin[lv.count] + N * ((N + kPanel - 1) / kPanel);
+        ++lv.count;
+      }
+      if (lv.count > 0) levels.push_back(lv);
     }
   }
-  auto chain_pending = [&](int s, int e) {
-    return fused && e >= k0[s] && e <= plans[s].chain_top;
-  };
-  auto panel_counter = [&](int s, int e, int64_t c0) {
-    return pbase[s] + e * npan[s] + (int)(c0 / kPanel);
-  };
+  // completion counters: the level barriers first, then the giants (one per
+  // 128-row block and one per 128-column block)
+  const int ncounters0 = levels.empty() ? 0 : kLevelCounters;
+  int ncounters = 0;
   std::map<std::pair<int, int>, int> gbase;
   std::vector<int> nblk(nslots);
   for (int s = 0; s < nslots; ++s) {
@@ -581,7 +670,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     }
   }
   auto is_new_giant = [&](int s, int e) { return gbase.count({s, e}) != 0; };
-  auto pending = [&](int s, int e) { return is_new_giant(s, e) || chain_pending(s, e); };
+  auto pending = [&](int s, int e) { return is_new_giant(s, e); };
 
   std::vector<Task> tasks;
   // dependency on rows [r0, r0 + 128) (all columns) of exponent e
@@ -590,9 +679,6 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     if (it != gbase.end()) {
       *dep = it->second + (int)(r0 / kGBM);
       *target = nblk[s];
-    } else if (chain_pending(s, e)) {
-      *dep = cbase[s] + e;
-      *target = nchain[s][e];
     } else {
       *dep = -1;
       *target = 0;
@@ -604,9 +690,6 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     if (it != gbase.end()) {
       *dep = it->second + nblk[s] + (int)(c0 / kGBN);
       *target = nblk[s];
-    } else if (chain_pending(s, e) && e >= 2) {
-      *dep = panel_counter(s, e, c0);
-      *target = per_panel[s];
     } else {
       rows_dep(s, e, 0, dep, target);
     }
@@ -662,97 +745,6 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   // instances answered by powers complete before the launch first
   for (int s = 0; s < nslots; ++s) push_ready_traces(s, 0);
 
-  if (fused) {
-    // each column panel's chain goes to one queue (its XCD keeps the panel
-    // of X in its L2 from level to level); panels are spread over the queues
-    // by their work, largest first, onto the least loaded queue
-    std::vector<std::vector<int>> pqueue(nslots);
-    {
-      struct Chain {
-        double work;
-        int s, p;
-      };
-      std::vector<Chain> chains;
-      for (int s = 0; s < nslots; ++s) {
-        const Plan &p = plans[s];
-        const int64_t N = c->sets[p.n].N;
-        pqueue[s].assign(npan[s], 0);
-        for (int P = 0; P < npan[s] && p.chain_top >= 2; ++P) {
-          const int64_t width = std::min<int64_t>(kPanel, N - (int64_t)P * kPanel);
-          chains.push_back({(double)p.view.nnz * (double)width * (double)(p.chain_top - 1), s, P});
-        }
-      }
-      std::stable_sort(chains.begin(), chains.end(),
-                       [](const Chain &a, const Chain &b) { return a.work > b.work; });
-      double load[kQueues] = {0};
-      for (const Chain &ch : chains) {
-        const int q = (int)(std::min_element(load, load + kQueues) - load);
-        load[q] += ch.work;
-        pqueue[ch.s][ch.p] = q;
-      }
-    }
-    // chain levels, level by level over all n
-    int max_top = 0;
-    for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
-    for (int k = 1; k <= max_top; ++k) {
-      for (int s = 0; s < nslots; ++s) {
-        const Plan &p = plans[s];
-        if (!chain_pending(s, k)) continue;
-        const int64_t N = c->sets[p.n].N;
-        const size_t first = tasks.size();
-        if (k == 1) {
-          // A^1 in row blocks over all columns
-          const int64_t rows =
-              std::max<int64_t>(1, std::min<int64_t>(N, 262144 / std::max<int64_t>(N, 1)));
-          for (int64_t r0 = 0; r0 < N; r0 += rows) {
-            Task t{};
-            t.type = kBuild;
-            t.slot = s;
-            t.out = 1;
-            t.row0 = (int32_t)r0;
-            t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
-            t.c0 = 0;
-            t.c1 = (int32_t)N;
-            t.dep = t.dep2 = -1;
-            t.done = cbase[s] + 1;
-            t.done2 = -1;
-            tasks.push_back(t);
-            ++nchain[s][1];
-          }
-          deal(first);
-        } else {
-          const int rows = rows_of(c, p.n, N);
-          per_panel[s] = (int)((N + rows - 1) / rows);
-          // level k of panel P reads panel P of A^(k-1): that panel's counter
-          // when level k-1 is computed in this launch, the power's counter
-          // for A^1, nothing when it is resident
-          for (int64_t c0 = 0; c0 < N; c0 += kPanel) {
-            for (int64_t r0 = 0; r0 < N; r0 += rows) {
-              Task t{};
-              t.type = kSpmm;
-              t.slot = s;
-              t.out = k;
-              t.x = k - 1;
-              t.row0 = (int32_t)r0;
-              t.row1 = (int32_t)std::min<int64_t>(r0 + rows, N);
-              t.c0 = (int32_t)c0;
-              t.c1 = (int32_t)std::min<int64_t>(c0 + kPanel, N);
-              cols_dep(s, k - 1, c0, &t.dep, &t.dep_target);
-              t.dep2 = -1;
-              t.done = panel_counter(s, k, c0);
-              t.done2 = cbase[s] + k;
-              t.queue = pqueue[s][c0 / kPanel];
-              tasks.push_back(t);
-              ++nchain[s][k];
-            }
-          }
-        }
-      }
-      for (int s = 0; s < nslots; ++s)
-        if (k <= plans[s].chain_top) push_ready_traces(s, k);
-    }
-  }
-
   // giants in increasing exponent, interleaved over n; a giant's two factors
   // have smaller exponents and are queued before it
   std::vector<std::vector<int>> gl(nslots);
@@ -800,6 +792,18 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       return TP_EINVAL;
     }
 
+  // counters in memory: the level barrier's first, then one 256-byte line
+  // per task counter (atomics and polls on one line serialize)
+  const int cfirst = ncounters0;
+  auto phys = [&](int32_t ix) { return ix < 0 ? ix : (int32_t)(cfirst + ix * kLine); };
+  for (Task &t : tasks) {
+    t.dep = phys(t.dep);
+    t.dep2 = phys(t.dep2);
+    t.done = phys(t.done);
+    t.done2 = phys(t.done2);
+  }
+  const int64_t counter_words = (int64_t)cfirst + (int64_t)ncounters * kLine;
+
   // queues: each keeps the dependency order of the whole list
   std::vector<Task> ordered;
   ordered.reserve(tasks.size());
@@ -824,8 +828,14 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   TP_HIP_CHECK(grow(c->d_slots, kMaxSlots * sizeof(Slot)));
   TP_HIP_CHECK(grow(c->d_ptrs, nptr * sizeof(void *)));
   TP_HIP_CHECK(grow(c->d_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max(ncounters, 1) * sizeof(int32_t)));
+  TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max<int64_t>(counter_words, 1) * sizeof(int32_t)));
   TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t)));
+  const size_t lbytes = levels.size() * sizeof(Level);
+  if (lbytes) {
+    TP_HIP_CHECK(grow_host(c->h_levels, lbytes));
+    TP_HIP_CHECK(grow(c->d_levels, lbytes));
+    memcpy(c->h_levels.p, levels.data(), lbytes);
+  }
 
   memcpy(c->h_tasks.p, tasks.data(), tbytes);
   Slot *hs = (Slot *)c->h_slots.p;
@@ -855,12 +865,16 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     hc->qcnt[q] = qcnt[q];
   }
   hc->abort = 0;
-  hc->pad = 0;
+  hc->nlevels = (int32_t)levels.size();
   hc->wait_limit = c->wait_limit;
 
-  const int grid = c->grid_override > 0 ? c->grid_override : default_grid();
+  // the level barriers need every workgroup resident at once: a fused batch
+  // with chain levels never launches more than the chip holds
+  const int resident = default_grid();
+  int grid = c->grid_override > 0 ? c->grid_override : resident;
+  if (!levels.empty()) grid = std::min(grid, resident);
   if (!c->exec || c->g_key[0] != c->d_tasks.p || c->g_key[1] != c->d_counters.p ||
-      c->g_key[2] != c->d_results.p || c->g_grid != grid ||
+      c->g_key[2] != c->d_results.p || c->g_key[3] != c->d_levels.p || c->g_grid != grid ||
       c->g_counter_cap != c->d_counters.bytes || c->g_result_cap != c->d_results.bytes) {
     const int rc = capture_graph(c, grid);
     if (rc != TP_OK) return rc;
@@ -872,6 +886,9 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
                               hipMemcpyHostToDevice, stream));
   TP_HIP_CHECK(hipMemcpyAsync(c->d_ctl.p, c->h_ctl.p, sizeof(Control), hipMemcpyHostToDevice,
                               stream));
+  if (lbytes)
+    TP_HIP_CHECK(hipMemcpyAsync(c->d_levels.p, c->h_levels.p, lbytes, hipMemcpyHostToDevice,
+                                stream));
   if (!c->staged) TP_HIP_CHECK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
   TP_HIP_CHECK(hipEventRecord(c->staged, stream));
   TP_HIP_CHECK(hipGraphLaunch(c->exec, stream));
@@ -922,10 +939,11 @@ void ctx_free(Ctx *c) {
   }
   for (auto &kv : c->sets)
     for (void *slab : kv.second.slabs) (void)hipFree(slab);
-  Buf *dev[] = {&c->d_tasks, &c->d_slots, &c->d_ptrs, &c->d_counters, &c->d_results, &c->d_ctl};
+  Buf *dev[] = {&c->d_tasks,   &c->d_slots, &c->d_ptrs,  &c->d_counters,
+                &c->d_results, &c->d_ctl,   &c->d_levels};
   for (Buf *b : dev)
     if (b->p) (void)hipFree(b->p);
-  Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl};
+  Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl, &c->h_levels};
   for (Buf *b : host)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -976,11 +994,6 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
   if (param == TP_PARAM_FUSED_CHAIN) {
     TP_REQUIRE(value == 0 || value == 1, "TP_PARAM_FUSED_CHAIN is 0 or 1");
     c->fused = (int)value;
-    return TP_OK;
-  }
-  if (param >= TP_PARAM_SPMM_ROWS && param < TP_PARAM_SPMM_ROWS + 16) {
-    TP_REQUIRE(value >= 0 && value <= 65536, "rows per task out of range");
-    c->spmm_rows[param - TP_PARAM_SPMM_ROWS] = (int)(value + 3) / 4 * 4;
     return TP_OK;
   }
   if (param >= TP_PARAM_BABY_STEPS && param < TP_PARAM_BABY_STEPS + 16) {
