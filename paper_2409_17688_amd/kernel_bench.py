@@ -50,6 +50,8 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--config", type=int, default=None, help="dense product tile config")
     ap.add_argument("--instances", default="mixed64", help="batch workload: mixed64 or n:mlist")
+    ap.add_argument("--fused", action="store_true",
+                    help="batch: chain levels inside the persistent launch too")
     args = ap.parse_args(argv)
 
     import torch
@@ -97,6 +99,7 @@ def main(argv=None):
         for _ in range(args.reps):
             ctx = tp.tp_ctx_create(64 << 30)
             try:
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, int(args.fused))
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 tp.tp_batch_power_trace(ctx, ns, ms)
@@ -104,7 +107,7 @@ def main(argv=None):
                 times.append(time.perf_counter() - t0)
             finally:
                 tp.tp_ctx_destroy(ctx)
-        out.update({"instances": len(inst), "ms": min(times) * 1e3,
+        out.update({"instances": len(inst), "fused": args.fused, "ms": min(times) * 1e3,
                     "ms_all": [round(t * 1e3, 2) for t in times]})
     print(json.dumps(out), flush=True)
 
