@@ -233,6 +233,61 @@ int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t 
 int tp_release_cache(void);
 
 /* ------------------------------------------------------------------------ */
+/* Recurrence of the powers: Lemma 1, Theorem 3, Algorithms 3, 4 and 5.      */
+/* ------------------------------------------------------------------------ */
+
+/* Matrix constant difference (Algorithm 3's test, exact reading): X and Y
+ * (u16, N x N) differ by a constant when they have the same INF entries and
+ * every finite entry of X is the matching entry of Y plus one common b, i.e.
+ * X = b (x) Y.  d_out (device int32[2]) receives {min, max} of the finite
+ * differences X - Y: min == max == b when it holds; min > max (INT32_MAX,
+ * INT32_MIN) when no entry is finite (it holds with b = 0); min < max when it
+ * fails (INF patterns that differ count as -2^30 and 2^30).  Needs ldx == ldy,
+ * a multiple of 8, and 16-byte aligned X and Y.  Reads 2 N^2 entries once
+ * (HBM bound); its small work buffer is stream-ordered (hipMallocAsync). */
+int tp_const_diff(int64_t N, const void *d_X, int64_t ldx, const void *d_Y, int64_t ldy,
+                  int32_t *d_out, hipStream_t stream);
+
+/* Result of tp_recurrence (all exponents are powers of A = A(D_n)). */
+typedef struct tp_recurrence {
+  int32_t found;        /* 1: A^(r0 + a) = b (x) A^r0 among A^1 .. A^K               */
+  int32_t window_short; /* 1: not found, and pairs Algorithm 3 would examine before
+                           giving up lay beyond the window                           */
+  int32_t K;            /* powers computed                                           */
+  int32_t window;       /* each A^k was compared with A^(k-1) .. A^(k-window)         */
+  int64_t r0, a, b;     /* Algorithm 3: the first pair (i, j) = (r0 + a, r0), i from K
+                           down, j from i - 1 down, with A^i = b (x) A^j (Table 3)    */
+  int64_t n0;           /* Algorithm 4: least n0 such that A^(k + a) = b (x) A^k for
+                           n0 <= k <= r0, going down from r0 (Table 4)               */
+} tp_recurrence_t;
+
+/* Computes A^1 .. A^K of A(D_n) (1 <= n <= 13) by the chain of sparse left
+ * products (Algorithm 2), keeping only the last window + 1 powers on the
+ * device; compares each A^k with A^(k-d), 1 <= d <= min(window, k - 1), by
+ * tp_const_diff, and writes diag_min_host[k - 1] = min_i (A^k)_ii for
+ * k = 1..K (host int32[K]; Algorithm 5's boundary values, gamma_2(P_n x C_k)
+ * for k >= 3 by Theorem 2).  Then runs Algorithms 3 and 4 on the comparison
+ * table into *out.  Algorithm 3's result equals the paper's exactly when it is
+ * found at i = K (every smaller distance was compared) or when window =
+ * K - 1 (every pair was); otherwise found = 0 and window_short = 1.
+ * 2 <= K <= 65535; 0 <= window <= 256, where 0 picks min(K - 1, 256) when
+ * those powers fit in free device memory, else the most that fit.  Device
+ * memory: (window + 1) N x round64(N) u16 powers, allocated and freed by the
+ * call, plus the state of n (process-wide cache).  Blocks until done.
+ * TP_EOVERFLOW when n * K >= 65535; TP_ENOMEM when an explicit window does
+ * not fit. */
+int tp_recurrence(int n, int K, int window, tp_recurrence_t *out, int32_t *diag_min_host,
+                  hipStream_t stream);
+
+/* gamma_2(P_n x C_m) for any m >= 3 from a recurrence and its boundary values
+ * (host only, no device work): diag_min[m - 1] when m <= K, else, when the
+ * recurrence was found, Theorem 3's finite difference equation solved from
+ * its start: gamma_2(n0 + r + q a) = gamma_2(n0 + r) + q b with 0 <= r < a.
+ * TP_EINVAL for m < 3, or m > K without a recurrence. */
+int tp_gamma2_recurrence(const tp_recurrence_t *rec, const int32_t *diag_min, int64_t m,
+                         int64_t *gamma2);
+
+/* ------------------------------------------------------------------------ */
 /* Batching: many (n, m) instances per call, one persistent launch each.     */
 /* ------------------------------------------------------------------------ */
 

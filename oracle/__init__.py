@@ -75,6 +75,8 @@ def _load():
     lib.oracle_power.restype = ctypes.c_int64
     lib.oracle_recurrence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int32, i64p]
     lib.oracle_recurrence.restype = ctypes.c_int
+    lib.oracle_constant_difference.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_int32, i64p]
+    lib.oracle_constant_difference.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
     lib.brute_is_2dominating.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
@@ -184,6 +186,19 @@ def recurrence(n: int, K: int = 50, inf: int = INF16):
     if ok != 1:
         return None
     return tuple(int(v) for v in out)
+
+
+def constant_difference(X: np.ndarray, Y: np.ndarray, inf: int = INF16):
+    """(holds, b) of Algorithm 3's test: X = b (x) Y exactly, i.e. the same INF
+    entries and one common difference b over the finite ones (b = 0 when no
+    entry is finite)."""
+    X = np.ascontiguousarray(X, dtype=np.int32)
+    Y = np.ascontiguousarray(Y, dtype=np.int32)
+    if X.shape != Y.shape:
+        raise ValueError("X and Y must have one shape")
+    b = ctypes.c_int64(0)
+    ok = _load().oracle_constant_difference(X.size, _i32(X), _i32(Y), inf, ctypes.byref(b))
+    return bool(ok), int(b.value)
 
 
 def threads() -> int:

@@ -263,6 +263,14 @@ static int constant_difference(int64_t cnt, const int32_t *X, const int32_t *Y,
     return 1;
 }
 
+/* The same test for callers: X and Y hold cnt entries each (row-major,
+ * contiguous).  Returns 1 and writes *b_out when X = b (x) Y, else 0. */
+int oracle_constant_difference(int64_t cnt, const int32_t *X, const int32_t *Y, int32_t inf,
+                               int64_t *b_out)
+{
+    return constant_difference(cnt, X, Y, inf, b_out);
+}
+
 /* Algorithms 3 and 4 on the first K powers.
  * Algorithm 3: for i = K down to 1, for j = i-1 down to 1, the first pair with
  * A^i = b x A^j gives a = i - j, b, r0 = j.

@@ -42,6 +42,20 @@ if not os.path.exists(LIB_PATH):
 
 lib = ctypes.CDLL(LIB_PATH)
 
+
+class Recurrence(ctypes.Structure):
+    """tp_recurrence_t: A^(r0 + a) = b (x) A^r0 (Algorithm 3) from n0 on
+    (Algorithm 4), found among the K powers compared `window` back."""
+    _fields_ = [("found", ctypes.c_int32), ("window_short", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("r0", ctypes.c_int64), ("a", ctypes.c_int64), ("b", ctypes.c_int64),
+                ("n0", ctypes.c_int64)]
+
+    def __repr__(self):
+        return (f"Recurrence(found={self.found}, window_short={self.window_short}, K={self.K}, "
+                f"window={self.window}, r0={self.r0}, a={self.a}, b={self.b}, n0={self.n0})")
+
+
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i = ctypes.c_int
@@ -73,6 +87,11 @@ _SIGS = {
     "tp_sparse_trace_of_product": ([_i, _i64, _p, _p, _p, _p, _i64, _p, _p], _i),
     "tp_tropical_power_trace": ([_i, _i64, ctypes.POINTER(ctypes.c_int32), _p], _i),
     "tp_release_cache": ([], _i),
+    "tp_const_diff": ([_i64, _p, _i64, _p, _i64, _p, _p], _i),
+    "tp_recurrence": ([_i, _i, _i, ctypes.POINTER(Recurrence), ctypes.POINTER(ctypes.c_int32),
+                       _p], _i),
+    "tp_gamma2_recurrence": ([ctypes.POINTER(Recurrence), ctypes.POINTER(ctypes.c_int32), _i64,
+                              ctypes.POINTER(_i64)], _i),
     "tp_ctx_create": ([ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)], _i),
     "tp_ctx_destroy": ([_p], _i),
     "tp_ctx_set_param": ([_p, _i, _i64], _i),
@@ -364,6 +383,50 @@ def tp_tropical_power_trace(n: int, m: int, stream=None) -> int:
     res = ctypes.c_int32(-1)
     _check(lib.tp_tropical_power_trace(n, m, ctypes.byref(res), _stream(stream)))
     return int(res.value)
+
+
+def tp_const_diff(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """out (device int32[2]) = {min, max} of the finite entries of X - Y, see
+    the C declaration for the INF cases."""
+    if X.dtype != torch.uint16 or Y.dtype != torch.uint16:
+        raise TypeError("X and Y must be uint16")
+    px, N, N2, ldx = _mat(X, "X")
+    py, N3, N4, ldy = _mat(Y, "Y")
+    if not (N == N2 == N3 == N4):
+        raise ValueError("X and Y must be square of one size")
+    # the row stride as allocated, also for one row (the kernel reads rows in
+    # 16-byte chunks of one common leading dimension)
+    ldx, ldy = max(X.stride(0), N), max(Y.stride(0), N)
+    if out is None:
+        out = torch.empty(2, dtype=torch.int32, device=X.device)
+    _check(lib.tp_const_diff(N, px, ldx, py, ldy, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def tp_recurrence(n: int, K: int = 50, window: int = 0, stream=None):
+    """(Recurrence, diag_min) for A(D_n)^1 .. A(D_n)^K; diag_min[k - 1] =
+    min_i (A^k)_ii, a host int32 array.  Blocks until done."""
+    import numpy as np
+    rec = Recurrence()
+    diag = np.zeros(max(int(K), 1), dtype=np.int32)
+    _check(lib.tp_recurrence(int(n), int(K), int(window), ctypes.byref(rec),
+                             diag.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             _stream(stream)))
+    return rec, diag
+
+
+def tp_gamma2_recurrence(rec: Recurrence, diag_min, m: int) -> int:
+    """gamma_2(P_n x C_m) for any m >= 3 from tp_recurrence's results (host)."""
+    import numpy as np
+    diag = np.ascontiguousarray(diag_min, dtype=np.int32)
+    if diag.ndim != 1 or diag.shape[0] < rec.K:
+        raise ValueError(f"diag_min must hold the {rec.K} diagonal minima")
+    out = ctypes.c_int64(0)
+    _check(lib.tp_gamma2_recurrence(ctypes.byref(rec),
+                                    diag.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    int(m), ctypes.byref(out)))
+    return int(out.value)
 
 
 def tp_release_cache() -> None:

@@ -156,7 +156,7 @@ double g_gemm_rate[13] = {0, 1e9, 1e9, 1e10, 5e10, 1e11, 3e11, 2e12,
 // built-in rule, row blocks from n = 11 on, where they were measured faster:
 // at n = 12 53 ms against 101 ms per step; the CSR gather wins up to n = 10).
 // Guarded by g_mu.
-int g_step_form[13] = {0};
+int g_step_form[14] = {0};  // n = 1..13
 
 int step_form(int n, int form) {
   if (form != TP_STEP_AUTO) return form;
