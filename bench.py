@@ -178,9 +178,33 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_suite:
         line["queries"] = query_suite(tp, synth)
+        line["recurrence"] = recurrence_suite(tp)
     if args.serve:
         line["serving"] = serve_suite(tp, synth)
     print(json.dumps(line), flush=True)
+
+
+# Total running time of the paper's whole pipeline (50 powers, Algorithms 3,
+# 4 and 5) in its fastest version, by path order (Table 7), in seconds.
+PAPER_TOTAL_S = {8: 0.6, 9: 3.5, 10: 32.5, 11: 6 * 60 + 32, 12: 3600 + 29 * 60 + 58}
+
+
+def recurrence_suite(tp):
+    """The recurrence of the powers (Algorithms 3, 4 and 5 on K = 50 powers)
+    by path order: wall time of tp_recurrence with the state already built,
+    the recurrence found (Tables 3 and 4), and the paper's total time."""
+    import torch
+    out = {}
+    for n, window in ((8, 0), (9, 0), (10, 0), (11, 6), (12, 4)):
+        tp.tp_recurrence(n, 3, 1)  # the state of n in the library's cache
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec, _ = tp.tp_recurrence(n, 50, window)
+        t = time.perf_counter() - t0
+        out[str(n)] = {"K": 50, "window": rec.window, "seconds": round(t, 4),
+                       "r0": rec.r0, "a": rec.a, "b": rec.b, "n0": rec.n0,
+                       "paper_total_seconds": PAPER_TOTAL_S[n]}
+    return out
 
 
 def serve_suite(tp, synth, count=2000):

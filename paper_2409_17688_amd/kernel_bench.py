@@ -6,6 +6,8 @@
     python -m paper_2409_17688_amd.kernel_bench --op trace --n 12
     python -m paper_2409_17688_amd.kernel_bench --op gemm --n 10 --config 0
     python -m paper_2409_17688_amd.kernel_bench --op batch --instances mixed64
+    python -m paper_2409_17688_amd.kernel_bench --op cdiff --n 12
+    python -m paper_2409_17688_amd.kernel_bench --op recurrence --n 12 --window 4
 
 Matrices use the library's resident layout (rows padded to 64 entries).
 Times come from HIP events on the launch stream; one JSON line per run with
@@ -16,6 +18,10 @@ the algorithmic work of one launch:
   trace  2 N^2 entries read (4 N^2 bytes)
   gemm   N^3 (min,+) operations
   batch  one persistent launch answering the instances (cold context)
+  cdiff  constant-difference test of A^2 against A (tp_const_diff): 2 N^2
+         entries read (4 N^2 bytes)
+  recurrence  tp_recurrence(n, K, window): K powers, each compared with the
+         window before it, then Algorithms 3 and 4 (wall time)
 """
 from __future__ import annotations
 
@@ -45,13 +51,16 @@ def _padded(torch, N):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", choices=["spmm", "bstep", "gather", "trace", "gemm", "batch"], required=True)
+    ap.add_argument("--op", choices=["spmm", "bstep", "gather", "trace", "gemm", "batch", "cdiff",
+                                     "recurrence"], required=True)
     ap.add_argument("--n", type=int, default=10)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--config", type=int, default=None, help="dense product tile config")
     ap.add_argument("--instances", default="mixed64", help="batch workload: mixed64 or n:mlist")
     ap.add_argument("--fused", action="store_true",
                     help="batch: chain levels inside the persistent launch too")
+    ap.add_argument("--K", type=int, default=50, help="recurrence: powers computed")
+    ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
     args = ap.parse_args(argv)
 
     import torch
@@ -59,7 +68,18 @@ def main(argv=None):
     from . import _lib as tp
     n = args.n
     out = {"op": args.op}
-    if args.op in ("spmm", "bstep", "gather", "trace", "gemm"):
+    if args.op == "recurrence":
+        tp.tp_recurrence(n, 3, 1)  # the state of n in the library's cache
+        times = []
+        for _ in range(args.reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rec, _ = tp.tp_recurrence(n, args.K, args.window)
+            times.append(time.perf_counter() - t0)
+        out.update({"n": n, "K": args.K, "window": rec.window, "found": rec.found, "r0": rec.r0,
+                    "a": rec.a, "b": rec.b, "n0": rec.n0, "s": min(times),
+                    "s_all": [round(t, 3) for t in times]})
+    elif args.op in ("spmm", "bstep", "gather", "trace", "gemm", "cdiff"):
         N = tp.tp_state_dim(n)
         X, Y = _padded(torch, N), _padded(torch, N)
         tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
@@ -74,6 +94,10 @@ def main(argv=None):
             form = tp.TP_STEP_BLOCKED if args.op == "bstep" else tp.TP_STEP_CSR
             t = _events(torch, lambda: tp.tp_state_left_mul(n, X, Y, form=form), args.reps)
             out.update({"nnz": nnz, "ms": t * 1e3, "Tminplus_ops": nnz * N / t / 1e12})
+        elif args.op == "cdiff":
+            tp.tp_state_left_mul(n, X, Y)
+            t = _events(torch, lambda: tp.tp_const_diff(Y, X), args.reps)
+            out.update({"ms": t * 1e3, "GBs": 4.0 * N * N / t / 1e9})
         elif args.op == "trace":
             tp.tp_minplus_spmm(*tp.tp_build_state_csr(n), X, Y)
             t = _events(torch, lambda: tp.tp_trace_of_product(X, Y), args.reps)
