@@ -28,7 +28,7 @@ namespace tp {
 namespace {
 
 constexpr int kMaxCmp = 8;           // earlier powers compared in one pass
-constexpr int kCmpBlocks = 1024;     // workgroups of one pass (4 rows each at a time)
+constexpr int kCmpBlocks = 2048;     // workgroups of one pass (4 rows each at a time)
 constexpr int32_t kMismatch = 1 << 30;
 constexpr int kMaxWindow = 256;      // earlier powers each power is compared with, at most
 
@@ -72,19 +72,35 @@ __global__ void __launch_bounds__(256) const_diff_kernel(int64_t N, const uint16
   }
   const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
   const int64_t ld8 = ld / 8, chunks = (N + 7) / 8;
+  // kUnroll chunks per lane per round, their loads issued before any is used
+  constexpr int kUnroll = 4;
   for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < N; r += (int64_t)gridDim.x * 4) {
-    for (int64_t c = lane; c < chunks; c += 64) {
-      const int64_t off = r * ld8 + c;
-      const int valid = N - c * 8 < 8 ? (int)(N - c * 8) : 8;
-      const u32x4 xv = Xg[off];
+    for (int64_t c0 = lane; c0 < chunks; c0 += 64 * kUnroll) {
+      u32x4 xv[kUnroll];
+      int valid[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t c = c0 + 64 * u;
+        valid[u] = c >= chunks ? 0 : (N - c * 8 < 8 ? (int)(N - c * 8) : 8);
+        xv[u] = c < chunks ? Xg[r * ld8 + c] : u32x4{0u, 0u, 0u, 0u};
+      }
 #pragma unroll
       for (int d = 0; d < kMaxCmp; ++d) {
         if (d < nd) {
-          const u32x4 yv = ((gconst<u32x4>)to_global(set.y[d]))[off];
-          fold_pair(xv.x, yv.x, valid, mn[d], mx[d]);
-          fold_pair(xv.y, yv.y, valid - 2, mn[d], mx[d]);
-          fold_pair(xv.z, yv.z, valid - 4, mn[d], mx[d]);
-          fold_pair(xv.w, yv.w, valid - 6, mn[d], mx[d]);
+          const gconst<u32x4> Yg = (gconst<u32x4>)to_global(set.y[d]);
+          u32x4 yv[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int64_t c = c0 + 64 * u;
+            yv[u] = c < chunks ? Yg[r * ld8 + c] : u32x4{0u, 0u, 0u, 0u};
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            fold_pair(xv[u].x, yv[u].x, valid[u], mn[d], mx[d]);
+            fold_pair(xv[u].y, yv[u].y, valid[u] - 2, mn[d], mx[d]);
+            fold_pair(xv[u].z, yv[u].z, valid[u] - 4, mn[d], mx[d]);
+            fold_pair(xv[u].w, yv[u].w, valid[u] - 6, mn[d], mx[d]);
+          }
         }
       }
     }

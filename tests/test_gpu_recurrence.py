@@ -167,3 +167,21 @@ def test_recurrence_rejects_bad_arguments(tp):
     assert lib.tp_recurrence(5, 70000, 0, ctypes.byref(rec), diag, None) == tp.TP_EINVAL
     assert lib.tp_recurrence(5, 50, 257, ctypes.byref(rec), diag, None) == tp.TP_EINVAL
     assert lib.tp_recurrence(12, 6000, 0, ctypes.byref(rec), diag, None) == tp.TP_EOVERFLOW
+
+
+def test_n13_beyond_the_papers_gpu(tp):
+    """n = 13 (N = 131,562; 34.6 GB per power, which the paper could not fit):
+    parity unpinned, so only properties.  Lemma 1 read on the diagonal: once
+    the powers repeat with (a, b) from n0 on, so do their diagonal minima;
+    Theorem 3's solution agrees with the computed minima; and the paper's
+    conjecture gamma_2 = (n + 2) m / 3 for m = 0 (mod 3) (Section 4)."""
+    say("recurrence 13")
+    rec, diag = tp.tp_recurrence(13, 50, 3)
+    assert rec.K == 50 and rec.window == 3
+    if rec.found:
+        for m in range(rec.n0, 51 - rec.a):
+            assert diag[m + rec.a - 1] == diag[m - 1] + rec.b, m
+        for m in range(3, 51):
+            assert tp.tp_gamma2_recurrence(rec, diag, m) == diag[m - 1]
+    for m in range(3, 51, 3):
+        assert diag[m - 1] == 15 * m // 3, m
