@@ -232,6 +232,35 @@ int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t 
 /* Frees the process-wide cache used by tp_tropical_power_trace. */
 int tp_release_cache(void);
 
+/* Start states pruned by the cycle's rotation symmetry.  A closed walk of
+ * length m visits m states whose zero counts add up to its label (Theorem 2),
+ * so an optimal walk passes through a state with at most floor(gamma_2 / m)
+ * zeros and may start there: gamma_2 = min over the states i with at most
+ * floor(gamma_2 / m) zeros of (A^m)_ii, computed from the columns i of the
+ * powers only.  tp_tropical_power_trace uses it when its cost model says so
+ * (first with a guessed bound k, then, if the value found allows more zeros,
+ * once more with floor(value / m)). */
+
+/* Indices (ascending, int32) of the states of A(D_n) with at most max_zeros
+ * zeros, into d_idx (device, room for cap; may be NULL to count only), queued
+ * on `stream`.  Returns the count or a negative status. */
+int64_t tp_state_select(int n, int max_zeros, int32_t *d_idx, int64_t cap, hipStream_t stream);
+
+/* d_X (u16, N x count, leading dimension ldx >= count, N = tp_state_dim(n))
+ * = the columns d_idx[0..count) of A(D_n); an index outside 0..N-1 gives a
+ * column of INF. */
+int tp_build_state_columns(int n, const int32_t *d_idx, int64_t count, void *d_X, int64_t ldx,
+                           hipStream_t stream);
+
+/* *d_out (device int32) = min_j d_X[d_idx[j]][j] over j < count whose index
+ * lies in 0..N-1 (u16 X with N rows, ldx >= count); INF when there is none. */
+int tp_diag_select_min(int64_t N, int64_t count, const int32_t *d_idx, const void *d_X,
+                       int64_t ldx, int32_t *d_out, hipStream_t stream);
+
+/* How tp_tropical_power_trace uses pruned start states: 0 = when its cost
+ * model prefers it (default), 1 = always, -1 = never.  Changes no result. */
+int tp_tune_prune(int mode);
+
 /* ------------------------------------------------------------------------ */
 /* Recurrence of the powers: Lemma 1, Theorem 3, Algorithms 3, 4 and 5.      */
 /* ------------------------------------------------------------------------ */

@@ -87,6 +87,10 @@ _SIGS = {
     "tp_sparse_trace_of_product": ([_i, _i64, _p, _p, _p, _p, _i64, _p, _p], _i),
     "tp_tropical_power_trace": ([_i, _i64, ctypes.POINTER(ctypes.c_int32), _p], _i),
     "tp_release_cache": ([], _i),
+    "tp_state_select": ([_i, _i, _p, _i64, _p], _i64),
+    "tp_build_state_columns": ([_i, _p, _i64, _p, _i64, _p], _i),
+    "tp_diag_select_min": ([_i64, _i64, _p, _p, _i64, _p, _p], _i),
+    "tp_tune_prune": ([_i], _i),
     "tp_const_diff": ([_i64, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_recurrence": ([_i, _i, _i, ctypes.POINTER(Recurrence), ctypes.POINTER(ctypes.c_int32),
                        _p], _i),
@@ -427,6 +431,55 @@ def tp_gamma2_recurrence(rec: Recurrence, diag_min, m: int) -> int:
                                     diag.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                     int(m), ctypes.byref(out)))
     return int(out.value)
+
+
+def tp_state_select(n: int, max_zeros: int, stream=None) -> torch.Tensor:
+    """Device int32 indices of the states of A(D_n) with at most max_zeros zeros."""
+    cnt = _check(lib.tp_state_select(int(n), int(max_zeros), None, 0, _stream(stream)))
+    out = torch.empty(max(cnt, 1), dtype=torch.int32, device="cuda")
+    _check(lib.tp_state_select(int(n), int(max_zeros), out.data_ptr(), out.numel(),
+                               _stream(stream)))
+    return out[:cnt]
+
+
+def tp_build_state_columns(n: int, idx: torch.Tensor, out: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+    """Columns idx of A(D_n) (u16, N x len(idx))."""
+    if idx.dtype != torch.int32 or not idx.is_cuda or idx.dim() != 1:
+        raise TypeError("idx must be a 1-D device int32 tensor")
+    idx = idx.contiguous()
+    N, cnt = tp_state_dim(n), idx.numel()
+    if out is None:
+        ld = max((cnt + 63) // 64 * 64, 64)
+        out = torch.empty((N, ld), dtype=torch.uint16, device="cuda")[:, :cnt]
+    px, rows, cols, ldx = _mat(out, "out")
+    if (rows, cols) != (N, cnt) or out.dtype != torch.uint16:
+        raise ValueError(f"out must be a ({N}, {cnt}) uint16 matrix")
+    _check(lib.tp_build_state_columns(int(n), idx.data_ptr(), cnt, px, max(out.stride(0), cnt),
+                                      _stream(stream)))
+    return out
+
+
+def tp_diag_select_min(X: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """out (device int32[1]) = min_j X[idx[j], j]."""
+    if X.dtype != torch.uint16:
+        raise TypeError("X must be uint16")
+    if idx.dtype != torch.int32 or not idx.is_cuda or idx.dim() != 1:
+        raise TypeError("idx must be a 1-D device int32 tensor")
+    idx = idx.contiguous()
+    px, rows, cols, ldx = _mat(X, "X")
+    if cols < idx.numel():
+        raise ValueError("X has fewer columns than idx has entries")
+    out = _scalar_out(out)
+    _check(lib.tp_diag_select_min(rows, idx.numel(), idx.data_ptr(), px,
+                                  max(X.stride(0) if rows else 0, idx.numel()), out.data_ptr(),
+                                  _stream(stream)))
+    return out
+
+
+def tp_tune_prune(mode: int) -> None:
+    _check(lib.tp_tune_prune(int(mode)))
 
 
 def tp_release_cache() -> None:

@@ -17,6 +17,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -78,6 +79,9 @@ struct State {
   DevBuf bptr, bent;  // blocked form of A(D_n), 16 rows per block
   int64_t nent = 0;
   bool csr_ready = false;
+  std::vector<uint8_t> zh;                // zero counts on the host
+  std::map<int, DevBuf> sel;              // states with <= k zeros (device int32), by k
+  std::map<int, int64_t> sel_count;
 };
 
 struct Workspace {
@@ -131,6 +135,9 @@ int get_state(int n, hipStream_t s, State **out) {
     TP_HIP_CHECK(ensure(st.bent, (size_t)std::max<int64_t>(nent, 1) * sizeof(uint64_t)));
     TP_HIP_CHECK(launch_block_fill(N, n, (const uint32_t *)st.masks.ptr,
                                    (const int64_t *)st.bptr.ptr, (uint64_t *)st.bent.ptr, s));
+    st.zh.assign((size_t)N, 0);
+    TP_HIP_CHECK(hipMemcpyAsync(st.zh.data(), st.z.ptr, (size_t)N, hipMemcpyDeviceToHost, s));
+    TP_HIP_CHECK(hipStreamSynchronize(s));
     st.csr_ready = true;
   }
   *out = &st;
@@ -258,6 +265,91 @@ int power_of(uint16_t *P, int64_t q, int64_t N, int64_t ld, uint16_t *dst, uint1
   return TP_OK;
 }
 
+// Pruning of start states: 0 = by the cost model, 1 = whenever valid, -1 =
+// never (tp_tune_prune).  Guarded by g_mu.
+int g_prune = 0;
+
+int64_t count_selected(const State *st, int k) {
+  int64_t c = 0;
+  for (uint8_t z : st->zh) c += z <= k;
+  return c;
+}
+
+// Device list of the states with at most k zeros, in increasing index (cached
+// per k).  Caller holds g_mu.
+int state_selection(State *st, int k, hipStream_t s, const int32_t **idx, int64_t *count) {
+  auto it = st->sel_count.find(k);
+  if (it == st->sel_count.end()) {
+    std::vector<int32_t> h;
+    for (size_t i = 0; i < st->zh.size(); ++i)
+      if (st->zh[i] <= k) h.push_back((int32_t)i);
+    DevBuf &b = st->sel[k];
+    TP_HIP_CHECK(ensure(b, std::max<size_t>(h.size(), 1) * sizeof(int32_t)));
+    if (!h.empty())
+      TP_HIP_CHECK(hipMemcpyAsync(b.ptr, h.data(), h.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
+    TP_HIP_CHECK(hipStreamSynchronize(s));
+    it = st->sel_count.emplace(k, (int64_t)h.size()).first;
+  }
+  *idx = (const int32_t *)st->sel[k].ptr;
+  *count = it->second;
+  return TP_OK;
+}
+
+// First guess of floor(gamma_2 / m): the walk label grows by about (n + 2) / 3
+// per step for every n the paper tabulates; a wrong guess costs a second
+// pass, never a wrong answer.
+int prune_guess(int n) { return n >= 2 ? (n + 2) / 3 : 1; }
+
+// gamma_2 as min over the states with at most k zeros of (A^m)_ii: the chain
+// A^k e_i for those columns only.  Buffers 0 and 1 of the workspace.
+int pruned_chain(State *st, int64_t m, int k, hipStream_t s, int32_t *out_host) {
+  const int32_t *idx = nullptr;
+  int64_t cnt = 0;
+  int rc = state_selection(st, k, s, &idx, &cnt);
+  if (rc != TP_OK) return rc;
+  if (cnt == 0) {
+    *out_host = kInf16;
+    return TP_OK;
+  }
+  const int64_t N = st->N, ld = (cnt + 63) / 64 * 64;
+  Workspace &ws = g_ws[current_device()];
+  const size_t mat = (size_t)N * (size_t)ld * sizeof(uint16_t);
+  TP_HIP_CHECK(ensure(ws.buf[0], mat));
+  TP_HIP_CHECK(ensure(ws.buf[1], mat));
+  TP_HIP_CHECK(ensure(ws.scalar, 64));
+  uint16_t *X = (uint16_t *)ws.buf[0].ptr, *Y = (uint16_t *)ws.buf[1].ptr;
+  TP_HIP_CHECK(launch_state_columns(st->n, N, (const uint32_t *)st->masks.ptr, idx, cnt, X, ld, s));
+  for (int64_t t = 2; t <= m; ++t) {
+    TP_HIP_CHECK(state_step(st, TP_STEP_AUTO, X, ld, Y, ld, cnt, s));
+    std::swap(X, Y);
+  }
+  int32_t *d_res = (int32_t *)ws.scalar.ptr;
+  TP_HIP_CHECK(launch_diag_select_min(N, cnt, idx, X, ld, d_res, s));
+  TP_HIP_CHECK(hipMemcpyAsync(out_host, d_res, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TP_HIP_CHECK(hipStreamSynchronize(s));
+  return TP_OK;
+}
+
+// The pruned chain with the guessed bound, then, if the value found allows
+// states with more zeros (floor(value / m) above the guess), once more with
+// that bound, which then covers the optimal walk's start.
+int pruned_power_trace(State *st, int64_t m, hipStream_t s, int32_t *gamma2_host) {
+  const int k1 = prune_guess(st->n);
+  int32_t g = 0;
+  int rc = pruned_chain(st, m, k1, s, &g);
+  if (rc != TP_OK) return rc;
+  const int64_t k2 = g / m;
+  if (k2 > k1) {
+    int32_t g2 = 0;
+    rc = pruned_chain(st, m, (int)std::min<int64_t>(k2, st->n), s, &g2);
+    if (rc != TP_OK) return rc;
+    g = std::min(g, g2);
+  }
+  *gamma2_host = g;
+  return TP_OK;
+}
+
 int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
   State *st = nullptr;
   int rc = get_state(n, s, &st);
@@ -269,6 +361,17 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
   const int64_t ld = (N + 63) / 64 * 64;
   const size_t mat = (size_t)N * (size_t)ld * sizeof(uint16_t);
   const Plan plan = choose_plan(n, m, (double)N, (double)st->nnz);
+  if (g_prune >= 0) {
+    // pruned chain: m - 1 sparse steps on |S| columns, one selected diagonal.
+    // A step on the narrow panel runs at about 3/4 of the full step's rate,
+    // and up to n = 10 no faster than 0.65 of a full step (latency of the
+    // gathered rows); measured so, it wins from n = 12 on (1.25-1.35x).
+    const double cnt = (double)count_selected(st, prune_guess(n));
+    const double full = (double)st->nnz * (double)N / g_spmm_rate[n] + kLaunch;
+    const double step = std::max(full * (cnt / (double)N) / 0.75, n <= 10 ? 0.65 * full : 0.0);
+    const double cost = (double)(m - 1) * step + 2.0 * N * cnt / kHbm;
+    if (g_prune > 0 || cost < plan.cost) return pruned_power_trace(st, m, s, gamma2_host);
+  }
   const int64_t c = plan.c, q = m / c, r = m % c;
 
   TP_HIP_CHECK(ensure(ws.scalar, 64));
@@ -612,6 +715,59 @@ int tp_tropical_power_trace(int n, int64_t m, int32_t *gamma2_host, hipStream_t 
   return power_trace_locked(n, m, gamma2_host, stream);
 }
 
+int64_t tp_state_select(int n, int max_zeros, int32_t *d_idx, int64_t cap, hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(max_zeros >= 0, "negative zero count");
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  int rc = get_state(n, stream, &st);
+  if (rc != TP_OK) return rc;
+  const int32_t *idx = nullptr;
+  int64_t cnt = 0;
+  rc = state_selection(st, std::min(max_zeros, n), stream, &idx, &cnt);
+  if (rc != TP_OK) return rc;
+  if (d_idx != nullptr) {
+    TP_REQUIRE(cap >= cnt, "%lld states selected, room for %lld", (long long)cnt,
+               (long long)cap);
+    if (cnt > 0)
+      TP_HIP_CHECK(hipMemcpyAsync(d_idx, idx, (size_t)cnt * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, stream));
+  }
+  return cnt;
+}
+
+int tp_build_state_columns(int n, const int32_t *d_idx, int64_t count, void *d_X, int64_t ldx,
+                           hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(count >= 0 && count < ((int64_t)1 << 31), "count out of range");
+  TP_REQUIRE(count == 0 || (d_idx != nullptr && d_X != nullptr), "NULL pointer");
+  TP_REQUIRE(ldx >= count, "leading dimension below count");
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  int rc = get_state(n, stream, &st);
+  if (rc != TP_OK) return rc;
+  TP_HIP_CHECK(launch_state_columns(n, st->N, (const uint32_t *)st->masks.ptr, d_idx, count,
+                                    (uint16_t *)d_X, ldx, stream));
+  return TP_OK;
+}
+
+int tp_diag_select_min(int64_t N, int64_t count, const int32_t *d_idx, const void *d_X,
+                       int64_t ldx, int32_t *d_out, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && count >= 0, "negative size");
+  TP_REQUIRE(d_out != nullptr, "d_out is NULL");
+  TP_REQUIRE(count == 0 || (d_idx != nullptr && d_X != nullptr), "NULL pointer");
+  TP_REQUIRE(ldx >= count, "leading dimension below count");
+  TP_HIP_CHECK(launch_diag_select_min(N, count, d_idx, (const uint16_t *)d_X, ldx, d_out, stream));
+  return TP_OK;
+}
+
+int tp_tune_prune(int mode) {
+  TP_REQUIRE(mode >= -1 && mode <= 1, "mode is -1, 0 or 1");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prune = mode;
+  return TP_OK;
+}
+
 int tp_release_cache(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto &kv : g_states) {
@@ -622,6 +778,7 @@ int tp_release_cache(void) {
     release(kv.second.colz);
     release(kv.second.bptr);
     release(kv.second.bent);
+    for (auto &sb : kv.second.sel) release(sb.second);
   }
   g_states.clear();
   for (auto &kv : g_ws) {

@@ -198,7 +198,9 @@ __global__ void __launch_bounds__(256) block_step_pipe_kernel(
   const kconst_u64 en = (kconst_u64)ent;
   const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
   const int64_t ld4 = ldx / 8;
-  const uint32_t off = (uint32_t)(c0 / 8);
+  // lanes past the last column read chunk 0 of each row (inside the row) and
+  // store nothing
+  const uint32_t off = c0 < ncols ? (uint32_t)(c0 / 8) : 0u;
 
   u16x2 acc[kRows][4];
 #pragma unroll

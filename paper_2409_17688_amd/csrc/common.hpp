@@ -172,6 +172,11 @@ hipError_t launch_sparse_trace(int dtype, int64_t N, const int64_t *rowptr, cons
 // trace.hip
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
 hipError_t launch_fill_bytes(void *p, size_t count, uint8_t value, hipStream_t s);
+// prune.hip: columns idx of A(D_n) as a dense u16 panel; min_j X[idx[j]][j]
+hipError_t launch_state_columns(int n, int64_t N, const uint32_t *masks, const int32_t *idx,
+                                int64_t count, uint16_t *X, int64_t ldx, hipStream_t s);
+hipError_t launch_diag_select_min(int64_t rows, int64_t count, const int32_t *idx,
+                                  const uint16_t *X, int64_t ldx, int32_t *out, hipStream_t s);
 hipError_t launch_trace_min(int dtype, int64_t N, const void *X, int64_t ldx, int32_t *out,
                             hipStream_t s);
 hipError_t launch_trace_of_product(int dtype, int64_t N, const void *X, int64_t ldx,

@@ -144,7 +144,9 @@ __device__ __forceinline__ void gather_row_colz(kconst_i64 rowptr, kconst_u32 co
   const int64_t b = rowptr[q], e = rowptr[q + 1];
   const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
   const int64_t ld4 = ldx / 8;
-  const uint32_t off = (uint32_t)(c0 / 8);
+  // lanes past the last column read chunk 0 of each row (inside the row) and
+  // store nothing
+  const uint32_t off = c0 < ncols ? (uint32_t)(c0 / 8) : 0u;
   u16x2 acc[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc[r] = splat(0xFFFFu);

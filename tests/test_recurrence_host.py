@@ -83,3 +83,17 @@ def test_theorem3_rejects_what_it_cannot_answer(tp, oracle_mod):
         tp.tp_gamma2_recurrence(rec, diag, 2)
     with pytest.raises(ValueError):
         tp.tp_gamma2_recurrence(rec, diag[:5], 4)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_rotation_pruning_on_the_oracle(oracle_mod, n):
+    """A closed walk's label is the sum of the zero counts of the m states it
+    visits, so an optimal one passes through a state with at most
+    floor(gamma_2 / m) zeros: the minimum over those diagonal entries alone
+    is gamma_2 (checked on the oracle's powers)."""
+    z = np.array([oracle_mod.zeros(n, int(c)) for c in oracle_mod.words(n)])
+    for m in range(3, 16):
+        P = oracle_mod.power(n, m)
+        g = int(P.diagonal().min())
+        k = g // m
+        assert int(P.diagonal()[z <= k].min()) == g, (n, m)
