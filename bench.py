@@ -289,6 +289,20 @@ def serve_suite(tp, synth, count=2000):
         plain_total += (time.perf_counter() - t0) / len(pick) * cnt
     out["plain_qps_estimate"] = round(count / plain_total, 2)
     out["served_vs_plain"] = round((count / t_warm) / (count / plain_total), 1)
+    # recurrence mode, reported apart from the served path: one recurrence of
+    # the powers per path order of the stream (K = 50), then every query from
+    # Theorem 3's solution on the host
+    t0 = time.perf_counter()
+    recs = {n: tp.tp_recurrence(n, 50, 4 if n >= 12 else (6 if n == 11 else 0))
+            for n in sorted(counts)}
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ans = [tp.tp_gamma2_recurrence(*recs[n], m) for _, n, m in unit]
+    t_ans = time.perf_counter() - t0
+    out["recurrence_mode"] = {
+        "setup_s": round(t_setup, 3), "answer_us_per_query": round(t_ans / count * 1e6, 2),
+        "qps_including_setup": round(count / (t_setup + t_ans), 1),
+        "agrees_with_served": all(a == served[(n, m)] for a, (_, n, m) in zip(ans, unit))}
     return out
 
 

@@ -30,9 +30,11 @@
 //      the whole grid one (row, 512-column panel) item per wave, with a
 //      barrier over the grid between levels; then the task list below.  The
 //      barrier needs every workgroup resident at once, so this mode never
-//      launches more workgroups than the chip holds; a batch that cannot get
-//      them all (the chip shared with other work that waits too) ends at
-//      the wait limit like any other stuck wait.
+//      launches more workgroups than the chip holds, and such launches of
+//      the process are ordered one after another on each device; a batch
+//      that cannot get them all (the chip shared with other work that waits
+//      too, such as another process's) ends at the wait limit like any other
+//      stuck wait.
 // The persistent kernel runs a list of tasks in dependency order:
 //   GEMM   one 128 x 128 tile of A^(x+y) = A^x x A^y
 //   TRACE  64 rows i of min_{i,k} (A^a)_ik + (A^b)_ki, folded into the
@@ -403,6 +405,14 @@ namespace {
 // own parameter takes precedence.
 std::mutex g_tune_mu;
 int g_tuned_baby[2][16] = {{0}};  // [fused mode][n]
+
+// Launches with level barriers need their whole grid resident at once; two of
+// them running together on one device (batches of two contexts on two
+// streams) could each hold part of the chip and wait for the rest until the
+// wait limit.  Such launches are ordered one after another through one event
+// per device (the end of the last one).
+std::mutex g_barrier_mu;
+std::map<int, hipEvent_t> g_barrier_done;
 
 int auto_baby(int n) { return n >= 8 ? 16 : 32; }
 
@@ -891,7 +901,18 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
                                 stream));
   if (!c->staged) TP_HIP_CHECK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
   TP_HIP_CHECK(hipEventRecord(c->staged, stream));
-  TP_HIP_CHECK(hipGraphLaunch(c->exec, stream));
+  if (levels.empty()) {
+    TP_HIP_CHECK(hipGraphLaunch(c->exec, stream));
+  } else {
+    std::lock_guard<std::mutex> lk(g_barrier_mu);
+    hipEvent_t &done = g_barrier_done[c->device];
+    if (done)
+      TP_HIP_CHECK(hipStreamWaitEvent(stream, done, 0));
+    else
+      TP_HIP_CHECK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    TP_HIP_CHECK(hipGraphLaunch(c->exec, stream));
+    TP_HIP_CHECK(hipEventRecord(done, stream));
+  }
   TP_HIP_CHECK(hipMemcpyAsync(gamma2_dev, c->d_results.p, (size_t)count * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, stream));
   // what this batch computes counts as resident for later batches on this

@@ -253,3 +253,27 @@ def test_giants_at_large_n_closed_form(tp):
         assert got == [gamma2_closed_form(n, m) for n, m in inst]
     finally:
         tp.tp_ctx_destroy(ctx)
+
+
+def test_fused_batches_of_two_contexts_on_two_streams(tp, oracle_table):
+    # launches with level barriers are ordered one after another on the
+    # device, so two cold fused batches on two streams both complete
+    import torch
+    inst = synth.batch_instances(seed=14, count=20)
+    ns, ms = [n for n, _ in inst], [m for _, m in inst]
+    want = [int(oracle_table[n][m - 1]) for n, m in inst]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ctxs = [tp.tp_ctx_create(32 << 30) for _ in streams]
+    try:
+        outs = []
+        for c, s in zip(ctxs, streams):
+            tp.tp_ctx_set_param(c, tp.TP_PARAM_FUSED_CHAIN, 1)
+            tp.tp_ctx_set_param(c, tp.TP_PARAM_WAIT_LIMIT_US, 5_000_000)
+            outs.append(tp.tp_batch_power_trace(c, ns, ms, stream=s))
+        for c, s, o in zip(ctxs, streams, outs):
+            tp.tp_ctx_check(c, stream=s)
+            s.synchronize()
+            assert o.cpu().numpy().tolist() == want
+    finally:
+        for c in ctxs:
+            tp.tp_ctx_destroy(c)
