@@ -33,7 +33,7 @@ N_DEFAULT = 8192
 # below only; set to None when that kernel changes until it is measured again.
 MEASURED_TRAFFIC = {"kernel": "minplus_gemm_kernel<128,256,32,8,16,3,u16,vec>",
                     "config": 1, "ksplit": 1,
-                    "bytes": (1055386 * 2.00 + 131072 * 1.00) * 1024}
+                    "bytes": (1053160 * 2.00 + 131072 * 1.00) * 1024}
 # tile configuration index -> kernel template arguments (BM, BN, BK, TM, TN, MINB)
 KERNEL_SHAPES = {0: "128,128,32,8,8,4", 1: "128,256,32,8,16,3", 2: "256,128,32,16,8,3",
                  3: "64,64,32,4,4,4", 4: "256,256,32,16,16,2"}

@@ -184,36 +184,42 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
   }
   __syncthreads();
 
+  // one step k of the slab: acc = min(acc, a_k + b_k) over the lane's tile
+  auto step = [&](const u16x2 (&a2)[TM2], const u16x2 (&b2)[TN2]) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const u16x2 av = splat((i & 1) ? a2[i >> 1].y : a2[i >> 1].x);
+      // all adds of the row first, then the mins: an add whose a_ik comes
+      // from the high half (op_sel) followed at once by the min reading its
+      // result costs a hazard wait state on gfx950; grouped, the results are
+      // consumed TN/2 instructions later and no waits are inserted
+      u16x2 sum[TN2];
+#pragma unroll
+      for (int j = 0; j < TN2; ++j) sum[j] = pk_add_sat(av, b2[j]);
+#pragma unroll
+      for (int j = 0; j < TN2; ++j) acc[i][j] = pk_min(acc[i][j], sum[j]);
+    }
+  };
+  static_assert(BK % 2 == 0, "the slab is walked two steps at a time");
+
   for (int s = 0; s < nslab; ++s) {
     const int buf = s & 1;
     if (s + 1 < nslab) global_load((s + 1) * BK);
-    u16x2 a_cur[TM2], b_cur[TN2];
-    lds_frag(buf, 0, a_cur, b_cur);
-#pragma unroll 2
-    for (int k = 0; k < BK; ++k) {
-      // fragments for step k + 1 are requested before the arithmetic of step k
-      u16x2 a_nxt[TM2], b_nxt[TN2];
-      if (k + 1 < BK) lds_frag(buf, k + 1, a_nxt, b_nxt);
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const u16x2 av = splat((i & 1) ? a_cur[i >> 1].y : a_cur[i >> 1].x);
-        // all adds of the row first, then the mins: an add whose a_ik comes
-        // from the high half (op_sel) followed at once by the min reading its
-        // result costs a hazard wait state on gfx950; grouped, the results
-        // are consumed TN/2 instructions later and no waits are inserted
-        u16x2 sum[TN2];
-#pragma unroll
-        for (int j = 0; j < TN2; ++j) sum[j] = pk_add_sat(av, b_cur[j]);
-#pragma unroll
-        for (int j = 0; j < TN2; ++j) acc[i][j] = pk_min(acc[i][j], sum[j]);
-      }
-      if (k + 1 < BK) {
-#pragma unroll
-        for (int i = 0; i < TM2; ++i) a_cur[i] = a_nxt[i];
-#pragma unroll
-        for (int j = 0; j < TN2; ++j) b_cur[j] = b_nxt[j];
-      }
+    // two fragment sets in turn: the fragments of the next step are
+    // requested before the arithmetic of the current one, and no registers
+    // are copied from one step to the next
+    u16x2 a0[TM2], b0[TN2], a1[TM2], b1[TN2];
+    lds_frag(buf, 0, a0, b0);
+#pragma unroll 1
+    for (int k = 0; k < BK - 2; k += 2) {
+      lds_frag(buf, k + 1, a1, b1);
+      step(a0, b0);
+      lds_frag(buf, k + 2, a0, b0);
+      step(a1, b1);
     }
+    lds_frag(buf, BK - 1, a1, b1);
+    step(a0, b0);
+    step(a1, b1);
     if (s + 1 < nslab) lds_store(buf ^ 1);
     __syncthreads();
   }
