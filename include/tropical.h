@@ -198,6 +198,17 @@ int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, 
  * rule).  The power chains of tp_tropical_power_trace use it too. */
 int tp_tune_step(int n, int form);
 
+/* All-pairs shortest paths by (min,+) squaring, the same semiring (Section 1)
+ * on another workload: d_D (N x N) = (I + W)^(2^t), t = ceil(log2(N - 1)),
+ * where W holds non-negative arc weights (INF = no arc) and I is the (min,+)
+ * identity, so d_D[i][j] = min(least weight of a path i -> j, INF) exactly
+ * (sums saturate; with non-negative weights the saturated sum of a path does
+ * not depend on the order of its additions).  d_T is an N x N work matrix
+ * (ldt >= N), distinct from d_W and d_D, unused when N <= 2; d_W may be
+ * d_D.  t dense products of N^3 operations each; no allocation. */
+int tp_apsp(int dtype, int64_t N, const void *d_W, int64_t ldw, void *d_D, int64_t ldd,
+            void *d_T, int64_t ldt, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Traces: Theorem 2 reads gamma_2 as the minimum of the diagonal.            */
 /* ------------------------------------------------------------------------ */

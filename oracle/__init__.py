@@ -75,6 +75,8 @@ def _load():
     lib.oracle_power.restype = ctypes.c_int64
     lib.oracle_recurrence.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int32, i64p]
     lib.oracle_recurrence.restype = ctypes.c_int
+    lib.oracle_apsp.argtypes = [ctypes.c_int64, i32p, ctypes.c_int32, i32p]
+    lib.oracle_apsp.restype = None
     lib.oracle_constant_difference.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_int32, i64p]
     lib.oracle_constant_difference.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
@@ -186,6 +188,17 @@ def recurrence(n: int, K: int = 50, inf: int = INF16):
     if ok != 1:
         return None
     return tuple(int(v) for v in out)
+
+
+def apsp(W: np.ndarray, inf: int = INF16) -> np.ndarray:
+    """min(shortest path weight, inf) for every ordered pair, by Floyd-Warshall
+    relaxation (non-negative weights, inf = no arc)."""
+    W = np.ascontiguousarray(W, dtype=np.int32)
+    if W.ndim != 2 or W.shape[0] != W.shape[1]:
+        raise ValueError("W must be square")
+    D = np.empty_like(W)
+    _load().oracle_apsp(W.shape[0], _i32(W), inf, _i32(D))
+    return D
 
 
 def constant_difference(X: np.ndarray, Y: np.ndarray, inf: int = INF16):

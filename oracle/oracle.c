@@ -21,6 +21,8 @@
  *     (A x B)_ij = min_k (a_ik + b_kj), with every sum >= INF taken as INF;
  *   - powers: Algorithm 2, A^k = A x A^(k-1);
  *   - gamma_2(P_n x C_m) = min_i (A^m)_ii (Theorem 2; Algorithm 5);
+ *   - all-pairs shortest paths by Floyd-Warshall relaxation, for the same
+ *     semiring applied to another workload;
  *   - recurrence search (Algorithm 3) and its minimal start (Algorithm 4),
  *     with "A^i - A^j is constant" read as A^i = b x A^j exactly (same INF
  *     pattern, every finite difference equal to one b).
@@ -261,6 +263,33 @@ static int constant_difference(int64_t cnt, const int32_t *X, const int32_t *Y,
     }
     *b_out = b;
     return 1;
+}
+
+/* All-pairs shortest paths on the same semiring (Section 1), written as the
+ * textbook Floyd-Warshall relaxation: D starts as W with a zero diagonal and,
+ * for every intermediate vertex k in turn, D[i][j] = min(D[i][j],
+ * D[i][k] + D[k][j]) with sums >= inf taken as inf.  Non-negative weights;
+ * N x N row-major int32, leading dimension N. */
+void oracle_apsp(int64_t N, const int32_t *W, int32_t inf, int32_t *D)
+{
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j)
+            D[i * N + j] = (i == j) ? 0 : (W[i * N + j] >= inf ? inf : W[i * N + j]);
+    for (int64_t k = 0; k < N; ++k) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t dik = D[i * N + k];
+            if (dik >= inf)
+                continue;
+            for (int64_t j = 0; j < N; ++j) {
+                int64_t t = dik + D[k * N + j];
+                if (t > inf)
+                    t = inf;
+                if (t < D[i * N + j])
+                    D[i * N + j] = (int32_t)t;
+            }
+        }
+    }
 }
 
 /* The same test for callers: X and Y hold cnt entries each (row-major,

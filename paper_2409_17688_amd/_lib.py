@@ -87,6 +87,7 @@ _SIGS = {
     "tp_sparse_trace_of_product": ([_i, _i64, _p, _p, _p, _p, _i64, _p, _p], _i),
     "tp_tropical_power_trace": ([_i, _i64, ctypes.POINTER(ctypes.c_int32), _p], _i),
     "tp_release_cache": ([], _i),
+    "tp_apsp": ([_i, _i64, _p, _i64, _p, _i64, _p, _i64, _p], _i),
     "tp_state_select": ([_i, _i, _p, _i64, _p], _i64),
     "tp_build_state_columns": ([_i, _p, _i64, _p, _i64, _p], _i),
     "tp_diag_select_min": ([_i64, _i64, _p, _p, _i64, _p, _p], _i),
@@ -480,6 +481,27 @@ def tp_diag_select_min(X: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | N
 
 def tp_tune_prune(mode: int) -> None:
     _check(lib.tp_tune_prune(int(mode)))
+
+
+def tp_apsp(W: torch.Tensor, D: torch.Tensor | None = None, T: torch.Tensor | None = None,
+            stream=None) -> torch.Tensor:
+    """All-pairs shortest paths: D = min(distance, INF) for the arc weights W
+    (INF = no arc), by (min,+) squaring."""
+    dt = _dtype_code(W)
+    pw, N, N2, ldw = _mat(W, "W")
+    if N != N2:
+        raise ValueError("W must be square")
+    if D is None:
+        D = torch.empty_like(W)
+    if T is None:
+        T = torch.empty_like(W)
+    for name, M in (("D", D), ("T", T)):
+        if M.dtype != W.dtype or tuple(M.shape) != (N, N):
+            raise ValueError(f"{name} must match W")
+    pd, _, _, ldd = _mat(D, "D")
+    pt, _, _, ldt = _mat(T, "T")
+    _check(lib.tp_apsp(dt, N, pw, ldw, pd, ldd, pt, ldt, _stream(stream)))
+    return D
 
 
 def tp_release_cache() -> None:

@@ -8,6 +8,7 @@
     python -m paper_2409_17688_amd.kernel_bench --op batch --instances mixed64
     python -m paper_2409_17688_amd.kernel_bench --op cdiff --n 12
     python -m paper_2409_17688_amd.kernel_bench --op recurrence --n 12 --window 4
+    python -m paper_2409_17688_amd.kernel_bench --op apsp --N 8192
 
 Matrices use the library's resident layout (rows padded to 64 entries).
 Times come from HIP events on the launch stream; one JSON line per run with
@@ -22,6 +23,9 @@ the algorithmic work of one launch:
          entries read (4 N^2 bytes)
   recurrence  tp_recurrence(n, K, window): K powers, each compared with the
          window before it, then Algorithms 3 and 4 (wall time)
+  apsp   all-pairs shortest paths on a random digraph of order N (weights
+         0..49 on 1 % of the pairs, default_rng(0)): ceil(log2(N-1)) dense
+         products of N^3 operations
 """
 from __future__ import annotations
 
@@ -52,7 +56,7 @@ def _padded(torch, N):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--op", choices=["spmm", "bstep", "gather", "trace", "gemm", "batch", "cdiff",
-                                     "recurrence"], required=True)
+                                     "recurrence", "apsp"], required=True)
     ap.add_argument("--n", type=int, default=10)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--config", type=int, default=None, help="dense product tile config")
@@ -61,6 +65,7 @@ def main(argv=None):
                     help="batch: chain levels inside the persistent launch too")
     ap.add_argument("--K", type=int, default=50, help="recurrence: powers computed")
     ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
+    ap.add_argument("--N", type=int, default=8192, help="apsp: order of the digraph")
     args = ap.parse_args(argv)
 
     import torch
@@ -68,7 +73,19 @@ def main(argv=None):
     from . import _lib as tp
     n = args.n
     out = {"op": args.op}
-    if args.op == "recurrence":
+    if args.op == "apsp":
+        import numpy as np
+        N = args.N
+        rng = np.random.default_rng(0)
+        W = rng.integers(0, 50, (N, N)).astype(np.uint16)
+        W[rng.random((N, N)) > 0.01] = 65535
+        Wd = torch.from_numpy(W.view(np.int16)).cuda().view(torch.uint16)
+        D, T = torch.empty_like(Wd), torch.empty_like(Wd)
+        t = _events(torch, lambda: tp.tp_apsp(Wd, D, T), args.reps)
+        sq = max(0, (N - 2).bit_length())
+        out.update({"N": N, "squarings": sq, "ms": t * 1e3,
+                    "Tminplus_ops": sq * float(N) ** 3 / t / 1e12})
+    elif args.op == "recurrence":
         tp.tp_recurrence(n, 3, 1)  # the state of n in the library's cache
         times = []
         for _ in range(args.reps):
