@@ -265,6 +265,40 @@ __device__ __forceinline__ void trace_tile(const T *__restrict__ X, int64_t ldx,
   __syncthreads();
 }
 
+// Folds min over i in [i0, i0+64), k in [k0, k0+64) of x_ik + y_ki into acc,
+// one wave per tile and no LDS: lane (kg, ig) = (lane / 8, lane % 8) reads the
+// 8 x 8 blocks X[i0+8ig ..][k0+8kg ..] and Y[k0+8kg ..][i0+8ig ..] (per load,
+// eight lanes cover 128 contiguous bytes of one row), transposes its Y block
+// in registers (one byte permute per packed pair) and adds it to its X block.
+// All 16 loads of a lane are in flight together.
+template <typename T, bool VEC>
+__device__ __forceinline__ void trace_tile_regs(const T *__restrict__ X, int64_t ldx,
+                                                const T *__restrict__ Y, int64_t ldy, int64_t N,
+                                                int64_t i0, int64_t k0, int lane,
+                                                u16x2 (&acc)[4]) {
+  const int ig = lane & 7, kg = lane >> 3;
+  const int64_t i = i0 + 8 * ig, k = k0 + 8 * kg;
+  uint4 xr[8], yr[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    xr[r] = load8<T, VEC>(X, ldx, i + r, k, N);
+    yr[r] = load8<T, VEC>(Y, ldy, k + r, i, N);
+  }
+  auto word = [](const uint4 &v, int w) { return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w; };
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    // row i + r of X against column i + r of Y: y_{k+2c, i+r} and
+    // y_{k+2c+1, i+r} packed like x_{i+r, k+2c} and x_{i+r, k+2c+1}
+    const uint32_t sel = (r & 1) ? 0x07060302u : 0x05040100u;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t yt = __builtin_amdgcn_perm(word(yr[2 * c + 1], r >> 1),
+                                                word(yr[2 * c], r >> 1), sel);
+      acc[c] = pk_min(acc[c], pk_add_sat(as_pk(word(xr[r], c)), as_pk(yt)));
+    }
+  }
+}
+
 // Minimum of the four packed accumulators over the whole workgroup (256
 // lanes); the result is valid in lane 0.  `part` is 4 ints of LDS.
 __device__ __forceinline__ int32_t block_min(const u16x2 (&acc)[4], int32_t *part) {

@@ -7,7 +7,7 @@
 // The second one closes a power chain without forming its last product: with
 // X = A^a and Y = A^b it gives gamma_2 for m = a + b at the price of one pass
 // over two matrices, which is bound by HBM bandwidth.  Both matrices stream
-// row-wise in 16-byte loads; Y's 64 x 64 tiles are transposed through LDS.
+// row-wise in 16-byte loads; Y's 8 x 8 blocks are transposed in registers.
 #include <algorithm>
 
 #include "device_core.hpp"
@@ -46,24 +46,24 @@ __global__ void __launch_bounds__(1024) trace_min_kernel(int64_t N, const T *__r
   }
 }
 
-// Workgroups walk 64 x 64 tiles (i-block, k-block) with a grid stride.  The
-// Y tile Y[k-block][i-block] is staged transposed in LDS so that x_ik and
-// y_ki meet as two 16-byte rows; the partial minimum is folded into *out with
-// one atomic per workgroup.
+// Waves walk 64 x 64 tiles (i-block, k-block) with a grid stride, each tile
+// by one wave with its Y block transposed in registers (trace_tile_regs);
+// the partial minimum is folded into *out with one atomic per workgroup.
 template <typename T, bool VEC>
 __global__ void __launch_bounds__(256) trace_of_product_kernel(int64_t N, const T *__restrict__ X,
                                                                int64_t ldx,
                                                                const T *__restrict__ Y,
                                                                int64_t ldy, int64_t tiles,
                                                                int32_t *__restrict__ out) {
-  __shared__ __attribute__((aligned(16))) uint16_t yt[64 * kTraceLdsStride];
   __shared__ int32_t part[4];
   u16x2 acc[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) acc[e] = splat(0xFFFFu);
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t total = tiles * tiles;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x)
-    trace_tile<T, VEC>(X, ldx, Y, ldy, N, (t % tiles) * 64, (t / tiles) * 64, yt, acc);
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < total; t += (int64_t)gridDim.x * 4)
+    trace_tile_regs<T, VEC>(X, ldx, Y, ldy, N, (t % tiles) * 64, (t / tiles) * 64, lane, acc);
   const int32_t best = min(block_min(acc, part), inf_of<T>());
   if (threadIdx.x == 0 && best < inf_of<T>()) atomicMin(out, best);
 }
@@ -100,7 +100,7 @@ hipError_t launch_trace_of_product(int dtype, int64_t N, const void *X, int64_t 
   hipError_t e = launch_fill_i32(out, 1, dtype == TP_U16 ? 0xFFFF : 0xFF, s);
   if (e != hipSuccess || N == 0) return e;
   const int64_t tiles = (N + 63) / 64;
-  const int64_t blocks = std::min<int64_t>(tiles * tiles, 4096);
+  const int64_t blocks = std::min<int64_t>((tiles * tiles + 3) / 4, 2048);  // a tile per wave
   const int64_t VE = 8;
   const size_t es = dtype == TP_U16 ? 2 : 1;
   const bool vec = (ldx % VE == 0) && (ldy % VE == 0) && ((uintptr_t)X % (VE * es) == 0) &&
