@@ -317,8 +317,9 @@ def query_suite(tp, synth):
     the batch; median of three fresh contexts); 'fused cold' the same with
     the chain levels inside the one persistent launch (TP_PARAM_FUSED_CHAIN);
     'batched warm' repeats the batch on the same context (powers resident,
-    only the traces run).  Every batched answer is compared with the plain
-    one."""
+    only the traces run); for the sweep also 'sweep chain', one chain of 256
+    powers with the diagonal minimum of each.  Every batched answer is
+    compared with the plain one."""
     import torch
     out = {}
     for name, inst in (("mixed64", synth.batch_instances(seed=0)),
@@ -388,6 +389,20 @@ def query_suite(tp, synth):
                      "cold_speedup": round(t_plain / t_cold, 2),
                      "fused_cold_speedup": round(t_plain / t_fused, 2),
                      "warm_speedup": round(t_plain / t_warm, 2)}
+        if name == "sweep_n8":
+            # one sweep chain X_k = A x X_(k-1) with the diagonal minimum of
+            # every power (tp_recurrence with the smallest window): all 254
+            # answers from a single chain of 256 powers
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, diag = tp.tp_recurrence(8, 256, 1)
+            t_sweep = time.perf_counter() - t0
+            if [int(diag[m - 1]) for m in ms] != plain:
+                print("MISMATCH in sweep_n8: sweep chain and plain answers differ",
+                      file=sys.stderr)
+                sys.exit(1)
+            out[name]["sweep_chain_qps"] = round(k / t_sweep, 1)
+            out[name]["sweep_chain_speedup"] = round(t_plain / t_sweep, 2)
     return out
 
 
