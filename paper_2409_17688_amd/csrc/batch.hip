@@ -128,7 +128,7 @@ constexpr int kLevelCounters = (2 * kMaxXcc + 2) * kLine;
 // XCC_ID hardware register (bits 3:0): which XCD, and so which L2, a wave is on
 constexpr int kHwRegXccId = (3 << 11) | 20;
 constexpr uint16_t kInf = 0xFFFFu;
-constexpr int kPanel = 512;                       // columns of an SPMM task: 64 lanes x 8
+constexpr int kPanel = 512;                       // columns of a chain level item: 64 lanes x 8
 constexpr int kGBM = 128, kGBN = 128, kGBK = 32;  // dense product tile
 
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {

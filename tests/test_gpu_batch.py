@@ -100,6 +100,19 @@ def test_large_n_in_batch_closed_form(tp):
         tp.tp_ctx_destroy(ctx)
 
 
+def test_fused_mode_large_n_closed_form(tp):
+    # chain levels of large N inside the one launch (level items of n = 10,
+    # 11 and 12 next to small ones)
+    inst = [(10, 3), (10, 40), (11, 5), (11, 24), (12, 5), (9, 100), (4, 7)]
+    ctx = tp.tp_ctx_create(120 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, 1)
+        got = _run(tp, ctx, inst)
+        assert got == [gamma2_closed_form(n, m) for n, m in inst]
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
 def test_budget_exceeded(tp):
     ctx = tp.tp_ctx_create(1 << 20)
     try:
