@@ -77,6 +77,8 @@ struct State {
   int64_t N = 0, nnz = -1;
   DevBuf masks, z, rowptr, col, colz;
   DevBuf bptr, bent;  // blocked form of A(D_n), 16 rows per block
+  DevBuf order;       // rows by decreasing out-degree (int32), for the packed gather
+  DevBuf border;      // row blocks by decreasing entry count (int32), for the blocked step
   int64_t nent = 0;
   bool csr_ready = false;
   std::vector<uint8_t> zh;                // zero counts on the host
@@ -135,9 +137,40 @@ int get_state(int n, hipStream_t s, State **out) {
     TP_HIP_CHECK(ensure(st.bent, (size_t)std::max<int64_t>(nent, 1) * sizeof(uint64_t)));
     TP_HIP_CHECK(launch_block_fill(N, n, (const uint32_t *)st.masks.ptr,
                                    (const int64_t *)st.bptr.ptr, (uint64_t *)st.bent.ptr, s));
+    {
+      // the blocked step's order: blocks with the most entries first
+      std::vector<int64_t> bp((size_t)nb + 1);
+      TP_HIP_CHECK(hipMemcpyAsync(bp.data(), st.bptr.ptr, bp.size() * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s));
+      TP_HIP_CHECK(hipStreamSynchronize(s));
+      std::vector<int32_t> bo((size_t)nb);
+      for (int64_t b = 0; b < nb; ++b) bo[b] = (int32_t)b;
+      std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t c) {
+        return bp[a + 1] - bp[a] > bp[c + 1] - bp[c];
+      });
+      TP_HIP_CHECK(ensure(st.border, std::max<size_t>(bo.size(), 1) * sizeof(int32_t)));
+      if (nb > 0)
+        TP_HIP_CHECK(hipMemcpy(st.border.ptr, bo.data(), bo.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice));
+    }
     st.zh.assign((size_t)N, 0);
     TP_HIP_CHECK(hipMemcpyAsync(st.zh.data(), st.z.ptr, (size_t)N, hipMemcpyDeviceToHost, s));
+    // the gather's row order: longest successor lists first, so that the
+    // longest chains of dependent gathers start with the launch instead of
+    // ending it (the all-zero word alone has 2^n successors)
+    std::vector<int64_t> rp((size_t)N + 1);
+    TP_HIP_CHECK(hipMemcpyAsync(rp.data(), st.rowptr.ptr, rp.size() * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
     TP_HIP_CHECK(hipStreamSynchronize(s));
+    std::vector<int32_t> ord((size_t)N);
+    for (int64_t i = 0; i < N; ++i) ord[i] = (int32_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+      return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+    });
+    TP_HIP_CHECK(ensure(st.order, std::max<size_t>(ord.size(), 1) * sizeof(int32_t)));
+    if (N > 0)
+      TP_HIP_CHECK(hipMemcpy(st.order.ptr, ord.data(), ord.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
     st.csr_ready = true;
   }
   *out = &st;
@@ -176,10 +209,12 @@ hipError_t state_step(const State *st, int form, const uint16_t *X, int64_t ldx,
                       int64_t ldy, int64_t ncols, hipStream_t s) {
   if (step_form(st->n, form) == TP_STEP_BLOCKED)
     return launch_block_step(st->N, (const int64_t *)st->bptr.ptr,
-                             (const uint64_t *)st->bent.ptr, X, ldx, Y, ldy, ncols, s);
+                             (const uint64_t *)st->bent.ptr, (const int32_t *)st->border.ptr, X,
+                             ldx, Y, ldy, ncols, s);
   if (state_gather_fits(X, ldx, Y, ldy, ncols))
     return launch_state_gather(st->N, (const int64_t *)st->rowptr.ptr,
-                               (const uint32_t *)st->colz.ptr, X, ldx, Y, ldy, ncols, s);
+                               (const uint32_t *)st->colz.ptr, (const int32_t *)st->order.ptr, X,
+                               ldx, Y, ldy, ncols, s);
   return launch_spmm(TP_U16, st->N, (const int64_t *)st->rowptr.ptr,
                      (const uint32_t *)st->col.ptr, (const uint8_t *)st->z.ptr, X, ldx, Y, ldy,
                      ncols, s);
@@ -435,9 +470,9 @@ hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, u
     form = step_form(v.n, TP_STEP_AUTO);
   }
   if (form == TP_STEP_BLOCKED)
-    return launch_block_step(v.N, v.bptr, v.bent, X, ldx, Y, ldy, ncols, s);
+    return launch_block_step(v.N, v.bptr, v.bent, v.border, X, ldx, Y, ldy, ncols, s);
   if (state_gather_fits(X, ldx, Y, ldy, ncols))
-    return launch_state_gather(v.N, v.rowptr, v.colz, X, ldx, Y, ldy, ncols, s);
+    return launch_state_gather(v.N, v.rowptr, v.colz, v.order, X, ldx, Y, ldy, ncols, s);
   return launch_spmm(TP_U16, v.N, v.rowptr, v.col, v.z, X, ldx, Y, ldy, ncols, s);
 }
 
@@ -457,6 +492,8 @@ int state_view(int n, hipStream_t s, StateView *out) {
   out->bptr = (const int64_t *)st->bptr.ptr;
   out->bent = (const uint64_t *)st->bent.ptr;
   out->nent = st->nent;
+  out->order = (const int32_t *)st->order.ptr;
+  out->border = (const int32_t *)st->border.ptr;
   return TP_OK;
 }
 
@@ -778,6 +815,8 @@ int tp_release_cache(void) {
     release(kv.second.colz);
     release(kv.second.bptr);
     release(kv.second.bent);
+    release(kv.second.order);
+    release(kv.second.border);
     for (auto &sb : kv.second.sel) release(sb.second);
   }
   g_states.clear();

@@ -93,6 +93,7 @@ struct Slot {
   const uint32_t *masks;
   const int64_t *rowptr;
   const uint32_t *colz;     // successors with their labels in the top byte
+  const int32_t *order;     // rows by decreasing out-degree
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
@@ -214,7 +215,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
           const Slot sl = slots[lv.slot[i]];
           const int64_t N = sl.N, ld = sl.ld;
           const int64_t l = item - lv.begin[i];
-          const int64_t panel = l / N, q = l - panel * N;
+          const int64_t panel = l / N, slot = l - panel * N;
+          // rows with the longest successor lists first
+          const int64_t q = sl.order ? (int64_t)((kconst_i32)sl.order)[slot] : slot;
           const int64_t c0 = panel * kPanel + (int64_t)lane * 8;
           if (c0 >= N) {
             // lanes past the last column of the last panel (their loads
@@ -861,6 +864,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.masks = p.view.masks;
     sl.rowptr = p.view.rowptr;
     sl.colz = p.view.colz;
+    sl.order = p.view.order;
     sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
     hs[s] = sl;
     for (size_t e = 0; e < ptr_stride; ++e) {

@@ -113,6 +113,7 @@ __device__ __forceinline__ void apply_entry(u16x2 (&acc)[kRows][4], uint32_t m, 
 template <bool VEC, int U>
 __global__ void __launch_bounds__(256) block_step_kernel(int64_t N, const int64_t *__restrict__ bptr,
                                                          const uint64_t *__restrict__ ent,
+                                                         const int32_t *__restrict__ border,
                                                          const uint16_t *__restrict__ X,
                                                          int64_t ldx, uint16_t *__restrict__ Y,
                                                          int64_t ldy, int64_t ncols) {
@@ -123,8 +124,10 @@ __global__ void __launch_bounds__(256) block_step_kernel(int64_t N, const int64_
   const int64_t groups = (nblocks + 3) / 4;
   const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t panel = t / groups;
-  const int64_t b = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (b >= nblocks) return;
+  const int64_t bslot = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (bslot >= nblocks) return;
+  // blocks with the most entries first
+  const int64_t b = border ? (int64_t)((kconst_i32)border)[bslot] : bslot;
   const int64_t c0 = (panel * 64 + lane) * VE;
   const kconst_i64 bp = (kconst_i64)bptr;
   const kconst_u64 en = (kconst_u64)ent;
@@ -184,15 +187,17 @@ __global__ void __launch_bounds__(256) block_step_kernel(int64_t N, const int64_
 template <int U>
 __global__ void __launch_bounds__(256) block_step_pipe_kernel(
     int64_t N, const int64_t *__restrict__ bptr, const uint64_t *__restrict__ ent,
-    const uint16_t *__restrict__ X, int64_t ldx, uint16_t *__restrict__ Y, int64_t ldy,
-    int64_t ncols) {
+    const int32_t *__restrict__ border, const uint16_t *__restrict__ X, int64_t ldx,
+    uint16_t *__restrict__ Y, int64_t ldy, int64_t ncols) {
   const int lane = threadIdx.x & 63;
   const int64_t nblocks = (N + kRows - 1) / kRows;
   const int64_t groups = (nblocks + 3) / 4;
   const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t panel = t / groups;
-  const int64_t b = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (b >= nblocks) return;
+  const int64_t bslot = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (bslot >= nblocks) return;
+  // blocks with the most entries first
+  const int64_t b = border ? (int64_t)((kconst_i32)border)[bslot] : bslot;
   const int64_t c0 = (panel * 64 + lane) * 8;
   const kconst_i64 bp = (kconst_i64)bptr;
   const kconst_u64 en = (kconst_u64)ent;
@@ -264,8 +269,8 @@ __global__ void __launch_bounds__(256) block_step_pipe_kernel(
 }
 
 hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t *ent,
-                                 const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
-                                 int64_t ncols, hipStream_t s) {
+                                 const int32_t *border, const uint16_t *X, int64_t ldx,
+                                 uint16_t *Y, int64_t ldy, int64_t ncols, hipStream_t s) {
   constexpr int VE = 8;
   const int64_t nblocks = (N + kRows - 1) / kRows;
   const int64_t panels = (ncols + 64 * VE - 1) / (64 * VE);
@@ -276,14 +281,14 @@ hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t 
   // step (n <= 10: 0.30 vs 0.52 ms at n = 9); from n = 11 on cache bandwidth
   // does, and the plain one is 2 % faster (n = 12: 53.4 vs 54.5 ms)
   if (vec && ldx >= (ncols + 7) / 8 * 8 && N < 16384)
-    hipLaunchKernelGGL((block_step_pipe_kernel<4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
-                       Y, ldy, ncols);
+    hipLaunchKernelGGL((block_step_pipe_kernel<4>), grid, dim3(256), 0, s, N, bptr, ent, border,
+                       X, ldx, Y, ldy, ncols);
   else if (vec)
-    hipLaunchKernelGGL((block_step_kernel<true, 4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
-                       Y, ldy, ncols);
+    hipLaunchKernelGGL((block_step_kernel<true, 4>), grid, dim3(256), 0, s, N, bptr, ent, border,
+                       X, ldx, Y, ldy, ncols);
   else
-    hipLaunchKernelGGL((block_step_kernel<false, 4>), grid, dim3(256), 0, s, N, bptr, ent, X, ldx,
-                       Y, ldy, ncols);
+    hipLaunchKernelGGL((block_step_kernel<false, 4>), grid, dim3(256), 0, s, N, bptr, ent,
+                       border, X, ldx, Y, ldy, ncols);
   return hipGetLastError();
 }
 
@@ -312,10 +317,10 @@ hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int6
 }
 
 hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
-                             const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
-                             int64_t ncols, hipStream_t s) {
+                             const int32_t *border, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                             int64_t ldy, int64_t ncols, hipStream_t s) {
   if (N == 0 || ncols == 0) return hipSuccess;
-  return launch_block_step_u16(N, bptr, ent, X, ldx, Y, ldy, ncols, s);
+  return launch_block_step_u16(N, bptr, ent, border, X, ldx, Y, ldy, ncols, s);
 }
 
 }  // namespace tp

@@ -52,6 +52,7 @@ using gmut = __attribute__((address_space(1))) T *;
 // Read-only tables (the resident CSR): through constant-space views a
 // wave-uniform index becomes a scalar load.
 typedef const __attribute__((address_space(4))) int64_t *kconst_i64;
+typedef const __attribute__((address_space(4))) int32_t *kconst_i32;
 typedef const __attribute__((address_space(4))) uint32_t *kconst_u32;
 typedef const __attribute__((address_space(4))) uint64_t *kconst_u64;
 
@@ -112,6 +113,8 @@ struct StateView {
   const int64_t *bptr;
   const uint64_t *bent;
   int64_t nent;
+  const int32_t *order;   // rows by decreasing out-degree
+  const int32_t *border;  // row blocks by decreasing entry count
 };
 int state_view(int n, hipStream_t s, StateView *out);
 // Y = A(D_n) x X (u16) in the form the library picks for n (tp_tune_step).
@@ -129,10 +132,11 @@ hipError_t launch_scan_rowptr(int64_t N, int64_t *rowptr, hipStream_t s);
 hipError_t launch_csr_fill(int64_t N, int n, const uint32_t *masks, const int64_t *rowptr,
                            uint32_t *col, uint32_t *colz, hipStream_t s);
 
-// spmm.hip: the state matrix's own step from its packed successor list
+// spmm.hip: the state matrix's own step from its packed successor list; rows
+// in `order` (a permutation of 0..rows-1) when it is not NULL
 hipError_t launch_state_gather(int64_t rows, const int64_t *rowptr, const uint32_t *colz,
-                               const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
-                               int64_t ncols, hipStream_t s);
+                               const int32_t *order, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                               int64_t ldy, int64_t ncols, hipStream_t s);
 bool state_gather_fits(const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t ncols);
 
 // blockstep.hip: the sparse left step over blocks of 16 rows
@@ -141,9 +145,10 @@ hipError_t launch_block_count(int64_t N, int n, const uint32_t *masks, int64_t *
                               hipStream_t s);
 hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int64_t *bptr,
                              uint64_t *ent, hipStream_t s);
+// blocks in `border` (a permutation of the blocks) when it is not NULL
 hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
-                             const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
-                             int64_t ncols, hipStream_t s);
+                             const int32_t *border, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                             int64_t ldy, int64_t ncols, hipStream_t s);
 
 // gemm.hip
 // config >= 0: that tile configuration with ksplit slices (>= 1); config < 0:

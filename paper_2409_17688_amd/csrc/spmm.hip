@@ -45,6 +45,7 @@ template <int U>
 __global__ void __launch_bounds__(256) state_gather_kernel(int64_t rows,
                                                            const int64_t *__restrict__ rowptr,
                                                            const uint32_t *__restrict__ colz,
+                                                           const int32_t *__restrict__ order,
                                                            const uint16_t *__restrict__ X,
                                                            int64_t ldx, uint16_t *__restrict__ Y,
                                                            int64_t ldy, int64_t ncols) {
@@ -52,8 +53,10 @@ __global__ void __launch_bounds__(256) state_gather_kernel(int64_t rows,
   const int64_t groups = (rows + 3) / 4;
   const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t panel = t / groups;
-  const int64_t q = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (q >= rows) return;
+  const int64_t slot = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (slot >= rows) return;
+  // rows in the given order (longest successor lists first), else in index order
+  const int64_t q = order ? (int64_t)((kconst_i32)order)[slot] : slot;
   const int64_t c0 = (panel * 64 + lane) * 8;
   gather_row_colz<U>((kconst_i64)rowptr, (kconst_u32)colz, X, ldx, Y, ldy, ncols, q, c0);
 }
@@ -113,13 +116,13 @@ hipError_t launch_spmm(int dtype, int64_t rows, const int64_t *rowptr, const uin
 }
 
 hipError_t launch_state_gather(int64_t rows, const int64_t *rowptr, const uint32_t *colz,
-                               const uint16_t *X, int64_t ldx, uint16_t *Y, int64_t ldy,
-                               int64_t ncols, hipStream_t s) {
+                               const int32_t *order, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                               int64_t ldy, int64_t ncols, hipStream_t s) {
   if (rows == 0 || ncols == 0) return hipSuccess;
   const int64_t panels = (ncols + 511) / 512;
   dim3 grid((unsigned)(((rows + 3) / 4) * panels));
-  hipLaunchKernelGGL(state_gather_kernel<8>, grid, dim3(256), 0, s, rows, rowptr, colz, X, ldx,
-                     Y, ldy, ncols);
+  hipLaunchKernelGGL(state_gather_kernel<8>, grid, dim3(256), 0, s, rows, rowptr, colz, order, X,
+                     ldx, Y, ldy, ncols);
   return hipGetLastError();
 }
 
