@@ -277,10 +277,11 @@ hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t 
   const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
   const bool vec = (ldx % VE == 0) && (ldy % VE == 0) && ((uintptr_t)X % 16 == 0) &&
                    ((uintptr_t)Y % 16 == 0);
-  // the pipelined kernel wins while the gathered rows' latency bounds the
-  // step (n <= 10: 0.30 vs 0.52 ms at n = 9); from n = 11 on cache bandwidth
-  // does, and the plain one is 2 % faster (n = 12: 53.4 vs 54.5 ms)
-  if (vec && ldx >= (ncols + 7) / 8 * 8 && N < 16384)
+  // the pipelined kernel (two rounds of gathers in flight) wherever rows can
+  // be read as whole 16-byte chunks: with the blocks taken longest first it
+  // is as fast as the plain one at n = 12 (45.6 ms) and faster below (n = 11:
+  // 5.41 vs 5.58 ms; n = 9: 0.30 vs 0.52 ms)
+  if (vec && ldx >= (ncols + 7) / 8 * 8)
     hipLaunchKernelGGL((block_step_pipe_kernel<4>), grid, dim3(256), 0, s, N, bptr, ent, border,
                        X, ldx, Y, ldy, ncols);
   else if (vec)
