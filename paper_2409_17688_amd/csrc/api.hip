@@ -82,6 +82,7 @@ struct State {
   int64_t nent = 0;
   bool csr_ready = false;
   std::vector<uint8_t> zh;                // zero counts on the host
+  std::vector<int32_t> degh;              // out-degrees on the host
   std::map<int, DevBuf> sel;              // states with <= k zeros (device int32), by k
   std::map<int, int64_t> sel_count;
 };
@@ -163,7 +164,11 @@ int get_state(int n, hipStream_t s, State **out) {
                                 hipMemcpyDeviceToHost, s));
     TP_HIP_CHECK(hipStreamSynchronize(s));
     std::vector<int32_t> ord((size_t)N);
-    for (int64_t i = 0; i < N; ++i) ord[i] = (int32_t)i;
+    st.degh.assign((size_t)N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+      ord[i] = (int32_t)i;
+      st.degh[i] = (int32_t)(rp[i + 1] - rp[i]);
+    }
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
       return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
     });
@@ -494,6 +499,7 @@ int state_view(int n, hipStream_t s, StateView *out) {
   out->nent = st->nent;
   out->order = (const int32_t *)st->order.ptr;
   out->border = (const int32_t *)st->border.ptr;
+  out->degh = st->degh.data();
   return TP_OK;
 }
 

@@ -93,7 +93,6 @@ struct Slot {
   const uint32_t *masks;
   const int64_t *rowptr;
   const uint32_t *colz;     // successors with their labels in the top byte
-  const int32_t *order;     // rows by decreasing out-degree
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
 };
 
@@ -110,14 +109,18 @@ struct Control {
 
 constexpr int kMaxSlots = 16;
 
-// Fused mode: one chain level (exponent k) of every slot that needs it; its
-// work items are (row, 512-column panel) pairs, panel-major per slot, the
-// i-th slot's being [begin[i], begin[i+1]).
+// Fused mode: one chain level (exponent k) of every slot that needs it.  Its
+// work items are (slot, 512-column panel, row) triples packed in 32 bits
+// (slot in bits 28..31, panel in 20..27, row in 0..19), items[off ..
+// off + count) of the launch's item list, ordered by decreasing length of the
+// row's successor list; levels with the same slots share one list.
 struct Level {
-  int32_t count, k;
-  int32_t slot[kMaxSlots];
-  int64_t begin[kMaxSlots + 1];
+  int32_t k, pad;
+  int64_t off, count;
 };
+__host__ __device__ constexpr uint32_t item_code(int slot, int64_t panel, int64_t q) {
+  return ((uint32_t)slot << 28) | ((uint32_t)panel << 20) | (uint32_t)q;
+}
 // Level barrier counters at the start of the counter array, each on a
 // 256-byte line of its own (atomics on one line serialize): workgroups per
 // XCC, then the registrations, then arrivals per XCC and the XCCs done.  The
@@ -164,6 +167,7 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
                                                        const Task *__restrict__ tasks,
                                                        const Slot *__restrict__ slots,
                                                        const Level *__restrict__ levels,
+                                                       const uint32_t *__restrict__ items,
                                                        int32_t *__restrict__ counters,
                                                        int32_t *__restrict__ results) {
   // one LDS arena: the dense product's A and B slabs, or a trace's Y tile
@@ -207,23 +211,26 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
     for (int L = 0; L < nlev; ++L) {
       if (ld_relaxed(&ctl->abort) == 0) {
         const Level &lv = levels[L];
-        const int64_t total = lv.begin[lv.count];
-        for (int64_t item = (int64_t)blockIdx.x * 4 + wv; item < total;
-             item += (int64_t)gridDim.x * 4) {
-          int i = 0;
-          while (i + 1 < lv.count && item >= lv.begin[i + 1]) ++i;
-          const Slot sl = slots[lv.slot[i]];
+        const int64_t count = lv.count;
+        const kconst_u32 list = (kconst_u32)(items + lv.off);
+        // items longest first, dealt to the waves in a snake (wave w takes
+        // position w of even rounds and W - 1 - w of odd ones), so every
+        // wave's share adds up to about the same length
+        const int32_t W = (int32_t)gridDim.x * 4, w = (int32_t)blockIdx.x * 4 + wv;
+        int32_t odd = 0;
+        for (int64_t base = 0; base < count; base += W, odd ^= 1) {
+          const int64_t p = base + (odd ? W - 1 - w : w);
+          if (p >= count) continue;
+          const uint32_t code = list[p];
+          const Slot sl = slots[code >> 28];
           const int64_t N = sl.N, ld = sl.ld;
-          const int64_t l = item - lv.begin[i];
-          const int64_t panel = l / N, slot = l - panel * N;
-          // rows with the longest successor lists first
-          const int64_t q = sl.order ? (int64_t)((kconst_i32)sl.order)[slot] : slot;
+          const int64_t panel = (code >> 20) & 0xFFu, q = code & 0xFFFFFu;
           const int64_t c0 = panel * kPanel + (int64_t)lane * 8;
           if (c0 >= N) {
             // lanes past the last column of the last panel (their loads
             // would leave X's rows)
           } else if (lv.k >= 2) {
-            gather_row_colz<6>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, sl.powers[lv.k - 1],
+            gather_row_colz<7>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, sl.powers[lv.k - 1],
                                ld, sl.powers[lv.k], ld, N, q, c0);
           } else {
             // A^1: row q, this lane's 8 columns
@@ -231,9 +238,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
             uint16_t e[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-              const int64_t p = c0 + j;
-              const uint32_t mp = p < N ? sl.masks[p] : 0u;
-              e[j] = (p < N && can_follow(mq, mp, sl.full))
+              const int64_t pc = c0 + j;
+              const uint32_t mp = pc < N ? sl.masks[pc] : 0u;
+              e[j] = (pc < N && can_follow(mq, mp, sl.full))
                          ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
                          : kInf;
             }
@@ -386,11 +393,11 @@ struct Ctx {
   int device = 0;
   size_t budget = 0, used = 0;
   std::map<int, PowerSet> sets;
-  Buf d_tasks, d_slots, d_ptrs, d_counters, d_results, d_ctl, d_levels;
-  Buf h_tasks, h_slots, h_ptrs, h_ctl, h_levels;
+  Buf d_tasks, d_slots, d_ptrs, d_counters, d_results, d_ctl, d_levels, d_items;
+  Buf h_tasks, h_slots, h_ptrs, h_ctl, h_levels, h_items;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
-  void *g_key[4] = {nullptr, nullptr, nullptr, nullptr};
+  void *g_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   size_t g_counter_cap = 0, g_result_cap = 0;
   int g_grid = 0;
   hipEvent_t staged = nullptr;
@@ -495,7 +502,8 @@ int capture_graph(Ctx *c, int grid) {
                      (int32_t *)c->d_results.p, nr, (int32_t)kInf);
   hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(256), 0, c->cap_stream, (Control *)c->d_ctl.p,
                      (const Task *)c->d_tasks.p, (const Slot *)c->d_slots.p,
-                     (const Level *)c->d_levels.p, (int32_t *)c->d_counters.p,
+                     (const Level *)c->d_levels.p, (const uint32_t *)c->d_items.p,
+                     (int32_t *)c->d_counters.p,
                      (int32_t *)c->d_results.p);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -507,6 +515,7 @@ int capture_graph(Ctx *c, int grid) {
   c->g_key[1] = c->d_counters.p;
   c->g_key[2] = c->d_results.p;
   c->g_key[3] = c->d_levels.p;
+  c->g_key[4] = c->d_items.p;
   c->g_counter_cap = c->d_counters.bytes;
   c->g_result_cap = c->d_results.bytes;
   c->g_grid = grid;
@@ -654,20 +663,54 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   // ends in a barrier over the grid, so the tasks below see complete powers
   // in both modes
   std::vector<Level> levels;
+  std::vector<uint32_t> items;
   if (fused) {
     int max_top = 0;
     for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
+    std::vector<int> prev_set;
+    int64_t off = 0, cnt = 0;
     for (int k = 1; k <= max_top; ++k) {
+      std::vector<int> set;
+      for (int s = 0; s < nslots; ++s)
+        if (k >= k0[s] && k <= plans[s].chain_top) set.push_back(s);
+      if (set.empty()) continue;
+      if (set != prev_set) {
+        // the items of these slots by decreasing length of the row's
+        // successor list (a bucket per out-degree), a row's panels together
+        int maxdeg = 0;
+        for (int s : set) {
+          const Plan &p = plans[s];
+          for (int64_t q = 0; q < p.view.N; ++q) maxdeg = std::max(maxdeg, (int)p.view.degh[q]);
+        }
+        std::vector<int64_t> pos((size_t)maxdeg + 1, 0);
+        for (int s : set) {
+          const Plan &p = plans[s];
+          const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
+          for (int64_t q = 0; q < p.view.N; ++q) pos[p.view.degh[q]] += panels;
+        }
+        off = (int64_t)items.size();
+        int64_t at = off;
+        for (int d = maxdeg; d >= 0; --d) {
+          const int64_t n_d = pos[d];
+          pos[d] = at;
+          at += n_d;
+        }
+        cnt = at - off;
+        items.resize((size_t)at);
+        for (int s : set) {
+          const Plan &p = plans[s];
+          const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
+          for (int64_t q = 0; q < p.view.N; ++q)
+            for (int64_t P = 0; P < panels; ++P)
+              items[(size_t)pos[p.view.degh[q]]++] = item_code(s, P, q);
+        }
+        prev_set = set;
+      }
       Level lv{};
       lv.k = k;
-      for (int s = 0; s < nslots; ++s) {
-        if (k < k0[s] || k > plans[s].chain_top) continue;
-        const int64_t N = c->sets[plans[s].n].N;
-        lv.slot[lv.count] = s;
-        lv.begin[lv.count + 1] = lv.begin[lv.count] + N * ((N + kPanel - 1) / kPanel);
-        ++lv.count;
-      }
-      if (lv.count > 0) levels.push_back(lv);
+      lv.off = off;
+      lv.count = cnt;
+      levels.push_back(lv);
     }
   }
   // completion counters: the level barriers first, then the giants (one per
@@ -848,10 +891,14 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max<int64_t>(counter_words, 1) * sizeof(int32_t)));
   TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t)));
   const size_t lbytes = levels.size() * sizeof(Level);
+  const size_t ibytes = items.size() * sizeof(uint32_t);
   if (lbytes) {
     TP_HIP_CHECK(grow_host(c->h_levels, lbytes));
     TP_HIP_CHECK(grow(c->d_levels, lbytes));
     memcpy(c->h_levels.p, levels.data(), lbytes);
+    TP_HIP_CHECK(grow_host(c->h_items, ibytes));
+    TP_HIP_CHECK(grow(c->d_items, ibytes));
+    memcpy(c->h_items.p, items.data(), ibytes);
   }
 
   memcpy(c->h_tasks.p, tasks.data(), tbytes);
@@ -868,7 +915,6 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.masks = p.view.masks;
     sl.rowptr = p.view.rowptr;
     sl.colz = p.view.colz;
-    sl.order = p.view.order;
     sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
     hs[s] = sl;
     for (size_t e = 0; e < ptr_stride; ++e) {
@@ -892,7 +938,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   int grid = c->grid_override > 0 ? c->grid_override : resident;
   if (!levels.empty()) grid = std::min(grid, resident);
   if (!c->exec || c->g_key[0] != c->d_tasks.p || c->g_key[1] != c->d_counters.p ||
-      c->g_key[2] != c->d_results.p || c->g_key[3] != c->d_levels.p || c->g_grid != grid ||
+      c->g_key[2] != c->d_results.p || c->g_key[3] != c->d_levels.p ||
+      c->g_key[4] != c->d_items.p || c->g_grid != grid ||
       c->g_counter_cap != c->d_counters.bytes || c->g_result_cap != c->d_results.bytes) {
     const int rc = capture_graph(c, grid);
     if (rc != TP_OK) return rc;
@@ -904,9 +951,12 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
                               hipMemcpyHostToDevice, stream));
   TP_HIP_CHECK(hipMemcpyAsync(c->d_ctl.p, c->h_ctl.p, sizeof(Control), hipMemcpyHostToDevice,
                               stream));
-  if (lbytes)
+  if (lbytes) {
     TP_HIP_CHECK(hipMemcpyAsync(c->d_levels.p, c->h_levels.p, lbytes, hipMemcpyHostToDevice,
                                 stream));
+    TP_HIP_CHECK(hipMemcpyAsync(c->d_items.p, c->h_items.p, ibytes, hipMemcpyHostToDevice,
+                                stream));
+  }
   if (!c->staged) TP_HIP_CHECK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
   TP_HIP_CHECK(hipEventRecord(c->staged, stream));
   if (levels.empty()) {
@@ -968,11 +1018,11 @@ void ctx_free(Ctx *c) {
   }
   for (auto &kv : c->sets)
     for (void *slab : kv.second.slabs) (void)hipFree(slab);
-  Buf *dev[] = {&c->d_tasks,   &c->d_slots, &c->d_ptrs,  &c->d_counters,
-                &c->d_results, &c->d_ctl,   &c->d_levels};
+  Buf *dev[] = {&c->d_tasks, &c->d_slots,  &c->d_ptrs,   &c->d_counters,
+                &c->d_results, &c->d_ctl, &c->d_levels, &c->d_items};
   for (Buf *b : dev)
     if (b->p) (void)hipFree(b->p);
-  Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl, &c->h_levels};
+  Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl, &c->h_levels, &c->h_items};
   for (Buf *b : host)
     if (b->p) (void)hipHostFree(b->p);
 }

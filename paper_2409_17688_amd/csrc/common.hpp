@@ -115,6 +115,7 @@ struct StateView {
   int64_t nent;
   const int32_t *order;   // rows by decreasing out-degree
   const int32_t *border;  // row blocks by decreasing entry count
+  const int32_t *degh;    // host: out-degree of each row
 };
 int state_view(int n, hipStream_t s, StateView *out);
 // Y = A(D_n) x X (u16) in the form the library picks for n (tp_tune_step).
