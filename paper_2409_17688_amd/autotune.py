@@ -13,8 +13,8 @@ What it tunes (none of it changes a result, only which kernel shape runs):
     rates of that step and of the tuned dense product per n
     (``tp_tune_planner``);
   * the batch engine, n = 4..9: baby steps c for the default mode and for
-    the fused mode, on a batch of 12 instances with m uniform in 3..200
-    (``tp_tune_batch``).
+    the fused mode, on a batch of 32 instances with m uniform in 3..256,
+    median of three cold batches per candidate (``tp_tune_batch``).
 
 Every candidate is checked against the reference shape (tile configuration
 0 without a split for products, the built-in batch parameters for batches):
@@ -141,7 +141,8 @@ def tune_planner(ns, log):
 
 
 def _batch_time(ns, ms, params, reps=3):
-    best, res = None, None
+    """(median seconds of `reps` cold batches on fresh contexts, answers)."""
+    times, res = [], None
     for _ in range(reps):
         ctx = tp.tp_ctx_create(64 << 30)
         try:
@@ -155,19 +156,19 @@ def _batch_time(ns, ms, params, reps=3):
             res = r.cpu().numpy().tolist()
         finally:
             tp.tp_ctx_destroy(ctx)
-        best = t if best is None else min(best, t)
-    return best, res
+        times.append(t)
+    return sorted(times)[len(times) // 2], res
 
 
 def tune_batch(ns, baby_list, seed, log):
     """{n: [baby steps, seconds, fused baby steps, seconds]}: fastest cold
-    batch of 12 instances in each mode."""
+    batch of 32 instances in each mode (median of three per candidate)."""
     rng = np.random.default_rng(seed)
     out = {}
     # load the batch kernel once so that the first candidate is not charged for it
     _batch_time([4], [5], {}, reps=1)
     for n in ns:
-        ms = [int(m) for m in rng.integers(3, 201, 12)]
+        ms = [int(m) for m in rng.integers(3, 257, 32)]
         nl = [n] * len(ms)
         tp.tp_tropical_power_trace(n, 3)  # state in the cache
         _, ref = _batch_time(nl, ms, {}, reps=1)
