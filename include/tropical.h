@@ -198,6 +198,50 @@ int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, 
  * rule).  The power chains of tp_tropical_power_trace use it too. */
 int tp_tune_step(int n, int form);
 
+/* Compact powers: a power P of A(D_n) held as 8-bit residuals x plus one
+ * int32 offset per row, P[q][c] = R[q] + x[q][c] with x in 0..254; a row of
+ * INF entries only is R[q] = 0x3FFFFFFF with x = 255.  Half the bytes of the
+ * 16-bit form for the power chain of Algorithm 2.  Status words are device
+ * int32 that the calls OR bits into (the caller clears them and reads them
+ * when convenient): 1 = a row spans more than 254 or a result cannot be held
+ * (the matrix written is then not valid), 2 = a row mixes finite and INF
+ * entries (the same).  Leading dimensions are in elements (bytes for the
+ * residuals). */
+
+/* d_Y (N x ncols, u8 residuals) and d_R (N, int32) from the 16-bit matrix
+ * d_X (N x ncols): R[q] = least entry of row q, x = entry - R[q].  One
+ * workgroup per row.  TP_EINVAL on a bad size or NULL pointer. */
+int tp_compact_from_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx, void *d_Y,
+                        int64_t ldy, int32_t *d_R, int32_t *d_status, hipStream_t stream);
+
+/* d_Y (N x ncols, u16) = min(R[q] + x[q][c], INF = 65535), x = 255 giving
+ * INF: the 16-bit form of a compact power, equal to the 16-bit chain's. */
+int tp_compact_to_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx, const int32_t *d_R,
+                      void *d_Y, int64_t ldy, hipStream_t stream);
+
+/* (d_Y, d_RY) = A(D_n) x (d_X, d_RX) in compact form, N = tp_state_dim(n)
+ * rows of ncols columns: Algorithm 2's left step with the arc labels of
+ * Section 2.2 (they depend on the successor only, so a row's new offset is
+ * min over its successors p of z_p + R_X[p] and the residuals need one add
+ * per gathered row).  The residuals of a held power never grow under the
+ * step, so a held input gives a held output.  d_X and d_Y: 8-byte aligned,
+ * ld a multiple of 8 and at least ncols rounded up to 8; X, Y and the two
+ * offset vectors must not overlap.  1 <= n <= 13.  Uses the cached blocked
+ * and CSR forms of A(D_n) (built on first use per device and n). */
+int tp_compact_step(int n, const void *d_X, int64_t ldx, const int32_t *d_RX, void *d_Y,
+                    int64_t ldy, int32_t *d_RY, int64_t ncols, int32_t *d_status,
+                    hipStream_t stream);
+
+/* *d_out = min over rows q with x[q][q] != 255 of min(R[q] + x[q][q], 65535)
+ * (65535 when there is none): the diagonal minimum of Theorem 2 on a square
+ * compact power (ldx >= N). */
+int tp_compact_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *d_R,
+                        int32_t *d_out, hipStream_t stream);
+
+/* Gathers per round in tp_compact_step (4, the default, or 8).  Changes
+ * speed only. */
+int tp_tune_compact_step(int unroll);
+
 /* All-pairs shortest paths by (min,+) squaring, the same semiring (Section 1)
  * on another workload: d_D (N x N) = (I + W)^(2^t), t = ceil(log2(N - 1)),
  * where W holds non-negative arc weights (INF = no arc) and I is the (min,+)

@@ -92,6 +92,11 @@ _SIGS = {
     "tp_build_state_columns": ([_i, _p, _i64, _p, _i64, _p], _i),
     "tp_diag_select_min": ([_i64, _i64, _p, _p, _i64, _p, _p], _i),
     "tp_tune_prune": ([_i], _i),
+    "tp_compact_from_u16": ([_i64, _i64, _p, _i64, _p, _i64, _p, _p, _p], _i),
+    "tp_compact_to_u16": ([_i64, _i64, _p, _i64, _p, _p, _i64, _p], _i),
+    "tp_compact_step": ([_i, _p, _i64, _p, _p, _i64, _p, _i64, _p, _p], _i),
+    "tp_compact_diag_min": ([_i64, _p, _i64, _p, _p, _p], _i),
+    "tp_tune_compact_step": ([_i], _i),
     "tp_const_diff": ([_i64, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_recurrence": ([_i, _i, _i, ctypes.POINTER(Recurrence), ctypes.POINTER(ctypes.c_int32),
                        _p], _i),
@@ -502,6 +507,90 @@ def tp_apsp(W: torch.Tensor, D: torch.Tensor | None = None, T: torch.Tensor | No
     pt, _, _, ldt = _mat(T, "T")
     _check(lib.tp_apsp(dt, N, pw, ldw, pd, ldd, pt, ldt, _stream(stream)))
     return D
+
+
+# ---------------------------------------------------------- compact powers --
+COMPACT_DEAD = 0x3FFFFFFF
+COMPACT_RANGE, COMPACT_MIXED = 1, 2
+
+
+def _u8rows(M: torch.Tensor, name: str, ncols: int):
+    if M.dtype != torch.uint8 or M.dim() != 2 or M.device.type != "cuda":
+        raise ValueError(f"{name} must be a 2-D uint8 CUDA tensor")
+    if M.stride(1) != 1 or M.shape[1] < ncols:
+        raise ValueError(f"{name} needs unit column stride and at least {ncols} columns")
+    return ctypes.c_void_p(M.data_ptr()), M.shape[0], M.stride(0)
+
+
+def tp_compact_from_u16(X: torch.Tensor, Y: torch.Tensor | None = None,
+                        R: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                        stream=None):
+    """(Y, R): the compact form of the 16-bit matrix X (u8 residuals, one
+    int32 offset per row).  Bits of ``status`` (int32 CUDA tensor of one
+    element, ORed into): COMPACT_RANGE, COMPACT_MIXED."""
+    if X.dtype != torch.uint16:
+        raise ValueError("X must be uint16")
+    px, N, ncols, ldx = _mat(X, "X")
+    if Y is None:
+        Y = torch.empty((N, (ncols + 7) // 8 * 8 or 8), dtype=torch.uint8, device=X.device)
+    if R is None:
+        R = torch.empty(max(N, 1), dtype=torch.int32, device=X.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+    py, Ny, ldy = _u8rows(Y, "Y", ncols)
+    if Ny != N or R.numel() < N or R.dtype != torch.int32:
+        raise ValueError("Y must have N rows and R N int32 entries")
+    _check(lib.tp_compact_from_u16(N, ncols, px, ldx, py, ldy, ctypes.c_void_p(R.data_ptr()),
+                                   ctypes.c_void_p(status.data_ptr()), _stream(stream)))
+    return Y, R
+
+
+def tp_compact_to_u16(X: torch.Tensor, R: torch.Tensor, ncols: int,
+                      Y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The 16-bit form (N x ncols) of the compact matrix (X, R)."""
+    px, N, ldx = _u8rows(X, "X", ncols)
+    if Y is None:
+        Y = torch.empty((N, ncols), dtype=torch.uint16, device=X.device)
+    py, Ny, nc, ldy = _mat(Y, "Y")
+    if Ny != N or nc != ncols or R.numel() < N or R.dtype != torch.int32:
+        raise ValueError("Y must be N x ncols and R N int32 entries")
+    _check(lib.tp_compact_to_u16(N, ncols, px, ldx, ctypes.c_void_p(R.data_ptr()), py, ldy,
+                                 _stream(stream)))
+    return Y
+
+
+def tp_compact_step(n: int, X: torch.Tensor, RX: torch.Tensor, ncols: int,
+                    Y: torch.Tensor | None = None, RY: torch.Tensor | None = None,
+                    status: torch.Tensor | None = None, stream=None):
+    """(Y, RY) = A(D_n) x (X, RX) in compact form."""
+    px, N, ldx = _u8rows(X, "X", ncols)
+    if Y is None:
+        Y = torch.empty_like(X)
+    if RY is None:
+        RY = torch.empty_like(RX)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+    py, Ny, ldy = _u8rows(Y, "Y", ncols)
+    if Ny != N or RX.dtype != torch.int32 or RY.dtype != torch.int32 or \
+            RX.numel() < N or RY.numel() < N:
+        raise ValueError("Y must have N rows and RX, RY N int32 entries")
+    _check(lib.tp_compact_step(int(n), px, ldx, ctypes.c_void_p(RX.data_ptr()), py, ldy,
+                               ctypes.c_void_p(RY.data_ptr()), int(ncols),
+                               ctypes.c_void_p(status.data_ptr()), _stream(stream)))
+    return Y, RY
+
+
+def tp_compact_diag_min(X: torch.Tensor, R: torch.Tensor, stream=None) -> int:
+    """Diagonal minimum of a square compact power (Theorem 2)."""
+    px, N, ldx = _u8rows(X, "X", X.shape[0])
+    out = torch.empty(1, dtype=torch.int32, device=X.device)
+    _check(lib.tp_compact_diag_min(N, px, ldx, ctypes.c_void_p(R.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return int(out.item())
+
+
+def tp_tune_compact_step(unroll: int) -> None:
+    _check(lib.tp_tune_compact_step(int(unroll)))
 
 
 def tp_release_cache() -> None:

@@ -1,0 +1,390 @@
+// Compact powers: the chain step on 8-bit residuals with one offset per row.
+//
+// A power P of A(D_n) is held as
+//   P[q][c] = R[q] + x[q][c],   x in 0..254 (u8),   R[q] int32,
+// half the bytes of the 16-bit form, with a row whose entries are all INF
+// held as R[q] = kDead and x = 255.  A row can be held when its entries are
+// all finite and span at most 254; a row with both finite and INF entries,
+// or a wider one, is reported by the conversion.  The powers of A(D_n) reach
+// that shape after a few steps (every state then reaches every other, and
+// the entries of a row differ by a few units).
+//
+// The left step Y = A(D_n) x X keeps the form.  Row q's offset is
+//   R_Y[q] = min over successors p of q of (z_p + R_X[p]),
+// a (min,+) product of A with the offsets (Section 2.2: the arc label z_p
+// depends on the successor only), and the residuals are
+//   y[q][c] = min over p of (z_p + R_X[p] - R_Y[q] + x[p][c]).
+// With p* the successor that gives R_Y[q], y[q][c] <= x[p*][c]: residuals
+// never grow from one power to the next and rows stay finite, so a held
+// power's successors can be held too.  The shifts z_p + R_X[p] - base are
+// per-entry constants, so the step is the blocked gather of blockstep.hip
+// (16 rows per block, the union of their successor lists, one add per entry
+// shared by the block's rows, then mins) on half the gathered bytes; base is
+// the least offset of the block's rows and each row subtracts its own offset
+// at the store.  Offsets are exact integers: P[q][c] above 65535 is INF only
+// when expanded to the 16-bit form, as the 16-bit chain saturates there.
+#include <algorithm>
+
+#include "device_core.hpp"
+
+namespace tp {
+
+namespace {
+
+constexpr int kRows = 16;                // rows per block (the blocked form's)
+constexpr int32_t kDead = 0x3FFFFFFF;    // offset of an all-INF row
+constexpr int32_t kMaxGap = 0xFF00;      // largest offset gap inside a block
+constexpr int32_t kStatusRange = 1;      // a residual above 254 or a gap above kMaxGap
+constexpr int32_t kStatusMixed = 2;      // a row with finite and INF entries
+
+int g_unroll = 4;  // entries per round of the step (4 or 8)
+
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// R_Y[q] = min over successors p (CSR with labels in the top byte) of
+// z_p + R_X[p], over live successors only; kDead when none is live.  One
+// wave per row.
+__global__ void __launch_bounds__(256) compact_offsets_kernel(int64_t N, const int64_t *rowptr,
+                                                              const uint32_t *colz,
+                                                              const int32_t *RX, int32_t *RY) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= N) return;
+  const gconst<int32_t> rx = to_global(RX);
+  const gconst<uint32_t> cz = to_global(colz);
+  int32_t m = kDead;
+  for (int64_t e = rowptr[q] + lane; e < rowptr[q + 1]; e += 64) {
+    const uint32_t c = cz[e];
+    const int32_t r = rx[c & 0xFFFFFFu];
+    if (r < kDead) m = min(m, r + (int32_t)(c >> 24));
+  }
+  m = wave_min_i32(m);
+  if (lane == 0) RY[q] = m;
+}
+
+// Four residuals (bytes of w) as two packed 16-bit pairs.
+__device__ __forceinline__ void unpack8(uint32_t w, u16x2 &lo, u16x2 &hi) {
+  lo = as_pk(__builtin_amdgcn_perm(0u, w, 0x0c010c00u));
+  hi = as_pk(__builtin_amdgcn_perm(0u, w, 0x0c030c02u));
+}
+
+// acc[r] = min(acc[r], lab + v) for the rows r whose bit is set in m.
+__device__ __forceinline__ void apply_entry(u16x2 (&acc)[kRows][4], uint32_t m, u16x2 lab,
+                                            const u16x2 (&v)[4]) {
+  u16x2 s[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = pk_add_sat(lab, v[k]);
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    if (m & (1u << r)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[r][k] = pk_min(acc[r][k], s[k]);
+    }
+  }
+}
+
+// One wave per (block of 16 rows, 512-column panel); lanes own 8 columns
+// (8 bytes of each gathered row); blocks by decreasing entry count; two
+// rounds of U gathers in flight.  Rows of X and Y are read and written as
+// whole 8-byte chunks (ldx, ldy multiples of 8, at least ncols rounded up).
+template <int U>
+__global__ void __launch_bounds__(256) compact_step_kernel(
+    int64_t N, const int64_t *__restrict__ bptr, const uint64_t *__restrict__ ent,
+    const int32_t *__restrict__ border, const uint8_t *__restrict__ X, int64_t ldx,
+    const int32_t *__restrict__ RX, uint8_t *__restrict__ Y, int64_t ldy,
+    const int32_t *__restrict__ RY, int64_t ncols, int32_t *__restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t groups = (nblocks + 3) / 4;
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t panel = t / groups;
+  const int64_t bslot = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (bslot >= nblocks) return;
+  const int64_t b = border ? (int64_t)((kconst_i32)border)[bslot] : bslot;
+  const int64_t c0 = (panel * 64 + lane) * 8;
+  const kconst_i64 bp = (kconst_i64)bptr;
+  const kconst_u64 en = (kconst_u64)ent;
+  const kconst_i32 rx = (kconst_i32)RX;
+  const kconst_i32 ry = (kconst_i32)RY;
+  const gconst<u32x2> Xg = (gconst<u32x2>)to_global(X);
+  const int64_t ld8 = ldx / 8;
+  // lanes past the last column read chunk 0 of each row and store nothing
+  const uint32_t off = c0 < ncols ? (uint32_t)(c0 / 8) : 0u;
+
+  int32_t base = kDead;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    if (q < N) base = min(base, ry[q]);
+  }
+
+  u16x2 acc[kRows][4];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[r][k] = splat(0xFFFFu);
+
+  const int64_t e0 = bp[b], e1 = bp[b + 1];
+  if (base < kDead && e0 < e1) {
+    const int64_t last = e1 - 1;
+    // per entry: mz = label z_p in bits 0..7, row mask in bits 8..23
+    auto fetch = [&](int64_t i, uint32_t (&w)[U], int32_t (&o)[U], u32x2 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = i + u;
+        const uint64_t x = en[k < last ? k : last];
+        const uint32_t mz = (uint32_t)(x >> 24);
+        w[u] = k <= last ? mz : (mz & 0xFFu);  // past the end: no rows
+        const int64_t p = (int64_t)(uint32_t)(x & 0xFFFFFFu);
+        o[u] = rx[p];
+        v[u] = Xg[p * ld8 + off];
+      }
+    };
+    auto apply = [&](const uint32_t (&w)[U], const int32_t (&o)[U], const u32x2 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // z_p + R_X[p] - base >= 0 for every successor of the block's rows
+        const int32_t sh = o[u] + (int32_t)(w[u] & 0xFFu) - base;
+        const uint16_t lab = (o[u] >= kDead || sh > 0xFFFF) ? (uint16_t)0xFFFFu : (uint16_t)sh;
+        u16x2 row[4];
+        unpack8(v[u].x, row[0], row[1]);
+        unpack8(v[u].y, row[2], row[3]);
+        apply_entry(acc, w[u] >> 8, splat(lab), row);
+      }
+    };
+    uint32_t wa[U], wb[U];
+    int32_t oa[U], ob[U];
+    u32x2 va[U], vb[U];
+    fetch(e0, wa, oa, va);
+    for (int64_t i = e0;;) {
+      bool more = i + U <= last;
+      if (more) fetch(i + U, wb, ob, vb);
+      apply(wa, oa, va);
+      i += U;
+      if (!more) break;
+      more = i + U <= last;
+      if (more) fetch(i + U, wa, oa, va);
+      apply(wb, ob, vb);
+      i += U;
+      if (!more) break;
+    }
+  }
+  if (c0 >= ncols) return;
+  uint32_t bad = 0;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    if (q >= N) break;
+    // (a vector load: the block's 16 offsets are not kept in scalar
+    // registers across the gather loop)
+    const int32_t rq = to_global(RY)[q];
+    uint32_t lo, hi;
+    if (rq >= kDead) {
+      lo = hi = 0xFFFFFFFFu;
+    } else {
+      const int32_t gap = rq - base;
+      if (gap > kMaxGap) bad = 1;
+      const u16x2 d = splat((uint16_t)min(gap, 0xFFFF));
+      u16x2 y[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) y[k] = __builtin_elementwise_sub_sat(acc[r][k], d);
+      // residuals above 254 (not possible from held inputs) are reported
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (c0 + 2 * k < ncols && y[k].x > 254) bad = 1;
+        if (c0 + 2 * k + 1 < ncols && y[k].y > 254) bad = 1;
+      }
+      lo = __builtin_amdgcn_perm(as_u32(y[1]), as_u32(y[0]), 0x06040200u);
+      hi = __builtin_amdgcn_perm(as_u32(y[3]), as_u32(y[2]), 0x06040200u);
+    }
+    if (c0 + 8 <= ncols) {
+      *(gmut<u32x2>)(to_global_mut(Y) + q * ldy + c0) = u32x2{lo, hi};
+    } else {
+      const gmut<uint8_t> yp = to_global_mut(Y) + q * ldy + c0;
+      for (int k = 0; k < 8 && c0 + k < ncols; ++k)
+        yp[k] = (uint8_t)(((k < 4 ? lo : hi) >> (8 * (k & 3))) & 0xFFu);
+    }
+  }
+  if (bad) atomicOr(status, kStatusRange);
+}
+
+// One workgroup (256 lanes) per row: R = least entry, x = entry - R.
+__global__ void __launch_bounds__(256) compact_from_u16_kernel(int64_t ncols, const uint16_t *X,
+                                                               int64_t ldx, uint8_t *Y,
+                                                               int64_t ldy, int32_t *R,
+                                                               int32_t *status) {
+  __shared__ int32_t red[3][4];
+  const int64_t q = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const gconst<uint16_t> x = to_global(X) + q * ldx;
+  int32_t mn = 0xFFFF, mx = -1, inf = 0;
+  for (int64_t c = threadIdx.x; c < ncols; c += 256) {
+    const int32_t v = x[c];
+    mn = min(mn, v);
+    if (v == 0xFFFF) inf = 1;
+    else mx = max(mx, v);
+  }
+  mn = wave_min_i32(mn);
+  mx = wave_max_i32(mx);
+  inf = wave_max_i32(inf);
+  if (lane == 0) {
+    red[0][wv] = mn;
+    red[1][wv] = mx;
+    red[2][wv] = inf;
+  }
+  __syncthreads();
+  mn = min(min(red[0][0], red[0][1]), min(red[0][2], red[0][3]));
+  mx = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
+  inf = max(max(red[2][0], red[2][1]), max(red[2][2], red[2][3]));
+  const bool dead = (mn == 0xFFFF);
+  if (threadIdx.x == 0) {
+    R[q] = dead ? kDead : mn;
+    int32_t st = 0;
+    if (!dead && inf) st |= kStatusMixed;
+    if (!dead && mx - mn > 254) st |= kStatusRange;
+    if (st) atomicOr(status, st);
+  }
+  const gmut<uint8_t> y = to_global_mut(Y) + q * ldy;
+  for (int64_t c = threadIdx.x; c < ncols; c += 256) {
+    const int32_t v = x[c];
+    y[c] = (dead || v == 0xFFFF) ? (uint8_t)0xFF : (uint8_t)min(v - mn, 255);
+  }
+}
+
+// P[q][c] = R[q] + x[q][c] saturated at INF = 65535 (x = 255 is INF).
+__global__ void __launch_bounds__(256) compact_to_u16_kernel(int64_t ncols, const uint8_t *X,
+                                                             int64_t ldx, const int32_t *R,
+                                                             uint16_t *Y, int64_t ldy) {
+  const int64_t q = blockIdx.x;
+  const int32_t r = R[q];
+  const gconst<uint8_t> x = to_global(X) + q * ldx;
+  const gmut<uint16_t> y = to_global_mut(Y) + q * ldy;
+  for (int64_t c = (int64_t)blockIdx.y * 256 + threadIdx.x; c < ncols;
+       c += (int64_t)gridDim.y * 256) {
+    const int32_t v = x[c];
+    y[c] = (r >= kDead || v == 0xFF) ? (uint16_t)0xFFFFu : (uint16_t)min(r + v, 0xFFFF);
+  }
+}
+
+// out = min(*out, min over live rows q of R[q] + x[q][q]) (entries past 65535
+// count as INF = 65535).
+__global__ void __launch_bounds__(256) compact_diag_kernel(int64_t N, const uint8_t *X,
+                                                           int64_t ldx, const int32_t *R,
+                                                           int32_t *out) {
+  __shared__ int32_t red[4];
+  int32_t m = 0xFFFF;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < N; q += (int64_t)gridDim.x * 256) {
+    const int32_t r = R[q];
+    const int32_t v = X[q * ldx + q];
+    if (r < kDead && v != 0xFF) m = min(m, min(r + v, 0xFFFF));
+  }
+  m = wave_min_i32(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = min(min(red[0], red[1]), min(red[2], red[3]));
+    if (m < 0xFFFF) atomicMin(out, m);
+  }
+}
+
+bool chunk_ok(const void *p, int64_t ld, int64_t ncols) {
+  return ((uintptr_t)p % 8 == 0) && (ld % 8 == 0) && ld >= (ncols + 7) / 8 * 8;
+}
+
+}  // namespace
+
+}  // namespace tp
+
+using namespace tp;
+
+extern "C" {
+
+int tp_compact_from_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx, void *d_Y,
+                        int64_t ldy, int32_t *d_R, int32_t *d_status, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && ncols >= 0 && N < ((int64_t)1 << 31), "bad size");
+  if (N == 0) return TP_OK;
+  TP_REQUIRE(ldx >= (ncols > 0 ? ncols : 1) && ldy >= (ncols > 0 ? ncols : 1),
+             "leading dimension < ncols");
+  TP_REQUIRE(d_X && d_Y && d_R && d_status, "NULL pointer");
+  hipLaunchKernelGGL(compact_from_u16_kernel, dim3((unsigned)N), dim3(256), 0, stream, ncols,
+                     (const uint16_t *)d_X, ldx, (uint8_t *)d_Y, ldy, d_R, d_status);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_to_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx, const int32_t *d_R,
+                      void *d_Y, int64_t ldy, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && ncols >= 0 && N < ((int64_t)1 << 31), "bad size");
+  if (N == 0 || ncols == 0) return TP_OK;
+  TP_REQUIRE(ldx >= ncols && ldy >= ncols, "leading dimension < ncols");
+  TP_REQUIRE(d_X && d_Y && d_R, "NULL pointer");
+  const dim3 grid((unsigned)N, (unsigned)std::min<int64_t>((ncols + 255) / 256, 64));
+  hipLaunchKernelGGL(compact_to_u16_kernel, grid, dim3(256), 0, stream, ncols,
+                     (const uint8_t *)d_X, ldx, d_R, (uint16_t *)d_Y, ldy);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_step(int n, const void *d_X, int64_t ldx, const int32_t *d_RX, void *d_Y,
+                    int64_t ldy, int32_t *d_RY, int64_t ncols, int32_t *d_status,
+                    hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(ncols >= 0, "negative size");
+  if (ncols == 0) return TP_OK;
+  TP_REQUIRE(d_X && d_Y && d_RX && d_RY && d_status, "NULL pointer");
+  TP_REQUIRE(d_X != d_Y && d_RX != d_RY, "the step cannot run in place");
+  TP_REQUIRE(chunk_ok(d_X, ldx, ncols) && chunk_ok(d_Y, ldy, ncols),
+             "X and Y need 8-byte aligned rows with ld a multiple of 8, at least ncols "
+             "rounded up to 8");
+  StateView v;
+  const int rc = state_view(n, stream, &v);
+  if (rc != TP_OK) return rc;
+  const int64_t N = v.N;
+  hipLaunchKernelGGL(compact_offsets_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, stream,
+                     N, v.rowptr, v.colz, d_RX, d_RY);
+  TP_HIP_CHECK(hipGetLastError());
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t panels = (ncols + 511) / 512;
+  const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
+  if (g_unroll == 8)
+    hipLaunchKernelGGL((compact_step_kernel<8>), grid, dim3(256), 0, stream, N, v.bptr, v.bent,
+                       v.border, (const uint8_t *)d_X, ldx, d_RX, (uint8_t *)d_Y, ldy,
+                       (const int32_t *)d_RY, ncols, d_status);
+  else
+    hipLaunchKernelGGL((compact_step_kernel<4>), grid, dim3(256), 0, stream, N, v.bptr, v.bent,
+                       v.border, (const uint8_t *)d_X, ldx, d_RX, (uint8_t *)d_Y, ldy,
+                       (const int32_t *)d_RY, ncols, d_status);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *d_R,
+                        int32_t *d_out, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && N < ((int64_t)1 << 31), "bad size");
+  TP_REQUIRE(d_out != nullptr, "out is NULL");
+  TP_HIP_CHECK(launch_fill_i32(d_out, 1, 0xFFFF, stream));
+  if (N == 0) return TP_OK;
+  TP_REQUIRE(ldx >= N && d_X && d_R, "bad X or R");
+  const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+  hipLaunchKernelGGL(compact_diag_kernel, dim3(blocks), dim3(256), 0, stream, N,
+                     (const uint8_t *)d_X, ldx, d_R, d_out);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_tune_compact_step(int unroll) {
+  TP_REQUIRE(unroll == 4 || unroll == 8, "unroll %d is not 4 or 8", unroll);
+  g_unroll = unroll;
+  return TP_OK;
+}
+
+}  // extern "C"

@@ -9,6 +9,7 @@
     python -m paper_2409_17688_amd.kernel_bench --op cdiff --n 12
     python -m paper_2409_17688_amd.kernel_bench --op recurrence --n 12 --window 4
     python -m paper_2409_17688_amd.kernel_bench --op apsp --N 8192
+    python -m paper_2409_17688_amd.kernel_bench --op cstep --n 12 --reps 5
 
 Matrices use the library's resident layout (rows padded to 64 entries).
 Times come from HIP events on the launch stream; one JSON line per run with
@@ -23,6 +24,8 @@ the algorithmic work of one launch:
          entries read (4 N^2 bytes)
   recurrence  tp_recurrence(n, K, window): K powers, each compared with the
          window before it, then Algorithms 3 and 4 (wall time)
+  cstep  the same product on compact powers (tp_compact_step: 8-bit residuals,
+         one offset per row), from A^3; the offsets' product is included
   apsp   all-pairs shortest paths on a random digraph of order N (weights
          0..49 on 1 % of the pairs, default_rng(0)): ceil(log2(N-1)) dense
          products of N^3 operations
@@ -56,7 +59,7 @@ def _padded(torch, N):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--op", choices=["spmm", "bstep", "gather", "trace", "gemm", "batch", "cdiff",
-                                     "recurrence", "apsp"], required=True)
+                                     "recurrence", "apsp", "cstep"], required=True)
     ap.add_argument("--n", type=int, default=10)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--config", type=int, default=None, help="dense product tile config")
@@ -66,6 +69,7 @@ def main(argv=None):
     ap.add_argument("--K", type=int, default=50, help="recurrence: powers computed")
     ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
     ap.add_argument("--N", type=int, default=8192, help="apsp: order of the digraph")
+    ap.add_argument("--unroll", type=int, default=4, help="cstep: gathers per round (4 or 8)")
     args = ap.parse_args(argv)
 
     import torch
@@ -96,6 +100,25 @@ def main(argv=None):
         out.update({"n": n, "K": args.K, "window": rec.window, "found": rec.found, "r0": rec.r0,
                     "a": rec.a, "b": rec.b, "n0": rec.n0, "s": min(times),
                     "s_all": [round(t, 3) for t in times]})
+    elif args.op == "cstep":
+        N = tp.tp_state_dim(n)
+        nnz = tp.tp_state_nnz(n)
+        X, Y = _padded(torch, N), _padded(torch, N)
+        tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
+        tp.tp_state_left_mul(n, X, Y)
+        tp.tp_state_left_mul(n, Y, X)  # A^3
+        ld = (N + 63) // 64 * 64
+        X8 = torch.empty((N, ld), dtype=torch.uint8, device="cuda")
+        Y8 = torch.empty_like(X8)
+        RX = torch.empty(N, dtype=torch.int32, device="cuda")
+        RY = torch.empty_like(RX)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        tp.tp_compact_from_u16(X, X8, RX, st)
+        del X, Y
+        tp.tp_tune_compact_step(args.unroll)
+        t = _events(torch, lambda: tp.tp_compact_step(n, X8, RX, N, Y8, RY, st), args.reps)
+        out.update({"n": n, "N": N, "nnz": nnz, "unroll": args.unroll, "ms": t * 1e3,
+                    "Tminplus_ops": nnz * N / t / 1e12, "status": int(st.item())})
     elif args.op in ("spmm", "bstep", "gather", "trace", "gemm", "cdiff"):
         N = tp.tp_state_dim(n)
         X, Y = _padded(torch, N), _padded(torch, N)

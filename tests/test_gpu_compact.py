@@ -1,0 +1,259 @@
+"""Compact powers (8-bit residuals with one offset per row): the chain step,
+the conversions and the diagonal minimum against the oracle's powers, the
+16-bit chain and the closed form."""
+import numpy as np
+import pytest
+
+from closed_form import gamma2_closed_form
+
+pytestmark = pytest.mark.gpu
+
+INF = 65535
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2409_17688_amd as tp
+    return tp
+
+
+def _dev16(M):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(M, dtype=np.uint16).view(np.int16)).cuda() \
+        .view(torch.uint16)
+
+
+def _host(T):
+    return T.cpu().view(__import__("torch").int16).numpy().view(np.uint16).astype(np.int64)
+
+
+def _u8(N, ncols):
+    import torch
+    return torch.empty((N, (ncols + 63) // 64 * 64 or 64), dtype=torch.uint8, device="cuda")
+
+
+def _status():
+    import torch
+    return torch.zeros(1, dtype=torch.int32, device="cuda")
+
+
+def _padded16(N, ncols=None):
+    import torch
+    ncols = N if ncols is None else ncols
+    ld = (ncols + 63) // 64 * 64 or 64
+    return torch.empty((N, ld), dtype=torch.uint16, device="cuda")[:, :ncols]
+
+
+@pytest.mark.parametrize("n", range(2, 8))
+def test_compact_chain_matches_oracle_powers(tp, oracle_mod, n):
+    """A^k for k = 3..24 through compact steps == the oracle's A^k, and the
+    compact diagonal minimum == the oracle's (Theorem 2)."""
+    import torch
+    A = oracle_mod.state_matrix(n)
+    N = A.shape[0]
+    P = [None, A]
+    for _ in range(2, 25):
+        P.append(oracle_mod.minplus(A, P[-1]))
+    X8, Y8 = _u8(N, N), _u8(N, N)
+    RX = torch.empty(N, dtype=torch.int32, device="cuda")
+    RY = torch.empty_like(RX)
+    st = _status()
+    tp.tp_compact_from_u16(_dev16(P[3]), X8, RX, st)
+    assert int(st.item()) == 0, n
+    for k in range(3, 25):
+        got = _host(tp.tp_compact_to_u16(X8, RX, N))
+        assert (got == P[k]).all(), (n, k)
+        assert tp.tp_compact_diag_min(X8[:, :N], RX) == oracle_mod.trace_min(P[k]), (n, k)
+        tp.tp_compact_step(n, X8, RX, N, Y8, RY, st)
+        X8, Y8, RX, RY = Y8, X8, RY, RX
+    assert int(st.item()) == 0, n
+
+
+@pytest.mark.parametrize("n,ncols,unroll", [(8, 1386, 4), (8, 1386, 8), (8, 700, 4),
+                                            (8, 13, 8), (9, 3447, 4), (10, 1031, 8)])
+def test_compact_chain_matches_u16_chain(tp, n, ncols, unroll):
+    """Column panels of A^4, several 512-column panels and ragged tails:
+    six compact steps == six 16-bit steps, element for element."""
+    import torch
+    N = tp.tp_state_dim(n)
+    A = _padded16(N)
+    tp.tp_build_state_matrix(n, tp.TP_U16, out=A)
+    X, Y = _padded16(N, ncols), _padded16(N, ncols)
+    tp.tp_state_left_mul(n, A[:, :ncols].contiguous(), Y)  # A^2 on the columns
+    tp.tp_state_left_mul(n, Y, X)
+    tp.tp_state_left_mul(n, X, Y)
+    X.copy_(Y)  # A^4 on the columns
+    X8, Y8 = _u8(N, ncols), _u8(N, ncols)
+    RX = torch.empty(N, dtype=torch.int32, device="cuda")
+    RY = torch.empty_like(RX)
+    st = _status()
+    tp.tp_compact_from_u16(X, X8, RX, st)
+    assert int(st.item()) == 0
+    tp.tp_tune_compact_step(unroll)
+    try:
+        for k in range(6):
+            tp.tp_state_left_mul(n, X, Y)
+            X, Y = Y, X
+            tp.tp_compact_step(n, X8, RX, ncols, Y8, RY, st)
+            X8, Y8, RX, RY = Y8, X8, RY, RX
+            assert torch.equal(tp.tp_compact_to_u16(X8, RX, ncols), X), (n, ncols, k)
+    finally:
+        tp.tp_tune_compact_step(4)
+    assert int(st.item()) == 0
+
+
+def test_compact_diag_min_gives_closed_form(tp):
+    """gamma2(P_10 x C_m) for m = 3..40 as compact diagonal minima."""
+    import torch
+    n = 10
+    N = tp.tp_state_dim(n)
+    A, B = _padded16(N), _padded16(N)
+    tp.tp_build_state_matrix(n, tp.TP_U16, out=A)
+    tp.tp_state_left_mul(n, A, B)
+    tp.tp_state_left_mul(n, B, A)  # A^3
+    X8, Y8 = _u8(N, N), _u8(N, N)
+    RX = torch.empty(N, dtype=torch.int32, device="cuda")
+    RY = torch.empty_like(RX)
+    st = _status()
+    tp.tp_compact_from_u16(A, X8, RX, st)
+    for m in range(3, 41):
+        assert tp.tp_compact_diag_min(X8[:, :N], RX) == gamma2_closed_form(n, m), m
+        tp.tp_compact_step(n, X8, RX, N, Y8, RY, st)
+        X8, Y8, RX, RY = Y8, X8, RY, RX
+    assert int(st.item()) == 0
+
+
+def test_compact_full_size_n12(tp):
+    """n = 12 (N = 52,929), the size the step is measured at: two compact
+    steps from A^3 == two 16-bit steps, every element."""
+    import torch
+    n = 12
+    N = tp.tp_state_dim(n)
+    X, Y = _padded16(N), _padded16(N)
+    tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
+    tp.tp_state_left_mul(n, X, Y)
+    tp.tp_state_left_mul(n, Y, X)  # A^3
+    X8, Y8 = _u8(N, N), _u8(N, N)
+    RX = torch.empty(N, dtype=torch.int32, device="cuda")
+    RY = torch.empty_like(RX)
+    st = _status()
+    tp.tp_compact_from_u16(X, X8, RX, st)
+    assert int(st.item()) == 0
+    for k in (4, 5):
+        tp.tp_state_left_mul(n, X, Y)
+        X, Y = Y, X
+        tp.tp_compact_step(n, X8, RX, N, Y8, RY, st)
+        X8, Y8, RX, RY = Y8, X8, RY, RX
+        assert torch.equal(tp.tp_compact_to_u16(X8, RX, N), X), k
+        assert tp.tp_compact_diag_min(X8[:, :N], RX) == tp.tp_trace_min(X), k
+    assert int(st.item()) == 0
+
+
+def test_compact_n13_column_panel(tp):
+    """n = 13 (N = 131,562, successors past 2^16): a 1,000-column panel of
+    A^3, three compact steps == three 16-bit steps."""
+    import torch
+    n, ncols = 13, 1000
+    N = tp.tp_state_dim(n)
+    idx = torch.arange(ncols, dtype=torch.int32, device="cuda") * 131
+    X = tp.tp_build_state_columns(n, idx)
+    Y = torch.empty_like(X)
+    # A^3 columns: A x (A x columns of A)
+    _left13(tp, n, X, Y)
+    _left13(tp, n, Y, X)
+    X8, Y8 = _u8(N, ncols), _u8(N, ncols)
+    RX = torch.empty(N, dtype=torch.int32, device="cuda")
+    RY = torch.empty_like(RX)
+    st = _status()
+    tp.tp_compact_from_u16(X, X8, RX, st)
+    assert int(st.item()) == 0
+    for k in range(3):
+        _left13(tp, n, X, Y)
+        X, Y = Y, X
+        tp.tp_compact_step(n, X8, RX, ncols, Y8, RY, st)
+        X8, Y8, RX, RY = Y8, X8, RY, RX
+        assert torch.equal(tp.tp_compact_to_u16(X8, RX, ncols), X), k
+    assert int(st.item()) == 0
+
+
+def _left13(tp, n, X, Y):
+    """Y = A(D_n) x X in 16 bits by the CSR product (tp_state_left_mul
+    takes n <= 12)."""
+    rowptr, col, z = tp.tp_build_state_csr(n)
+    tp.tp_minplus_spmm(rowptr, col, z, X, Y)
+
+
+def test_compact_conversion_reports_what_it_cannot_hold(tp, oracle_mod):
+    import torch
+    # A itself: rows with finite and INF entries
+    A = oracle_mod.state_matrix(5)
+    N = A.shape[0]
+    st = _status()
+    tp.tp_compact_from_u16(_dev16(A), _u8(N, N), torch.empty(N, dtype=torch.int32,
+                                                              device="cuda"), st)
+    assert int(st.item()) & tp.COMPACT_MIXED
+    # a row spanning 300
+    M = np.zeros((4, 40), dtype=np.int64)
+    M[2, 7] = 300
+    st = _status()
+    tp.tp_compact_from_u16(_dev16(M), _u8(4, 40), torch.empty(4, dtype=torch.int32,
+                                                               device="cuda"), st)
+    assert int(st.item()) == tp.COMPACT_RANGE
+    # spans of exactly 254 and rows of INF only are held and come back unchanged
+    M = np.full((5, 77), 1000, dtype=np.int64)
+    M[0, 3] = 1254
+    M[1, :] = INF
+    M[3, :] = np.arange(77) + 60000
+    st = _status()
+    X8 = _u8(5, 77)
+    R = torch.empty(5, dtype=torch.int32, device="cuda")
+    tp.tp_compact_from_u16(_dev16(M), X8, R, st)
+    assert int(st.item()) == 0
+    assert int(R[1].item()) == tp.COMPACT_DEAD
+    assert (_host(tp.tp_compact_to_u16(X8, R, 77)) == M).all()
+
+
+def test_compact_step_with_dead_rows(tp):
+    """Rows of INF only in the input (dead successors) give the 16-bit step's
+    result."""
+    import torch
+    n = 7
+    N = tp.tp_state_dim(n)
+    A, B = _padded16(N), _padded16(N)
+    tp.tp_build_state_matrix(n, tp.TP_U16, out=A)
+    tp.tp_state_left_mul(n, A, B)
+    tp.tp_state_left_mul(n, B, A)  # A^3
+    rng = np.random.default_rng(7)
+    dead = torch.from_numpy(rng.random(N) < 0.3).cuda()
+    A.view(torch.int16)[dead] = -1  # INF
+    X8, Y8 = _u8(N, N), _u8(N, N)
+    RX = torch.empty(N, dtype=torch.int32, device="cuda")
+    RY = torch.empty_like(RX)
+    st = _status()
+    tp.tp_compact_from_u16(A, X8, RX, st)
+    assert int(st.item()) == 0
+    tp.tp_state_left_mul(n, A, B)
+    tp.tp_compact_step(n, X8, RX, N, Y8, RY, st)
+    assert torch.equal(tp.tp_compact_to_u16(Y8, RY, N), B)
+    assert int(st.item()) == 0
+
+
+def test_compact_argument_checks(tp):
+    import torch
+    n = 4
+    N = tp.tp_state_dim(n)
+    X8, Y8 = _u8(N, N), _u8(N, N)
+    R = torch.zeros(N, dtype=torch.int32, device="cuda")
+    R2 = torch.zeros(N, dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_step(n, X8, R, N, X8, R2)  # in place
+    odd = torch.empty((N, 60), dtype=torch.uint8, device="cuda")[:, :N]
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_step(n, odd, R, N, Y8, R2)  # ld not a multiple of 8
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_step(14, X8, R, N, Y8, R2)
+    tp.tp_compact_step(n, X8, R, 0, Y8, R2)  # no columns: nothing to do
+    with pytest.raises(RuntimeError):
+        tp.tp_tune_compact_step(5)
