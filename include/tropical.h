@@ -238,8 +238,39 @@ int tp_compact_step(int n, const void *d_X, int64_t ldx, const int32_t *d_RX, vo
 int tp_compact_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *d_R,
                         int32_t *d_out, hipStream_t stream);
 
-/* Gathers per round in tp_compact_step (4, the default, or 8).  Changes
- * speed only. */
+/* Shared-base compact powers: one base G per power, P[q][c] = G + x[q][c]
+ * with x in 0..254 and every entry finite; d_base is a device int32[2]
+ * holding G and the least residual held.  A whole power of A(D_n) spans a
+ * few units more than one of its rows, so it fits too, and the step adds
+ * only the arc label per gathered row (no per-row offset).  Status bits as
+ * above. */
+
+/* d_Y (u8 residuals) and d_base from the 16-bit d_X: G = least entry;
+ * an INF entry sets status bit 2, a residual above 254 bit 1. */
+int tp_compact_shared_from_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx,
+                               void *d_Y, int64_t ldy, int32_t *d_base, int32_t *d_status,
+                               hipStream_t stream);
+
+/* d_Y (u16) = min(G + x, INF = 65535). */
+int tp_compact_shared_to_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx,
+                             const int32_t *d_base, void *d_Y, int64_t ldy, hipStream_t stream);
+
+/* (d_Y, d_by) = A(D_n) x (d_X, d_bx), Algorithm 2's left step: the output is
+ * held over G_Y = G_X + (least residual of X), which no entry of the output
+ * is below (labels are non-negative), so its residuals are its span plus the
+ * growth of its least entry; one above 254 sets status bit 1.  Layout
+ * requirements as tp_compact_step; d_bx and d_by distinct. */
+int tp_compact_shared_step(int n, const void *d_X, int64_t ldx, const int32_t *d_bx, void *d_Y,
+                           int64_t ldy, int32_t *d_by, int64_t ncols, int32_t *d_status,
+                           hipStream_t stream);
+
+/* *d_out = min(min over q of G + x[q][q], 65535): Theorem 2's diagonal
+ * minimum of a square shared-base power. */
+int tp_compact_shared_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *d_base,
+                               int32_t *d_out, hipStream_t stream);
+
+/* Gathers per round in tp_compact_step and tp_compact_shared_step (4, the
+ * default, or 8).  Changes speed only. */
 int tp_tune_compact_step(int unroll);
 
 /* All-pairs shortest paths by (min,+) squaring, the same semiring (Section 1)

@@ -97,6 +97,10 @@ _SIGS = {
     "tp_compact_step": ([_i, _p, _i64, _p, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_compact_diag_min": ([_i64, _p, _i64, _p, _p, _p], _i),
     "tp_tune_compact_step": ([_i], _i),
+    "tp_compact_shared_from_u16": ([_i64, _i64, _p, _i64, _p, _i64, _p, _p, _p], _i),
+    "tp_compact_shared_to_u16": ([_i64, _i64, _p, _i64, _p, _p, _i64, _p], _i),
+    "tp_compact_shared_step": ([_i, _p, _i64, _p, _p, _i64, _p, _i64, _p, _p], _i),
+    "tp_compact_shared_diag_min": ([_i64, _p, _i64, _p, _p, _p], _i),
     "tp_const_diff": ([_i64, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_recurrence": ([_i, _i, _i, ctypes.POINTER(Recurrence), ctypes.POINTER(ctypes.c_int32),
                        _p], _i),
@@ -586,6 +590,75 @@ def tp_compact_diag_min(X: torch.Tensor, R: torch.Tensor, stream=None) -> int:
     out = torch.empty(1, dtype=torch.int32, device=X.device)
     _check(lib.tp_compact_diag_min(N, px, ldx, ctypes.c_void_p(R.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return int(out.item())
+
+
+def _base(t, name):
+    if t.dtype != torch.int32 or t.numel() < 2 or not t.is_cuda:
+        raise ValueError(f"{name} must be an int32 CUDA tensor of two elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def tp_compact_shared_from_u16(X: torch.Tensor, Y: torch.Tensor | None = None,
+                               base: torch.Tensor | None = None,
+                               status: torch.Tensor | None = None, stream=None):
+    """(Y, base): the shared-base compact form of the 16-bit matrix X
+    (base = [G, least residual])."""
+    if X.dtype != torch.uint16:
+        raise ValueError("X must be uint16")
+    px, N, ncols, ldx = _mat(X, "X")
+    if Y is None:
+        Y = torch.empty((N, (ncols + 7) // 8 * 8 or 8), dtype=torch.uint8, device=X.device)
+    if base is None:
+        base = torch.empty(2, dtype=torch.int32, device=X.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+    py, Ny, ldy = _u8rows(Y, "Y", ncols)
+    if Ny != N:
+        raise ValueError("Y must have N rows")
+    _check(lib.tp_compact_shared_from_u16(N, ncols, px, ldx, py, ldy, _base(base, "base"),
+                                          ctypes.c_void_p(status.data_ptr()), _stream(stream)))
+    return Y, base
+
+
+def tp_compact_shared_to_u16(X: torch.Tensor, base: torch.Tensor, ncols: int,
+                             Y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    px, N, ldx = _u8rows(X, "X", ncols)
+    if Y is None:
+        Y = torch.empty((N, ncols), dtype=torch.uint16, device=X.device)
+    py, Ny, nc, ldy = _mat(Y, "Y")
+    if Ny != N or nc != ncols:
+        raise ValueError("Y must be N x ncols")
+    _check(lib.tp_compact_shared_to_u16(N, ncols, px, ldx, _base(base, "base"), py, ldy,
+                                        _stream(stream)))
+    return Y
+
+
+def tp_compact_shared_step(n: int, X: torch.Tensor, bx: torch.Tensor, ncols: int,
+                           Y: torch.Tensor | None = None, by: torch.Tensor | None = None,
+                           status: torch.Tensor | None = None, stream=None):
+    """(Y, by) = A(D_n) x (X, bx) in shared-base compact form."""
+    px, N, ldx = _u8rows(X, "X", ncols)
+    if Y is None:
+        Y = torch.empty_like(X)
+    if by is None:
+        by = torch.empty_like(bx)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+    py, Ny, ldy = _u8rows(Y, "Y", ncols)
+    if Ny != N:
+        raise ValueError("Y must have N rows")
+    _check(lib.tp_compact_shared_step(int(n), px, ldx, _base(bx, "bx"), py, ldy, _base(by, "by"),
+                                      int(ncols), ctypes.c_void_p(status.data_ptr()),
+                                      _stream(stream)))
+    return Y, by
+
+
+def tp_compact_shared_diag_min(X: torch.Tensor, base: torch.Tensor, stream=None) -> int:
+    px, N, ldx = _u8rows(X, "X", X.shape[0])
+    out = torch.empty(1, dtype=torch.int32, device=X.device)
+    _check(lib.tp_compact_shared_diag_min(N, px, ldx, _base(base, "base"),
+                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return int(out.item())
 
 

@@ -296,6 +296,205 @@ __global__ void __launch_bounds__(256) compact_diag_kernel(int64_t N, const uint
   }
 }
 
+// ---------------------------------------------------------------------------
+// Shared-base form: one base G per power, P[q][c] = G + x[q][c], x in 0..254,
+// every entry finite.  A whole power of A(D_n) spans a few units more than a
+// row does, so it fits as well, and the step needs no per-entry offset: the
+// label added per block entry is z_p as in the 16-bit step.  base[0] = G and
+// base[1] = the least residual held.  The step writes its output relative to
+// G_Y = G_X + base_X[1] (the least entry of the input: no entry of the output
+// is below it, labels being non-negative), so output residuals are
+// P_Y - min P_X: the span of the output plus the growth of its least entry.
+
+// base_Y = {G_X + m_X, INT_MAX}; the step folds its least residual into [1].
+__global__ void shared_prepare_kernel(const int32_t *bx, int32_t *by) {
+  if (threadIdx.x == 0) {
+    by[0] = bx[0] + bx[1];
+    by[1] = 0x7FFFFFFF;
+  }
+}
+
+template <int U>
+__global__ void __launch_bounds__(256) shared_step_kernel(
+    int64_t N, const int64_t *__restrict__ bptr, const uint64_t *__restrict__ ent,
+    const int32_t *__restrict__ border, const uint8_t *__restrict__ X, int64_t ldx,
+    const int32_t *__restrict__ bx, uint8_t *__restrict__ Y, int64_t ldy, int32_t *__restrict__ by,
+    int64_t ncols, int32_t *__restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t groups = (nblocks + 3) / 4;
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t panel = t / groups;
+  const int64_t bslot = (t - panel * groups) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (bslot >= nblocks) return;
+  const int64_t b = border ? (int64_t)((kconst_i32)border)[bslot] : bslot;
+  const int64_t c0 = (panel * 64 + lane) * 8;
+  const kconst_i64 bp = (kconst_i64)bptr;
+  const kconst_u64 en = (kconst_u64)ent;
+  const gconst<u32x2> Xg = (gconst<u32x2>)to_global(X);
+  const int64_t ld8 = ldx / 8;
+  const uint32_t off = c0 < ncols ? (uint32_t)(c0 / 8) : 0u;
+
+  u16x2 acc[kRows][4];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[r][k] = splat(0xFFFFu);
+
+  const int64_t e0 = bp[b], e1 = bp[b + 1];
+  if (e0 < e1) {
+    const int64_t last = e1 - 1;
+    auto fetch = [&](int64_t i, uint64_t (&w)[U], u32x2 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = i + u;
+        const uint64_t x = en[k < last ? k : last];
+        w[u] = k <= last ? x : (x & 0xFFFFFFFFull);  // past the end: no rows
+        v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ld8 + off];
+      }
+    };
+    auto apply = [&](const uint64_t (&w)[U], const u32x2 (&v)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        u16x2 row[4];
+        unpack8(v[u].x, row[0], row[1]);
+        unpack8(v[u].y, row[2], row[3]);
+        apply_entry(acc, (uint32_t)(w[u] >> 32), splat((uint16_t)((w[u] >> 24) & 0xFFu)), row);
+      }
+    };
+    uint64_t wa[U], wb[U];
+    u32x2 va[U], vb[U];
+    fetch(e0, wa, va);
+    for (int64_t i = e0;;) {
+      bool more = i + U <= last;
+      if (more) fetch(i + U, wb, vb);
+      apply(wa, va);
+      i += U;
+      if (!more) break;
+      more = i + U <= last;
+      if (more) fetch(i + U, wa, va);
+      apply(wb, vb);
+      i += U;
+      if (!more) break;
+    }
+  }
+  const u16x2 d = splat((uint16_t)min(((kconst_i32)bx)[1], 0xFFFF));
+  uint32_t bad = 0, low = 0xFFFFu;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t q = b * kRows + r;
+    if (q >= N || c0 >= ncols) break;
+    u16x2 y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) y[k] = __builtin_elementwise_sub_sat(acc[r][k], d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (c0 + 2 * k < ncols) {
+        bad |= (y[k].x > 254);
+        low = min(low, (uint32_t)y[k].x);
+      }
+      if (c0 + 2 * k + 1 < ncols) {
+        bad |= (y[k].y > 254);
+        low = min(low, (uint32_t)y[k].y);
+      }
+    }
+    const uint32_t lo = __builtin_amdgcn_perm(as_u32(y[1]), as_u32(y[0]), 0x06040200u);
+    const uint32_t hi = __builtin_amdgcn_perm(as_u32(y[3]), as_u32(y[2]), 0x06040200u);
+    if (c0 + 8 <= ncols) {
+      *(gmut<u32x2>)(to_global_mut(Y) + q * ldy + c0) = u32x2{lo, hi};
+    } else {
+      const gmut<uint8_t> yp = to_global_mut(Y) + q * ldy + c0;
+      for (int k = 0; k < 8 && c0 + k < ncols; ++k)
+        yp[k] = (uint8_t)(((k < 4 ? lo : hi) >> (8 * (k & 3))) & 0xFFu);
+    }
+  }
+  if (bad) atomicOr(status, kStatusRange);
+  // one atomic per wave, and only when it lowers what is there (a stale read
+  // can only add an atomic, never skip a needed one)
+  const int32_t wlow = wave_min_i32((int32_t)low);
+  if (lane == 0 && wlow < *(volatile int32_t *)(by + 1)) atomicMin(by + 1, wlow);
+}
+
+// base[0] = min(base[0], least entry); entries of INF are reported.
+__global__ void __launch_bounds__(256) shared_min_kernel(int64_t ncols, const uint16_t *X,
+                                                         int64_t ldx, int32_t *base,
+                                                         int32_t *status) {
+  __shared__ int32_t red[2][4];
+  const int64_t q = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const gconst<uint16_t> x = to_global(X) + q * ldx;
+  int32_t mn = 0xFFFF, inf = 0;
+  for (int64_t c = threadIdx.x; c < ncols; c += 256) {
+    const int32_t v = x[c];
+    mn = min(mn, v);
+    inf |= (v == 0xFFFF);
+  }
+  mn = wave_min_i32(mn);
+  inf = wave_max_i32(inf);
+  if (lane == 0) {
+    red[0][wv] = mn;
+    red[1][wv] = inf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mn = min(min(red[0][0], red[0][1]), min(red[0][2], red[0][3]));
+    inf = max(max(red[1][0], red[1][1]), max(red[1][2], red[1][3]));
+    atomicMin(base, mn);
+    if (inf) atomicOr(status, kStatusMixed);
+  }
+}
+
+// x = entry - base[0]; residuals above 254 are reported.
+__global__ void __launch_bounds__(256) shared_residual_kernel(int64_t ncols, const uint16_t *X,
+                                                              int64_t ldx, const int32_t *base,
+                                                              uint8_t *Y, int64_t ldy,
+                                                              int32_t *status) {
+  const int64_t q = blockIdx.x;
+  const int32_t g = base[0];
+  const gconst<uint16_t> x = to_global(X) + q * ldx;
+  const gmut<uint8_t> y = to_global_mut(Y) + q * ldy;
+  int32_t bad = 0;
+  for (int64_t c = threadIdx.x; c < ncols; c += 256) {
+    const int32_t v = x[c] - g;
+    bad |= (v > 254);
+    y[c] = (uint8_t)min(v, 255);
+  }
+  if (bad) atomicOr(status, kStatusRange);
+}
+
+__global__ void __launch_bounds__(256) shared_to_u16_kernel(int64_t ncols, const uint8_t *X,
+                                                            int64_t ldx, const int32_t *base,
+                                                            uint16_t *Y, int64_t ldy) {
+  const int64_t q = blockIdx.x;
+  const int32_t g = base[0];
+  const gconst<uint8_t> x = to_global(X) + q * ldx;
+  const gmut<uint16_t> y = to_global_mut(Y) + q * ldy;
+  for (int64_t c = (int64_t)blockIdx.y * 256 + threadIdx.x; c < ncols;
+       c += (int64_t)gridDim.y * 256) {
+    const int32_t v = x[c];
+    y[c] = v == 0xFF ? (uint16_t)0xFFFFu : (uint16_t)min(g + v, 0xFFFF);
+  }
+}
+
+__global__ void __launch_bounds__(256) shared_diag_kernel(int64_t N, const uint8_t *X,
+                                                          int64_t ldx, const int32_t *base,
+                                                          int32_t *out) {
+  __shared__ int32_t red[4];
+  const int32_t g = base[0];
+  int32_t m = 0xFFFF;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < N; q += (int64_t)gridDim.x * 256) {
+    const int32_t v = X[q * ldx + q];
+    if (v != 0xFF) m = min(m, min(g + v, 0xFFFF));
+  }
+  m = wave_min_i32(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = min(min(red[0], red[1]), min(red[2], red[3]));
+    if (m < 0xFFFF) atomicMin(out, m);
+  }
+}
+
 bool chunk_ok(const void *p, int64_t ld, int64_t ncols) {
   return ((uintptr_t)p % 8 == 0) && (ld % 8 == 0) && ld >= (ncols + 7) / 8 * 8;
 }
@@ -377,6 +576,86 @@ int tp_compact_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *
   const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
   hipLaunchKernelGGL(compact_diag_kernel, dim3(blocks), dim3(256), 0, stream, N,
                      (const uint8_t *)d_X, ldx, d_R, d_out);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_shared_from_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx,
+                               void *d_Y, int64_t ldy, int32_t *d_base, int32_t *d_status,
+                               hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && ncols >= 0 && N < ((int64_t)1 << 31), "bad size");
+  TP_REQUIRE(d_base && d_status, "NULL pointer");
+  TP_HIP_CHECK(launch_fill_i32(d_base, 1, 0xFFFF, stream));
+  TP_HIP_CHECK(launch_fill_i32(d_base + 1, 1, 0, stream));
+  if (N == 0 || ncols == 0) return TP_OK;
+  TP_REQUIRE(ldx >= ncols && ldy >= ncols, "leading dimension < ncols");
+  TP_REQUIRE(d_X && d_Y, "NULL pointer");
+  hipLaunchKernelGGL(shared_min_kernel, dim3((unsigned)N), dim3(256), 0, stream, ncols,
+                     (const uint16_t *)d_X, ldx, d_base, d_status);
+  TP_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(shared_residual_kernel, dim3((unsigned)N), dim3(256), 0, stream, ncols,
+                     (const uint16_t *)d_X, ldx, (const int32_t *)d_base, (uint8_t *)d_Y, ldy,
+                     d_status);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_shared_to_u16(int64_t N, int64_t ncols, const void *d_X, int64_t ldx,
+                             const int32_t *d_base, void *d_Y, int64_t ldy, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && ncols >= 0 && N < ((int64_t)1 << 31), "bad size");
+  if (N == 0 || ncols == 0) return TP_OK;
+  TP_REQUIRE(ldx >= ncols && ldy >= ncols, "leading dimension < ncols");
+  TP_REQUIRE(d_X && d_Y && d_base, "NULL pointer");
+  const dim3 grid((unsigned)N, (unsigned)std::min<int64_t>((ncols + 255) / 256, 64));
+  hipLaunchKernelGGL(shared_to_u16_kernel, grid, dim3(256), 0, stream, ncols,
+                     (const uint8_t *)d_X, ldx, d_base, (uint16_t *)d_Y, ldy);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_shared_step(int n, const void *d_X, int64_t ldx, const int32_t *d_bx, void *d_Y,
+                           int64_t ldy, int32_t *d_by, int64_t ncols, int32_t *d_status,
+                           hipStream_t stream) {
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
+  TP_REQUIRE(ncols >= 0, "negative size");
+  TP_REQUIRE(d_bx && d_by && d_bx != d_by, "base words NULL or shared");
+  if (ncols == 0) return TP_OK;
+  TP_REQUIRE(d_X && d_Y && d_status, "NULL pointer");
+  TP_REQUIRE(d_X != d_Y, "the step cannot run in place");
+  TP_REQUIRE(chunk_ok(d_X, ldx, ncols) && chunk_ok(d_Y, ldy, ncols),
+             "X and Y need 8-byte aligned rows with ld a multiple of 8, at least ncols "
+             "rounded up to 8");
+  StateView v;
+  const int rc = state_view(n, stream, &v);
+  if (rc != TP_OK) return rc;
+  const int64_t N = v.N;
+  hipLaunchKernelGGL(shared_prepare_kernel, dim3(1), dim3(64), 0, stream, d_bx, d_by);
+  TP_HIP_CHECK(hipGetLastError());
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t panels = (ncols + 511) / 512;
+  const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
+  if (g_unroll == 8)
+    hipLaunchKernelGGL((shared_step_kernel<8>), grid, dim3(256), 0, stream, N, v.bptr, v.bent,
+                       v.border, (const uint8_t *)d_X, ldx, d_bx, (uint8_t *)d_Y, ldy, d_by,
+                       ncols, d_status);
+  else
+    hipLaunchKernelGGL((shared_step_kernel<4>), grid, dim3(256), 0, stream, N, v.bptr, v.bent,
+                       v.border, (const uint8_t *)d_X, ldx, d_bx, (uint8_t *)d_Y, ldy, d_by,
+                       ncols, d_status);
+  TP_HIP_CHECK(hipGetLastError());
+  return TP_OK;
+}
+
+int tp_compact_shared_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *d_base,
+                               int32_t *d_out, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && N < ((int64_t)1 << 31), "bad size");
+  TP_REQUIRE(d_out != nullptr, "out is NULL");
+  TP_HIP_CHECK(launch_fill_i32(d_out, 1, 0xFFFF, stream));
+  if (N == 0) return TP_OK;
+  TP_REQUIRE(ldx >= N && d_X && d_base, "bad X or base");
+  const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+  hipLaunchKernelGGL(shared_diag_kernel, dim3(blocks), dim3(256), 0, stream, N,
+                     (const uint8_t *)d_X, ldx, d_base, d_out);
   TP_HIP_CHECK(hipGetLastError());
   return TP_OK;
 }

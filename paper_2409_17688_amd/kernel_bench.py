@@ -25,7 +25,8 @@ the algorithmic work of one launch:
   recurrence  tp_recurrence(n, K, window): K powers, each compared with the
          window before it, then Algorithms 3 and 4 (wall time)
   cstep  the same product on compact powers (tp_compact_step: 8-bit residuals,
-         one offset per row), from A^3; the offsets' product is included
+         one offset per row; --shared: tp_compact_shared_step, one base per
+         power), from A^3; the offsets' product is included
   apsp   all-pairs shortest paths on a random digraph of order N (weights
          0..49 on 1 % of the pairs, default_rng(0)): ceil(log2(N-1)) dense
          products of N^3 operations
@@ -70,6 +71,7 @@ def main(argv=None):
     ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
     ap.add_argument("--N", type=int, default=8192, help="apsp: order of the digraph")
     ap.add_argument("--unroll", type=int, default=4, help="cstep: gathers per round (4 or 8)")
+    ap.add_argument("--shared", action="store_true", help="cstep: one base per power")
     args = ap.parse_args(argv)
 
     import torch
@@ -110,15 +112,28 @@ def main(argv=None):
         ld = (N + 63) // 64 * 64
         X8 = torch.empty((N, ld), dtype=torch.uint8, device="cuda")
         Y8 = torch.empty_like(X8)
-        RX = torch.empty(N, dtype=torch.int32, device="cuda")
-        RY = torch.empty_like(RX)
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
-        tp.tp_compact_from_u16(X, X8, RX, st)
-        del X, Y
         tp.tp_tune_compact_step(args.unroll)
-        t = _events(torch, lambda: tp.tp_compact_step(n, X8, RX, N, Y8, RY, st), args.reps)
-        out.update({"n": n, "N": N, "nnz": nnz, "unroll": args.unroll, "ms": t * 1e3,
-                    "Tminplus_ops": nnz * N / t / 1e12, "status": int(st.item())})
+        if args.shared:
+            bx = torch.empty(2, dtype=torch.int32, device="cuda")
+            by = torch.empty_like(bx)
+            tp.tp_compact_shared_from_u16(X, X8, bx, st)
+            del X, Y
+            bufs = [(X8, bx), (Y8, by)]
+
+            def step():  # alternate the buffers: each step starts from the last output
+                (a, ba), (c, bc) = bufs
+                tp.tp_compact_shared_step(n, a, ba, N, c, bc, st)
+                bufs.reverse()
+            t = _events(torch, step, args.reps)
+        else:
+            RX = torch.empty(N, dtype=torch.int32, device="cuda")
+            RY = torch.empty_like(RX)
+            tp.tp_compact_from_u16(X, X8, RX, st)
+            del X, Y
+            t = _events(torch, lambda: tp.tp_compact_step(n, X8, RX, N, Y8, RY, st), args.reps)
+        out.update({"n": n, "N": N, "nnz": nnz, "unroll": args.unroll, "shared": args.shared,
+                    "ms": t * 1e3, "Tminplus_ops": nnz * N / t / 1e12, "status": int(st.item())})
     elif args.op in ("spmm", "bstep", "gather", "trace", "gemm", "cdiff"):
         N = tp.tp_state_dim(n)
         X, Y = _padded(torch, N), _padded(torch, N)

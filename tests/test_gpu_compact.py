@@ -257,3 +257,98 @@ def test_compact_argument_checks(tp):
     tp.tp_compact_step(n, X8, R, 0, Y8, R2)  # no columns: nothing to do
     with pytest.raises(RuntimeError):
         tp.tp_tune_compact_step(5)
+
+
+# ------------------------------------------------------ shared-base form --
+
+def _base2():
+    import torch
+    return torch.empty(2, dtype=torch.int32, device="cuda")
+
+
+@pytest.mark.parametrize("n", range(2, 8))
+def test_shared_chain_matches_oracle_powers(tp, oracle_mod, n):
+    """A^k, k = 3..40, through shared-base steps == the oracle's A^k, with
+    the diagonal minima."""
+    A = oracle_mod.state_matrix(n)
+    N = A.shape[0]
+    P = [None, A]
+    for _ in range(2, 41):
+        P.append(oracle_mod.minplus(A, P[-1]))
+    X8, Y8, bx, by, st = _u8(N, N), _u8(N, N), _base2(), _base2(), _status()
+    tp.tp_compact_shared_from_u16(_dev16(P[3]), X8, bx, st)
+    assert int(st.item()) == 0, n
+    for k in range(3, 41):
+        assert (_host(tp.tp_compact_shared_to_u16(X8, bx, N)) == P[k]).all(), (n, k)
+        assert tp.tp_compact_shared_diag_min(X8[:, :N], bx) == oracle_mod.trace_min(P[k]), (n, k)
+        tp.tp_compact_shared_step(n, X8, bx, N, Y8, by, st)
+        X8, Y8, bx, by = Y8, X8, by, bx
+    assert int(st.item()) == 0, n
+
+
+@pytest.mark.parametrize("n,ncols,unroll", [(8, 1386, 4), (8, 700, 8), (8, 13, 4),
+                                            (9, 3447, 8), (11, 2100, 4)])
+def test_shared_chain_matches_u16_chain(tp, n, ncols, unroll):
+    import torch
+    N = tp.tp_state_dim(n)
+    A = _padded16(N)
+    tp.tp_build_state_matrix(n, tp.TP_U16, out=A)
+    X, Y = _padded16(N, ncols), _padded16(N, ncols)
+    tp.tp_state_left_mul(n, A[:, :ncols].contiguous(), Y)
+    tp.tp_state_left_mul(n, Y, X)  # A^3 on the columns
+    X8, Y8, bx, by, st = _u8(N, ncols), _u8(N, ncols), _base2(), _base2(), _status()
+    tp.tp_compact_shared_from_u16(X, X8, bx, st)
+    assert int(st.item()) == 0
+    tp.tp_tune_compact_step(unroll)
+    try:
+        for k in range(8):
+            tp.tp_state_left_mul(n, X, Y)
+            X, Y = Y, X
+            tp.tp_compact_shared_step(n, X8, bx, ncols, Y8, by, st)
+            X8, Y8, bx, by = Y8, X8, by, bx
+            assert torch.equal(tp.tp_compact_shared_to_u16(X8, bx, ncols), X), (n, ncols, k)
+    finally:
+        tp.tp_tune_compact_step(4)
+    assert int(st.item()) == 0
+
+
+def test_shared_full_size_n12_and_closed_form(tp):
+    """n = 12 at full size: three shared-base steps from A^3 == the 16-bit
+    steps, and the diagonal minima == the closed form."""
+    import torch
+    n = 12
+    N = tp.tp_state_dim(n)
+    X, Y = _padded16(N), _padded16(N)
+    tp.tp_build_state_matrix(n, tp.TP_U16, out=X)
+    tp.tp_state_left_mul(n, X, Y)
+    tp.tp_state_left_mul(n, Y, X)  # A^3
+    X8, Y8, bx, by, st = _u8(N, N), _u8(N, N), _base2(), _base2(), _status()
+    tp.tp_compact_shared_from_u16(X, X8, bx, st)
+    assert int(st.item()) == 0
+    for m in (4, 5, 6):
+        tp.tp_state_left_mul(n, X, Y)
+        X, Y = Y, X
+        tp.tp_compact_shared_step(n, X8, bx, N, Y8, by, st)
+        X8, Y8, bx, by = Y8, X8, by, bx
+        assert torch.equal(tp.tp_compact_shared_to_u16(X8, bx, N), X), m
+        assert tp.tp_compact_shared_diag_min(X8[:, :N], bx) == gamma2_closed_form(n, m), m
+    assert int(st.item()) == 0
+
+
+def test_shared_conversion_reports(tp, oracle_mod):
+    A = oracle_mod.state_matrix(5)
+    N = A.shape[0]
+    st = _status()
+    tp.tp_compact_shared_from_u16(_dev16(A), _u8(N, N), _base2(), st)
+    assert int(st.item()) & tp.COMPACT_MIXED
+    M = np.full((6, 50), 500, dtype=np.int64)
+    M[4, 9] = 755
+    st = _status()
+    tp.tp_compact_shared_from_u16(_dev16(M), _u8(6, 50), _base2(), st)
+    assert int(st.item()) == tp.COMPACT_RANGE
+    M[4, 9] = 754
+    st, X8, b = _status(), _u8(6, 50), _base2()
+    tp.tp_compact_shared_from_u16(_dev16(M), X8, b, st)
+    assert int(st.item()) == 0
+    assert b.tolist() == [500, 0]
+    assert (_host(tp.tp_compact_shared_to_u16(X8, b, 50)) == M).all()
