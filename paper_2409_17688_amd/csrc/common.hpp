@@ -122,6 +122,17 @@ int state_view(int n, hipStream_t s, StateView *out);
 hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, uint16_t *Y,
                            int64_t ldy, int64_t ncols, hipStream_t s);
 
+// compact.hip: shared-base compact powers (u8 residuals, base[0] = G,
+// base[1] = least residual; status bits 1 = range, 2 = INF present)
+hipError_t launch_shared_from_u16(int64_t N, int64_t ncols, const uint16_t *X, int64_t ldx,
+                                  uint8_t *Y, int64_t ldy, int32_t *base, int32_t *status,
+                                  hipStream_t s);
+hipError_t launch_shared_step(const StateView &v, const uint8_t *X, int64_t ldx, const int32_t *bx,
+                              uint8_t *Y, int64_t ldy, int32_t *by, int64_t ncols,
+                              int32_t *status, hipStream_t s);
+hipError_t launch_shared_diag(int64_t N, const uint8_t *X, int64_t ldx, const int32_t *base,
+                              int32_t *out, hipStream_t s);
+
 // state.hip
 int64_t word_count_host(int n);
 hipError_t launch_words(int n, uint32_t *codes, uint8_t *zeros, uint32_t *masks, hipStream_t s);

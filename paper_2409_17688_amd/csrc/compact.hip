@@ -501,6 +501,45 @@ bool chunk_ok(const void *p, int64_t ld, int64_t ncols) {
 
 }  // namespace
 
+hipError_t launch_shared_from_u16(int64_t N, int64_t ncols, const uint16_t *X, int64_t ldx,
+                                  uint8_t *Y, int64_t ldy, int32_t *base, int32_t *status,
+                                  hipStream_t s) {
+  hipError_t e = launch_fill_i32(base, 1, 0xFFFF, s);
+  if (e == hipSuccess) e = launch_fill_i32(base + 1, 1, 0, s);
+  if (e != hipSuccess || N == 0 || ncols == 0) return e;
+  hipLaunchKernelGGL(shared_min_kernel, dim3((unsigned)N), dim3(256), 0, s, ncols, X, ldx, base,
+                     status);
+  hipLaunchKernelGGL(shared_residual_kernel, dim3((unsigned)N), dim3(256), 0, s, ncols, X, ldx,
+                     (const int32_t *)base, Y, ldy, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_step(const StateView &v, const uint8_t *X, int64_t ldx, const int32_t *bx,
+                              uint8_t *Y, int64_t ldy, int32_t *by, int64_t ncols,
+                              int32_t *status, hipStream_t s) {
+  const int64_t N = v.N;
+  hipLaunchKernelGGL(shared_prepare_kernel, dim3(1), dim3(64), 0, s, bx, by);
+  const int64_t nblocks = (N + kRows - 1) / kRows;
+  const int64_t panels = (ncols + 511) / 512;
+  const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
+  if (g_unroll == 8)
+    hipLaunchKernelGGL((shared_step_kernel<8>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
+                       v.border, X, ldx, bx, Y, ldy, by, ncols, status);
+  else
+    hipLaunchKernelGGL((shared_step_kernel<4>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
+                       v.border, X, ldx, bx, Y, ldy, by, ncols, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_diag(int64_t N, const uint8_t *X, int64_t ldx, const int32_t *base,
+                              int32_t *out, hipStream_t s) {
+  hipError_t e = launch_fill_i32(out, 1, 0xFFFF, s);
+  if (e != hipSuccess || N == 0) return e;
+  const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
+  hipLaunchKernelGGL(shared_diag_kernel, dim3(blocks), dim3(256), 0, s, N, X, ldx, base, out);
+  return hipGetLastError();
+}
+
 }  // namespace tp
 
 using namespace tp;
@@ -585,18 +624,10 @@ int tp_compact_shared_from_u16(int64_t N, int64_t ncols, const void *d_X, int64_
                                hipStream_t stream) {
   TP_REQUIRE(N >= 0 && ncols >= 0 && N < ((int64_t)1 << 31), "bad size");
   TP_REQUIRE(d_base && d_status, "NULL pointer");
-  TP_HIP_CHECK(launch_fill_i32(d_base, 1, 0xFFFF, stream));
-  TP_HIP_CHECK(launch_fill_i32(d_base + 1, 1, 0, stream));
-  if (N == 0 || ncols == 0) return TP_OK;
-  TP_REQUIRE(ldx >= ncols && ldy >= ncols, "leading dimension < ncols");
-  TP_REQUIRE(d_X && d_Y, "NULL pointer");
-  hipLaunchKernelGGL(shared_min_kernel, dim3((unsigned)N), dim3(256), 0, stream, ncols,
-                     (const uint16_t *)d_X, ldx, d_base, d_status);
-  TP_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(shared_residual_kernel, dim3((unsigned)N), dim3(256), 0, stream, ncols,
-                     (const uint16_t *)d_X, ldx, (const int32_t *)d_base, (uint8_t *)d_Y, ldy,
-                     d_status);
-  TP_HIP_CHECK(hipGetLastError());
+  TP_REQUIRE(N == 0 || ncols == 0 || (ldx >= ncols && ldy >= ncols && d_X && d_Y),
+             "bad X or Y");
+  TP_HIP_CHECK(launch_shared_from_u16(N, ncols, (const uint16_t *)d_X, ldx, (uint8_t *)d_Y, ldy,
+                                      d_base, d_status, stream));
   return TP_OK;
 }
 
@@ -628,21 +659,8 @@ int tp_compact_shared_step(int n, const void *d_X, int64_t ldx, const int32_t *d
   StateView v;
   const int rc = state_view(n, stream, &v);
   if (rc != TP_OK) return rc;
-  const int64_t N = v.N;
-  hipLaunchKernelGGL(shared_prepare_kernel, dim3(1), dim3(64), 0, stream, d_bx, d_by);
-  TP_HIP_CHECK(hipGetLastError());
-  const int64_t nblocks = (N + kRows - 1) / kRows;
-  const int64_t panels = (ncols + 511) / 512;
-  const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
-  if (g_unroll == 8)
-    hipLaunchKernelGGL((shared_step_kernel<8>), grid, dim3(256), 0, stream, N, v.bptr, v.bent,
-                       v.border, (const uint8_t *)d_X, ldx, d_bx, (uint8_t *)d_Y, ldy, d_by,
-                       ncols, d_status);
-  else
-    hipLaunchKernelGGL((shared_step_kernel<4>), grid, dim3(256), 0, stream, N, v.bptr, v.bent,
-                       v.border, (const uint8_t *)d_X, ldx, d_bx, (uint8_t *)d_Y, ldy, d_by,
-                       ncols, d_status);
-  TP_HIP_CHECK(hipGetLastError());
+  TP_HIP_CHECK(launch_shared_step(v, (const uint8_t *)d_X, ldx, d_bx, (uint8_t *)d_Y, ldy, d_by,
+                                  ncols, d_status, stream));
   return TP_OK;
 }
 
@@ -650,13 +668,8 @@ int tp_compact_shared_diag_min(int64_t N, const void *d_X, int64_t ldx, const in
                                int32_t *d_out, hipStream_t stream) {
   TP_REQUIRE(N >= 0 && N < ((int64_t)1 << 31), "bad size");
   TP_REQUIRE(d_out != nullptr, "out is NULL");
-  TP_HIP_CHECK(launch_fill_i32(d_out, 1, 0xFFFF, stream));
-  if (N == 0) return TP_OK;
-  TP_REQUIRE(ldx >= N && d_X && d_base, "bad X or base");
-  const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
-  hipLaunchKernelGGL(shared_diag_kernel, dim3(blocks), dim3(256), 0, stream, N,
-                     (const uint8_t *)d_X, ldx, d_base, d_out);
-  TP_HIP_CHECK(hipGetLastError());
+  TP_REQUIRE(N == 0 || (ldx >= N && d_X && d_base), "bad X or base");
+  TP_HIP_CHECK(launch_shared_diag(N, (const uint8_t *)d_X, ldx, d_base, d_out, stream));
   return TP_OK;
 }
 

@@ -185,3 +185,25 @@ def test_n13_beyond_the_papers_gpu(tp):
             assert tp.tp_gamma2_recurrence(rec, diag, m) == diag[m - 1]
     for m in range(3, 51, 3):
         assert diag[m - 1] == 15 * m // 3, m
+
+
+@pytest.mark.parametrize("n,K,window", [(1, 50, 0), (2, 50, 0), (4, 50, 0), (6, 50, 0),
+                                        (7, 50, 10), (7, 50, 18), (8, 50, 0), (9, 50, 0),
+                                        (10, 50, 0), (8, 5, 0), (5, 4, 0)])
+def test_compact_chain_recurrence_matches_16_bits(tp, oracle_mod, n, K, window):
+    """The chain on shared-base compact powers (forced from n = 2 on) gives
+    the 16-bit chain's search results and diagonal minima, and the oracle's."""
+    say("compact recurrence", n, K, window)
+    try:
+        tp.tp_tune_recurrence(0)
+        rec16, diag16 = tp.tp_recurrence(n, K, window)
+        tp.tp_tune_recurrence(2)
+        rec8, diag8 = tp.tp_recurrence(n, K, window)
+    finally:
+        tp.tp_tune_recurrence(11)
+    fields = ("K", "window", "found", "window_short", "r0", "a", "b", "n0")
+    assert [getattr(rec8, f) for f in fields] == [getattr(rec16, f) for f in fields]
+    assert list(diag8) == list(diag16) == list(oracle_mod.gamma2_sweep(n, K))
+    want = oracle_mod.recurrence(n, K)
+    if want is not None and not rec8.window_short:
+        assert (rec8.r0, rec8.a, rec8.b, rec8.n0) == want
