@@ -394,14 +394,15 @@ typedef struct tp_recurrence {
 int tp_recurrence(int n, int K, int window, tp_recurrence_t *out, int32_t *diag_min_host,
                   hipStream_t stream);
 
-/* Path orders from which tp_recurrence runs its chain on shared-base
- * compact powers (u8 residuals over one base per power, the powers from the
- * first one with no INF entry on): 11 by default, where that step is faster
- * than the 16-bit one; 0 keeps every chain in 16 bits.  Results are the
- * same either way: powers before the switch hold INF entries, so their
- * comparisons with the all-finite later ones fail as in 16 bits, and a
- * power that cannot be held sends the whole search back to 16 bits. */
-int tp_tune_recurrence(int compact_from_n);
+/* Path orders from which the power chains of tp_recurrence and of
+ * tp_tropical_power_trace's pruned plans run on shared-base compact powers
+ * (u8 residuals over one base per power, from the first power with no INF
+ * entry on): 11 by default, where that step is faster than the 16-bit one;
+ * 0 keeps every chain in 16 bits.  Results are the same either way: in the
+ * recurrence, powers before the switch hold INF entries, so their
+ * comparisons with the all-finite later ones fail as in 16 bits; a power
+ * that cannot be held sends the call back to the 16-bit chain. */
+int tp_tune_compact_chains(int compact_from_n);
 
 /* gamma_2(P_n x C_m) for any m >= 3 from a recurrence and its boundary values
  * (host only, no device work): diag_min[m - 1] when m <= K, else, when the

@@ -97,7 +97,7 @@ _SIGS = {
     "tp_compact_step": ([_i, _p, _i64, _p, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_compact_diag_min": ([_i64, _p, _i64, _p, _p, _p], _i),
     "tp_tune_compact_step": ([_i], _i),
-    "tp_tune_recurrence": ([_i], _i),
+    "tp_tune_compact_chains": ([_i], _i),
     "tp_compact_shared_from_u16": ([_i64, _i64, _p, _i64, _p, _i64, _p, _p, _p], _i),
     "tp_compact_shared_to_u16": ([_i64, _i64, _p, _i64, _p, _p, _i64, _p], _i),
     "tp_compact_shared_step": ([_i, _p, _i64, _p, _p, _i64, _p, _i64, _p, _p], _i),
@@ -663,9 +663,10 @@ def tp_compact_shared_diag_min(X: torch.Tensor, base: torch.Tensor, stream=None)
     return int(out.item())
 
 
-def tp_tune_recurrence(compact_from_n: int) -> None:
-    """Path orders from which tp_recurrence chains compact powers (0: never)."""
-    _check(lib.tp_tune_recurrence(int(compact_from_n)))
+def tp_tune_compact_chains(compact_from_n: int) -> None:
+    """Path orders from which the recurrence and the pruned plain path chain
+    compact powers (0: never)."""
+    _check(lib.tp_tune_compact_chains(int(compact_from_n)))
 
 
 def tp_tune_compact_step(unroll: int) -> None:

@@ -359,12 +359,51 @@ int pruned_chain(State *st, int64_t m, int k, hipStream_t s, int32_t *out_host) 
   TP_HIP_CHECK(ensure(ws.buf[1], mat));
   TP_HIP_CHECK(ensure(ws.scalar, 64));
   uint16_t *X = (uint16_t *)ws.buf[0].ptr, *Y = (uint16_t *)ws.buf[1].ptr;
+  int32_t *d_res = (int32_t *)ws.scalar.ptr;
   TP_HIP_CHECK(launch_state_columns(st->n, N, (const uint32_t *)st->masks.ptr, idx, cnt, X, ld, s));
+  // from n = 11 on (tp_tune_compact_chains) the steps after A^3 run on
+  // shared-base compact powers held in the same two buffers (u8 rows of ld
+  // bytes), and the last power comes back to 16 bits for the diagonal
+  constexpr int64_t kSwitch = 3;
+  if (compact_chain(st->n) && m >= kSwitch + 2) {
+    for (int64_t t = 2; t <= kSwitch; ++t) {
+      TP_HIP_CHECK(state_step(st, TP_STEP_AUTO, X, ld, Y, ld, cnt, s));
+      std::swap(X, Y);
+    }
+    int32_t *bx = d_res + 4, *by = d_res + 8, *status = d_res + 12;
+    uint8_t *X8 = (uint8_t *)Y, *Y8 = (uint8_t *)X;  // Y8 overwrites the 16-bit A^3 after it is read
+    TP_HIP_CHECK(launch_fill_i32(status, 1, 0, s));
+    TP_HIP_CHECK(launch_shared_from_u16(N, cnt, X, ld, X8, ld, bx, status, s));
+    StateView v{};
+    v.n = st->n;
+    v.N = N;
+    v.bptr = (const int64_t *)st->bptr.ptr;
+    v.bent = (const uint64_t *)st->bent.ptr;
+    v.border = (const int32_t *)st->border.ptr;
+    for (int64_t t = kSwitch + 1; t <= m; ++t) {
+      TP_HIP_CHECK(launch_shared_step(v, X8, ld, bx, Y8, ld, by, cnt, status, s));
+      std::swap(X8, Y8);
+      std::swap(bx, by);
+    }
+    // the last power (in X8) to 16 bits in the other buffer
+    uint16_t *P = (uint16_t *)Y8;
+    TP_HIP_CHECK(launch_shared_to_u16(N, cnt, X8, ld, bx, P, ld, s));
+    TP_HIP_CHECK(launch_diag_select_min(N, cnt, idx, P, ld, d_res, s));
+    int32_t host[13] = {0};
+    TP_HIP_CHECK(hipMemcpyAsync(host, d_res, sizeof(host), hipMemcpyDeviceToHost, s));
+    TP_HIP_CHECK(hipStreamSynchronize(s));
+    if (host[12] == 0) {
+      *out_host = host[0];
+      return TP_OK;
+    }
+    // a power the compact form could not hold: the 16-bit chain from the start
+    TP_HIP_CHECK(launch_state_columns(st->n, N, (const uint32_t *)st->masks.ptr, idx, cnt, X, ld,
+                                      s));
+  }
   for (int64_t t = 2; t <= m; ++t) {
     TP_HIP_CHECK(state_step(st, TP_STEP_AUTO, X, ld, Y, ld, cnt, s));
     std::swap(X, Y);
   }
-  int32_t *d_res = (int32_t *)ws.scalar.ptr;
   TP_HIP_CHECK(launch_diag_select_min(N, cnt, idx, X, ld, d_res, s));
   TP_HIP_CHECK(hipMemcpyAsync(out_host, d_res, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   TP_HIP_CHECK(hipStreamSynchronize(s));

@@ -124,6 +124,11 @@ hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, u
 
 // compact.hip: shared-base compact powers (u8 residuals, base[0] = G,
 // base[1] = least residual; status bits 1 = range, 2 = INF present)
+// Path orders from which the power chains of tp_recurrence and of the
+// pruned plain path run on shared-base compact powers (0: never).
+bool compact_chain(int n);
+hipError_t launch_shared_to_u16(int64_t N, int64_t ncols, const uint8_t *X, int64_t ldx,
+                                const int32_t *base, uint16_t *Y, int64_t ldy, hipStream_t s);
 hipError_t launch_shared_from_u16(int64_t N, int64_t ncols, const uint16_t *X, int64_t ldx,
                                   uint8_t *Y, int64_t ldy, int32_t *base, int32_t *status,
                                   hipStream_t s);

@@ -501,6 +501,10 @@ bool chunk_ok(const void *p, int64_t ld, int64_t ncols) {
 
 }  // namespace
 
+int g_compact_chain_from = 11;
+
+bool compact_chain(int n) { return g_compact_chain_from > 0 && n >= g_compact_chain_from; }
+
 hipError_t launch_shared_from_u16(int64_t N, int64_t ncols, const uint16_t *X, int64_t ldx,
                                   uint8_t *Y, int64_t ldy, int32_t *base, int32_t *status,
                                   hipStream_t s) {
@@ -511,6 +515,14 @@ hipError_t launch_shared_from_u16(int64_t N, int64_t ncols, const uint16_t *X, i
                      status);
   hipLaunchKernelGGL(shared_residual_kernel, dim3((unsigned)N), dim3(256), 0, s, ncols, X, ldx,
                      (const int32_t *)base, Y, ldy, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_to_u16(int64_t N, int64_t ncols, const uint8_t *X, int64_t ldx,
+                                const int32_t *base, uint16_t *Y, int64_t ldy, hipStream_t s) {
+  if (N == 0 || ncols == 0) return hipSuccess;
+  const dim3 grid((unsigned)N, (unsigned)std::min<int64_t>((ncols + 255) / 256, 64));
+  hipLaunchKernelGGL(shared_to_u16_kernel, grid, dim3(256), 0, s, ncols, X, ldx, base, Y, ldy);
   return hipGetLastError();
 }
 
@@ -637,10 +649,8 @@ int tp_compact_shared_to_u16(int64_t N, int64_t ncols, const void *d_X, int64_t 
   if (N == 0 || ncols == 0) return TP_OK;
   TP_REQUIRE(ldx >= ncols && ldy >= ncols, "leading dimension < ncols");
   TP_REQUIRE(d_X && d_Y && d_base, "NULL pointer");
-  const dim3 grid((unsigned)N, (unsigned)std::min<int64_t>((ncols + 255) / 256, 64));
-  hipLaunchKernelGGL(shared_to_u16_kernel, grid, dim3(256), 0, stream, ncols,
-                     (const uint8_t *)d_X, ldx, d_base, (uint16_t *)d_Y, ldy);
-  TP_HIP_CHECK(hipGetLastError());
+  TP_HIP_CHECK(launch_shared_to_u16(N, ncols, (const uint8_t *)d_X, ldx, d_base, (uint16_t *)d_Y,
+                                    ldy, stream));
   return TP_OK;
 }
 
@@ -670,6 +680,12 @@ int tp_compact_shared_diag_min(int64_t N, const void *d_X, int64_t ldx, const in
   TP_REQUIRE(d_out != nullptr, "out is NULL");
   TP_REQUIRE(N == 0 || (ldx >= N && d_X && d_base), "bad X or base");
   TP_HIP_CHECK(launch_shared_diag(N, (const uint8_t *)d_X, ldx, d_base, d_out, stream));
+  return TP_OK;
+}
+
+int tp_tune_compact_chains(int compact_from_n) {
+  TP_REQUIRE(compact_from_n >= 0, "negative path order");
+  g_compact_chain_from = compact_from_n;
   return TP_OK;
 }
 

@@ -336,9 +336,6 @@ tp_recurrence_t search(const std::vector<int32_t> &table, int K, int W) {
   return r;
 }
 
-// Path orders from which the chain runs on shared-base compact powers (u8
-// residuals over one base per power); 0 turns it off.
-int g_compact_from = 11;
 constexpr int kNotHeld = 1;  // the compact chain cannot hold these powers
 constexpr int kMaxEarly = 3;  // 16-bit powers before the switch, at most
 
@@ -513,7 +510,7 @@ int tp_recurrence(int n, int K, int window, tp_recurrence_t *out, int32_t *diag_
   StateView v{};
   int rc = state_view(n, stream, &v);
   if (rc != TP_OK) return rc;
-  if (g_compact_from > 0 && n >= g_compact_from) {
+  if (compact_chain(n)) {
     rc = recurrence_compact(v, K, window, out, diag_min_host, stream);
     if (rc != kNotHeld) return rc;
   }
@@ -558,12 +555,6 @@ int tp_recurrence(int n, int K, int window, tp_recurrence_t *out, int32_t *diag_
   TP_HIP_CHECK(hipStreamSynchronize(stream));
   for (int k = 1; k <= K; ++k) diag_min_host[k - 1] = diag[k];
   *out = search(table, K, W);
-  return TP_OK;
-}
-
-int tp_tune_recurrence(int compact_from_n) {
-  TP_REQUIRE(compact_from_n >= 0, "negative path order");
-  g_compact_from = compact_from_n;
   return TP_OK;
 }
 

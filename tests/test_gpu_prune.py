@@ -103,3 +103,21 @@ def test_prune_mode_rejects_bad_values(tp):
         tp.tp_tune_prune(2)
     with pytest.raises(tp.TropicalError):
         tp.tp_state_select(0, 1)
+
+
+def test_pruned_compact_chain_matches_oracle_and_16_bits(tp, oracle_mod, forced):
+    """The pruned plain path with its chain on shared-base compact powers
+    (forced from n = 2 on; n = 1 never holds and falls back): the oracle's
+    gamma_2 for n <= 8, m <= 40, and the 16-bit chain's for n = 9, 10."""
+    try:
+        tp.tp_tune_compact_chains(2)
+        for n in range(1, 9):
+            g = oracle_mod.gamma2_sweep(n, 40)
+            for m in range(3, 41):
+                assert tp.tp_tropical_power_trace(n, m) == g[m - 1], (n, m)
+        got = {(n, m): tp.tp_tropical_power_trace(n, m) for n in (9, 10) for m in (5, 6, 13, 40)}
+        tp.tp_tune_compact_chains(0)
+        for (n, m), v in got.items():
+            assert v == tp.tp_tropical_power_trace(n, m) == gamma2_closed_form(n, m), (n, m)
+    finally:
+        tp.tp_tune_compact_chains(11)

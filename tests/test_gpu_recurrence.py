@@ -195,12 +195,12 @@ def test_compact_chain_recurrence_matches_16_bits(tp, oracle_mod, n, K, window):
     the 16-bit chain's search results and diagonal minima, and the oracle's."""
     say("compact recurrence", n, K, window)
     try:
-        tp.tp_tune_recurrence(0)
+        tp.tp_tune_compact_chains(0)
         rec16, diag16 = tp.tp_recurrence(n, K, window)
-        tp.tp_tune_recurrence(2)
+        tp.tp_tune_compact_chains(2)
         rec8, diag8 = tp.tp_recurrence(n, K, window)
     finally:
-        tp.tp_tune_recurrence(11)
+        tp.tp_tune_compact_chains(11)
     fields = ("K", "window", "found", "window_short", "r0", "a", "b", "n0")
     assert [getattr(rec8, f) for f in fields] == [getattr(rec16, f) for f in fields]
     assert list(diag8) == list(diag16) == list(oracle_mod.gamma2_sweep(n, K))
