@@ -24,6 +24,7 @@
 // at the store.  Offsets are exact integers: P[q][c] above 65535 is INF only
 // when expanded to the 16-bit form, as the 16-bit chain saturates there.
 #include <algorithm>
+#include <atomic>
 
 #include "device_core.hpp"
 
@@ -37,7 +38,7 @@ constexpr int32_t kMaxGap = 0xFF00;      // largest offset gap inside a block
 constexpr int32_t kStatusRange = 1;      // a residual above 254 or a gap above kMaxGap
 constexpr int32_t kStatusMixed = 2;      // a row with finite and INF entries
 
-int g_unroll = 4;  // entries per round of the step (4 or 8)
+std::atomic<int> g_unroll{4};  // entries per round of the step (4 or 8)
 
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 #pragma unroll
@@ -501,9 +502,12 @@ bool chunk_ok(const void *p, int64_t ld, int64_t ncols) {
 
 }  // namespace
 
-int g_compact_chain_from = 11;
+std::atomic<int> g_compact_chain_from{11};
 
-bool compact_chain(int n) { return g_compact_chain_from > 0 && n >= g_compact_chain_from; }
+bool compact_chain(int n) {
+  const int from = g_compact_chain_from.load();
+  return from > 0 && n >= from;
+}
 
 hipError_t launch_shared_from_u16(int64_t N, int64_t ncols, const uint16_t *X, int64_t ldx,
                                   uint8_t *Y, int64_t ldy, int32_t *base, int32_t *status,

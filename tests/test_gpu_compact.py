@@ -352,3 +352,27 @@ def test_shared_conversion_reports(tp, oracle_mod):
     assert int(st.item()) == 0
     assert b.tolist() == [500, 0]
     assert (_host(tp.tp_compact_shared_to_u16(X8, b, 50)) == M).all()
+
+
+def test_shared_argument_checks(tp):
+    import torch
+    n = 4
+    N = tp.tp_state_dim(n)
+    X8, Y8 = _u8(N, N), _u8(N, N)
+    b1, b2 = _base2(), _base2()
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_shared_step(n, X8, b1, N, X8, b2)  # in place
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_shared_step(n, X8, b1, N, Y8, b1)  # one base word for both
+    odd = torch.empty((N, 60), dtype=torch.uint8, device="cuda")[:, :N]
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_shared_step(n, odd, b1, N, Y8, b2)  # ld not a multiple of 8
+    with pytest.raises(RuntimeError):
+        tp.tp_compact_shared_step(0, X8, b1, N, Y8, b2)
+    with pytest.raises(RuntimeError):
+        tp.tp_tune_compact_chains(-1)
+    tp.tp_compact_shared_step(n, X8, b1, 0, Y8, b2)  # no columns: nothing to do
+    # an empty matrix converts to base {INF, 0} and no status
+    st = _status()
+    Y, b = tp.tp_compact_shared_from_u16(_dev16(np.zeros((0, 0), dtype=np.int64)), status=st)
+    assert b.tolist() == [INF, 0] and int(st.item()) == 0
