@@ -207,3 +207,18 @@ def test_compact_chain_recurrence_matches_16_bits(tp, oracle_mod, n, K, window):
     want = oracle_mod.recurrence(n, K)
     if want is not None and not rec8.window_short:
         assert (rec8.r0, rec8.a, rec8.b, rec8.n0) == want
+
+
+@pytest.mark.parametrize("n,K,window", [(11, 200, 6), (12, 120, 4)])
+def test_compact_chain_long_runs_closed_form(tp, tables, n, K, window):
+    """Long chains on shared-base compact powers (the default from n = 11):
+    every diagonal minimum up to K == the closed form, and the recurrence of
+    Tables 3 and 4 found at i = K."""
+    say("long compact recurrence", n, K, window)
+    rec, diag = tp.tp_recurrence(n, K, window)
+    t3, t4 = tables
+    assert rec.found and not rec.window_short
+    assert rec.r0 == K - rec.a and (rec.a, rec.b) == t3[n][1:]
+    assert (rec.n0, rec.a, rec.b) == t4[n]
+    for m in range(3, K + 1):
+        assert diag[m - 1] == gamma2_closed_form(n, m), (n, m)
