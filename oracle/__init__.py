@@ -64,6 +64,8 @@ def _load():
     lib.oracle_follows.restype = ctypes.c_int
     lib.oracle_state_matrix.argtypes = [ctypes.c_int, ctypes.c_int32, i32p]
     lib.oracle_state_matrix.restype = ctypes.c_int64
+    lib.oracle_state_rows.argtypes = [ctypes.c_int, ctypes.c_int64, i64p, ctypes.c_int32, i32p]
+    lib.oracle_state_rows.restype = ctypes.c_int64
     lib.oracle_minplus.argtypes = [ctypes.c_int64] * 3 + [i32p, ctypes.c_int64, i32p, ctypes.c_int64,
                                                           i32p, ctypes.c_int64, ctypes.c_int32]
     lib.oracle_minplus.restype = None
@@ -133,6 +135,19 @@ def state_matrix(n: int, inf: int = INF16) -> np.ndarray:
     A = np.empty((N, N), dtype=np.int32)
     _load().oracle_state_matrix(n, inf, _i32(A))
     return A
+
+
+def state_rows(n: int, rows, inf: int = INF16) -> np.ndarray:
+    """Rows ``rows`` of A(D_n) (Algorithm 1) as a len(rows) x N int32 matrix,
+    without building the whole matrix (n = 11, 12)."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    N = word_count(n)
+    out = np.empty((rows.size, N), dtype=np.int32)
+    r = _load().oracle_state_rows(n, rows.size, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  inf, _i32(out))
+    if r < 0:
+        raise ValueError("bad path order or row index")
+    return out
 
 
 def minplus(A: np.ndarray, B: np.ndarray, inf: int = INF16) -> np.ndarray:

@@ -152,6 +152,30 @@ int64_t oracle_state_matrix(int n, int32_t inf, int32_t *A)
     return N;
 }
 
+/* Selected rows of Algorithm 1's matrix, for path orders whose whole matrix
+ * is too large to hold (n = 11, 12): out[r][p] = zeros(p) if p can follow
+ * word rows[r], else INF, by the same follows test as oracle_state_matrix.
+ * rows[] index the correct words in increasing order; out is nrows x N
+ * int32, leading dimension N.  Returns N, or -1 on bad n or a row index
+ * outside 0..N-1 (nothing written then). */
+int64_t oracle_state_rows(int n, int64_t nrows, const int64_t *rows, int32_t inf, int32_t *out)
+{
+    int64_t N = oracle_words(n, NULL);
+    if (N < 0 || nrows < 0)
+        return -1;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (rows[r] < 0 || rows[r] >= N)
+            return -1;
+    uint32_t *w = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    oracle_words(n, w);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r)
+        for (int64_t j = 0; j < N; ++j)
+            out[r * N + j] = oracle_follows(n, w[rows[r]], w[j]) ? oracle_zeros(n, w[j]) : inf;
+    free(w);
+    return N;
+}
+
 /* Section 1: C = A x B in the (min,+) semiring, saturating at INF.
  * C is M x N, A is M x K, B is K x N, all row-major int32 with the given
  * leading dimensions; inputs hold values in [0, INF].  C must not alias A or B. */

@@ -12,6 +12,9 @@ the path order n alone):
   ``numpy.random.default_rng(seed)``, A drawn before B.
 * ``stress_matrix``   -- matrices for parity stress tests (wide value ranges,
   chosen INF fractions, sums near INF).
+* ``residual_matrix`` -- 8-bit residuals with one shared base (and optionally
+  one offset per row) for the compact-power steps: uniform residuals in
+  [lo, hi] with the least value placed at least once.
 * ``batch_instances`` -- the mixed batch: 64 (n, m) pairs, n uniform in 4..9,
   m uniform in 3..200, n drawn before m.
 * ``serve_stream``    -- a Poisson stream of (arrival time, n, m) queries with
@@ -45,6 +48,23 @@ def stress_matrix(rows: int, cols: int, seed: int, lo: int = 0, hi: int = 30000,
     if inf_frac > 0:
         X[rng.random((rows, cols)) < inf_frac] = inf
     return X
+
+
+def residual_matrix(rows: int, cols: int, seed: int, lo: int = 0, hi: int = 14,
+                    base: int = 600, row_offsets: tuple | None = None):
+    """(x, base_word, offsets): x uint8 rows x cols uniform in [lo, hi] with
+    x[0, 0] = lo, so lo is the least residual; base_word = int32 [base, lo];
+    offsets = int32 per-row values uniform in row_offsets (inclusive), or
+    None when row_offsets is None."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(lo, hi + 1, size=(rows, cols)).astype(np.uint8)
+    if rows and cols:
+        x[0, 0] = lo
+    word = np.array([base, lo], dtype=np.int32)
+    off = None
+    if row_offsets is not None:
+        off = rng.integers(row_offsets[0], row_offsets[1] + 1, size=rows).astype(np.int32)
+    return x, word, off
 
 
 def batch_instances(seed: int = 0, count: int = 64, n_lo: int = 4, n_hi: int = 9,

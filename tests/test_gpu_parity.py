@@ -353,6 +353,21 @@ def test_power_trace_vs_oracle(tp, oracle_mod):
             assert tp.tp_tropical_power_trace(n, m) == g[m - 1], (n, m)
 
 
+@pytest.mark.parametrize("prune", [0, 1, -1])
+def test_power_trace_n8_every_m_to_256(tp, oracle_mod, prune):
+    """The mid-size plain path: gamma_2(P_8 x C_m) for every m = 3..256 ==
+    the oracle's chain of 256 powers, with start-state pruning chosen by the
+    cost model, forced, and off."""
+    g = oracle_mod.gamma2_sweep(8, 256)
+    tp.tp_tune_prune(prune)
+    try:
+        say("power_trace n = 8, m = 3..256, prune", prune)
+        got = [tp.tp_tropical_power_trace(8, m) for m in range(3, 257)]
+    finally:
+        tp.tp_tune_prune(0)
+    assert got == [int(v) for v in g[2:256]]
+
+
 def test_power_trace_config1_n3(tp, oracle_mod):
     """n = 3, m = 3..30: oracle, and exhaustive search for m <= 10."""
     g = oracle_mod.gamma2_sweep(3, 30, INF8)

@@ -174,7 +174,9 @@ def test_n13_beyond_the_papers_gpu(tp):
     parity unpinned, so only properties.  Lemma 1 read on the diagonal: once
     the powers repeat with (a, b) from n0 on, so do their diagonal minima;
     Theorem 3's solution agrees with the computed minima; and the paper's
-    conjecture gamma_2 = (n + 2) m / 3 for m = 0 (mod 3) (Section 4)."""
+    conjecture gamma_2 = (n + 2) m / 3 for m = 0 (mod 3) (Section 4), and the
+    one proven value Section 4 quotes for this path order: 2n + 1 = 27 at
+    cycle 5."""
     say("recurrence 13")
     rec, diag = tp.tp_recurrence(13, 50, 3)
     assert rec.K == 50 and rec.window == 3
@@ -185,6 +187,9 @@ def test_n13_beyond_the_papers_gpu(tp):
             assert tp.tp_gamma2_recurrence(rec, diag, m) == diag[m - 1]
     for m in range(3, 51, 3):
         assert diag[m - 1] == 15 * m // 3, m
+    # the cycle-5 value the paper quotes from its companion work (Section 4):
+    # gamma_2(C_5 x P_n) = 2n + 1 for odd n, proven for every path order
+    assert diag[5 - 1] == 2 * 13 + 1
 
 
 @pytest.mark.parametrize("n,K,window", [(1, 50, 0), (2, 50, 0), (4, 50, 0), (6, 50, 0),

@@ -182,3 +182,40 @@ def test_lemma1_shift(oracle_mod):
         lo = oracle_mod.power(n, m0 + t)
         assert (hi == lo + b).all()
     assert not (oracle_mod.power(n, m0 - 1 + a) == oracle_mod.power(n, m0 - 1) + b).all()
+
+
+def test_state_rows_are_rows_of_the_state_matrix(oracle_mod):
+    """Rows built alone (the form the n = 11..13 parity tests use) equal the
+    rows of the whole matrix for n = 1..9, in any order, repeated or not."""
+    rng = np.random.default_rng(9)
+    for n in range(1, 10):
+        A = oracle_mod.state_matrix(n)
+        N = A.shape[0]
+        rows = np.concatenate([[0, N - 1], rng.integers(0, N, 20), [0]])
+        assert (oracle_mod.state_rows(n, rows) == A[rows]).all(), n
+    with pytest.raises(ValueError):
+        oracle_mod.state_rows(4, [36])
+    with pytest.raises(ValueError):
+        oracle_mod.state_rows(4, [-1])
+
+
+def test_state_rows_fixed_columns_and_rows_at_large_n(oracle_mod):
+    """Two consequences of Section 2.2's rules that hold for every n, checked
+    where the whole matrix is not built (n = 10..13):
+    * the all-zero word can follow every word (no letter of it is 1 or 2, and
+      q_i = 2 only asks p_i = 0), with label n: column 0 is n in every row;
+    * after the all-2 word only the all-zero word can follow (q_i = 2 forces
+      p_i = 0 at every position): that row is n at column 0 and INF elsewhere;
+    * every finite entry is the number of zeros of its column's word."""
+    for n in range(10, 14):
+        codes = oracle_mod.words(n)
+        N = codes.size
+        all2 = int(np.searchsorted(codes, 3 ** n - 1))
+        assert codes[all2] == 3 ** n - 1
+        rows = np.array([0, 1, N // 3, N - 1, all2], dtype=np.int64)
+        R = oracle_mod.state_rows(n, rows)
+        assert (R[:, 0] == n).all(), n
+        assert R[-1, 0] == n and (R[-1, 1:] == INF).all(), n
+        fin = np.nonzero(R[:3] < INF)
+        for r, c in zip(*fin):
+            assert R[r, c] == oracle_mod.word_string(n, int(codes[c])).count("0")
