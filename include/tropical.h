@@ -269,6 +269,22 @@ int tp_compact_shared_step(int n, const void *d_X, int64_t ldx, const int32_t *d
 int tp_compact_shared_diag_min(int64_t N, const void *d_X, int64_t ldx, const int32_t *d_base,
                                int32_t *d_out, hipStream_t stream);
 
+/* *d_out = min(65535, G_X + G_P + min over t < count and k < N of
+ * x[r_t][k] + p[k][t]), r_t = d_idx[t] (r_t = t when d_idx is NULL, which
+ * needs count <= N): Theorem 2's trace of the product X x P read only on the
+ * diagonal entries of the listed states, for X a square shared-base power
+ * (N x N, rows r_t read) and P an N x count shared-base panel whose column t
+ * belongs to state r_t (the columns d_idx of another power, as
+ * tp_build_state_columns lays them out).  With d_idx NULL and count = N it is
+ * the whole trace of the product, min_i (X x P)_ii.  d_bx, d_bp: the two
+ * base words (G first).  Every d_idx[t] must lie in 0..N-1 (device memory,
+ * not checked).  16-byte aligned rows with ld a multiple of 16 take the
+ * vector path; any layout with ldx >= N, ldp >= count is accepted. */
+int tp_compact_shared_select_trace(int64_t N, int64_t count, const int32_t *d_idx,
+                                   const void *d_X, int64_t ldx, const int32_t *d_bx,
+                                   const void *d_P, int64_t ldp, const int32_t *d_bp,
+                                   int32_t *d_out, hipStream_t stream);
+
 /* Gathers per round in tp_compact_step and tp_compact_shared_step (4, the
  * default, or 8).  Changes speed only. */
 int tp_tune_compact_step(int unroll);

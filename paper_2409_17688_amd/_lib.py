@@ -102,6 +102,8 @@ _SIGS = {
     "tp_compact_shared_to_u16": ([_i64, _i64, _p, _i64, _p, _p, _i64, _p], _i),
     "tp_compact_shared_step": ([_i, _p, _i64, _p, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_compact_shared_diag_min": ([_i64, _p, _i64, _p, _p, _p], _i),
+    "tp_compact_shared_select_trace": ([_i64, _i64, _p, _p, _i64, _p, _p, _i64, _p, _p, _p],
+                                       _i),
     "tp_const_diff": ([_i64, _p, _i64, _p, _i64, _p, _p], _i),
     "tp_recurrence": ([_i, _i, _i, ctypes.POINTER(Recurrence), ctypes.POINTER(ctypes.c_int32),
                        _p], _i),
@@ -661,6 +663,29 @@ def tp_compact_shared_diag_min(X: torch.Tensor, base: torch.Tensor, stream=None)
     _check(lib.tp_compact_shared_diag_min(N, px, ldx, _base(base, "base"),
                                           ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return int(out.item())
+
+
+def tp_compact_shared_select_trace(X: torch.Tensor, bx: torch.Tensor, P: torch.Tensor,
+                                   bp: torch.Tensor, idx: torch.Tensor | None = None,
+                                   out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """out[0] = G_X + G_P + min over t of min_k x[r_t][k] + p[k][t] (saturated
+    at 65535): the trace of X x P on the diagonal entries of the states
+    idx (all N states when idx is None; then P is N x N)."""
+    px, N, ldx = _u8rows(X, "X", 0)
+    if X.shape[1] < N:
+        raise ValueError("X must be N x N")
+    count = int(idx.numel()) if idx is not None else N
+    pp, Np, ldp = _u8rows(P, "P", count)
+    if Np != N or P.shape[1] < count:
+        raise ValueError("P must be N x count")
+    if idx is not None and idx.dtype != torch.int32:
+        raise TypeError("idx must be int32")
+    out = _scalar_out(out)
+    _check(lib.tp_compact_shared_select_trace(
+        N, count, ctypes.c_void_p(idx.data_ptr()) if idx is not None else None, px, ldx,
+        _base(bx, "bx"), pp, ldp, _base(bp, "bp"), ctypes.c_void_p(out.data_ptr()),
+        _stream(stream)))
+    return out
 
 
 def tp_tune_compact_chains(compact_from_n: int) -> None:

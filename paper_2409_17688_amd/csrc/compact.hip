@@ -496,6 +496,104 @@ __global__ void __launch_bounds__(256) shared_diag_kernel(int64_t N, const uint8
   }
 }
 
+// Trace of a product of two shared-base powers over selected diagonal
+// entries (Theorem 2 with start states restricted to a list):
+//   out = min(65535, G_X + G_P + min over t < count, k < N of x[r_t][k] + p[k][t])
+// with r_t = idx[t] (or t without a list).  X supplies the rows r_t (count x N
+// bytes read), P is an N x count panel (its column t belongs to state r_t).
+// A workgroup takes 64 values of t and a run of 64-row k tiles; per tile each
+// thread loads 16 bytes of one P row and 16 bytes of one X row, the X tile is
+// stored transposed in LDS (k-major), and each thread folds its P row segment
+// against the matching 16 bytes of LDS.  Byte arithmetic in 32-bit lanes.
+constexpr int kTT = 64;          // t per workgroup
+constexpr int kTK = 64;          // k per tile
+constexpr int kXsRow = kTT + 16; // LDS row (bytes) of the transposed X tile: padded, 16-aligned
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) shared_select_trace_kernel(
+    int64_t N, int64_t count, const int32_t *__restrict__ idx, const uint8_t *__restrict__ X,
+    int64_t ldx, const int32_t *__restrict__ bx, const uint8_t *__restrict__ P, int64_t ldp,
+    const int32_t *__restrict__ bp, int64_t ktiles_per_wg, int32_t *out) {
+  __shared__ __attribute__((aligned(16))) uint8_t xs[kTK][kXsRow];
+  __shared__ int32_t red[4];
+  const int tid = threadIdx.x;
+  const int row = tid >> 2;         // k row of the P load; t row of the X load
+  const int q = (tid & 3) * 16;     // 16-byte quarter of the row
+  const int64_t t0 = (int64_t)blockIdx.x * kTT;
+  const int64_t ktiles = (N + kTK - 1) / kTK;
+  const int64_t kt_begin = (int64_t)blockIdx.y * ktiles_per_wg;
+  const int64_t kt_end = min(ktiles, kt_begin + ktiles_per_wg);
+  // the X row this thread loads: state r of t = t0 + row
+  const int64_t tx = t0 + row;
+  const bool tx_ok = tx < count;
+  const int64_t r = tx_ok ? (idx ? (int64_t)idx[tx] : tx) : 0;
+  const uint8_t *xrow = X + r * ldx;
+  int32_t best = 0x7FFFFFFF;
+  for (int64_t kt = kt_begin; kt < kt_end; ++kt) {
+    const int64_t k0 = kt * kTK;
+    // X tile: xs[k][t] = x[r_t][k0 + k]; 0xFF marks positions outside the matrix
+    uint8_t xv[16];
+    if (VEC && tx_ok && k0 + q < N) {
+      const uint4 w = *(const uint4 *)(xrow + k0 + q);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xv[i] = (uint8_t)(ws[i >> 2] >> (8 * (i & 3)));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        xv[i] = (tx_ok && k0 + q + i < N) ? xrow[k0 + q + i] : (uint8_t)0xFF;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) xs[q + i][row] = xv[i];
+    // P tile row k0 + row, t0 + q .. t0 + q + 15
+    const int64_t kp = k0 + row;
+    uint32_t pw[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    if (kp < N) {
+      const uint8_t *prow = P + kp * ldp + t0 + q;
+      if (VEC && t0 + q < count) {
+        const uint4 w = *(const uint4 *)prow;
+        pw[0] = w.x;
+        pw[1] = w.y;
+        pw[2] = w.z;
+        pw[3] = w.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (t0 + q + i < count)
+            pw[i >> 2] = (pw[i >> 2] & ~(0xFFu << (8 * (i & 3)))) |
+                         ((uint32_t)prow[i] << (8 * (i & 3)));
+      }
+    }
+    __syncthreads();
+    // fold: t = t0 + q + i, k = k0 + row; an entry is live when both sides
+    // lie inside the matrices (t < count, k < N: checked, not inferred from 0xFF,
+    // which a residual never takes but padding does)
+    if (kp < N) {
+      const uint4 w = *(const uint4 *)&xs[row][q];
+      const uint32_t xw[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (t0 + q + i < count) {
+          const int32_t a = (int32_t)((xw[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+          const int32_t b = (int32_t)((pw[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+          best = min(best, a + b);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  best = wave_min_i32(best);
+  if ((tid & 63) == 0) red[tid >> 6] = best;
+  __syncthreads();
+  if (tid == 0) {
+    best = min(min(red[0], red[1]), min(red[2], red[3]));
+    if (best != 0x7FFFFFFF) {
+      const int64_t v = (int64_t)bx[0] + (int64_t)bp[0] + best;
+      atomicMin(out, (int32_t)min<int64_t>(v, 0xFFFF));
+    }
+  }
+}
+
 bool chunk_ok(const void *p, int64_t ld, int64_t ncols) {
   return ((uintptr_t)p % 8 == 0) && (ld % 8 == 0) && ld >= (ncols + 7) / 8 * 8;
 }
@@ -553,6 +651,29 @@ hipError_t launch_shared_diag(int64_t N, const uint8_t *X, int64_t ldx, const in
   if (e != hipSuccess || N == 0) return e;
   const unsigned blocks = (unsigned)std::min<int64_t>((N + 255) / 256, 1024);
   hipLaunchKernelGGL(shared_diag_kernel, dim3(blocks), dim3(256), 0, s, N, X, ldx, base, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_select_trace(int64_t N, int64_t count, const int32_t *idx,
+                                      const uint8_t *X, int64_t ldx, const int32_t *bx,
+                                      const uint8_t *P, int64_t ldp, const int32_t *bp,
+                                      int32_t *out, hipStream_t s) {
+  hipError_t e = launch_fill_i32(out, 1, 0xFFFF, s);
+  if (e != hipSuccess || N == 0 || count == 0) return e;
+  const int64_t ttiles = (count + kTT - 1) / kTT;
+  const int64_t ktiles = (N + kTK - 1) / kTK;
+  // about 4096 workgroups over the t tiles and runs of k tiles
+  const int64_t ysplit = std::max<int64_t>(1, std::min<int64_t>(ktiles, 4096 / ttiles));
+  const int64_t per = (ktiles + ysplit - 1) / ysplit;
+  const dim3 grid((unsigned)ttiles, (unsigned)((ktiles + per - 1) / per));
+  const bool vec = ((uintptr_t)X % 16 == 0) && ((uintptr_t)P % 16 == 0) && ldx % 16 == 0 &&
+                   ldp % 16 == 0;
+  if (vec)
+    hipLaunchKernelGGL(shared_select_trace_kernel<true>, grid, dim3(256), 0, s, N, count, idx, X,
+                       ldx, bx, P, ldp, bp, per, out);
+  else
+    hipLaunchKernelGGL(shared_select_trace_kernel<false>, grid, dim3(256), 0, s, N, count, idx,
+                       X, ldx, bx, P, ldp, bp, per, out);
   return hipGetLastError();
 }
 
@@ -684,6 +805,22 @@ int tp_compact_shared_diag_min(int64_t N, const void *d_X, int64_t ldx, const in
   TP_REQUIRE(d_out != nullptr, "out is NULL");
   TP_REQUIRE(N == 0 || (ldx >= N && d_X && d_base), "bad X or base");
   TP_HIP_CHECK(launch_shared_diag(N, (const uint8_t *)d_X, ldx, d_base, d_out, stream));
+  return TP_OK;
+}
+
+int tp_compact_shared_select_trace(int64_t N, int64_t count, const int32_t *d_idx,
+                                   const void *d_X, int64_t ldx, const int32_t *d_bx,
+                                   const void *d_P, int64_t ldp, const int32_t *d_bp,
+                                   int32_t *d_out, hipStream_t stream) {
+  TP_REQUIRE(N >= 0 && count >= 0 && N < ((int64_t)1 << 31), "bad size");
+  TP_REQUIRE(d_out != nullptr, "out is NULL");
+  TP_REQUIRE(d_idx != nullptr || count <= N, "count %lld exceeds N %lld without a row list",
+             (long long)count, (long long)N);
+  TP_REQUIRE(N == 0 || count == 0 ||
+                 (d_X && d_P && d_bx && d_bp && ldx >= N && ldp >= count),
+             "bad X, P or base words");
+  TP_HIP_CHECK(launch_shared_select_trace(N, count, d_idx, (const uint8_t *)d_X, ldx, d_bx,
+                                          (const uint8_t *)d_P, ldp, d_bp, d_out, stream));
   return TP_OK;
 }
 

@@ -4,6 +4,8 @@ the conversions and the diagonal minimum against the oracle's powers, the
 import numpy as np
 import pytest
 
+import synth
+
 from closed_form import gamma2_closed_form
 
 pytestmark = pytest.mark.gpu
@@ -376,3 +378,56 @@ def test_shared_argument_checks(tp):
     st = _status()
     Y, b = tp.tp_compact_shared_from_u16(_dev16(np.zeros((0, 0), dtype=np.int64)), status=st)
     assert b.tolist() == [INF, 0] and int(st.item()) == 0
+
+
+@pytest.mark.parametrize("N,count,ld_pad", [(1, 1, 64), (63, 63, 64), (64, 20, 64), (65, 65, 3),
+                                            (225, 100, 64), (1000, 1000, 8), (1000, 333, 64),
+                                            (2100, 777, 16)])
+def test_shared_select_trace_vs_oracle(tp, oracle_mod, N, count, ld_pad):
+    """Trace of X x P on selected diagonal entries == the oracle's product of
+    the listed rows of X with the panel P, read on its diagonal; with and
+    without a row list, aligned (vector) and unaligned layouts, ragged t and
+    k tiles."""
+    import torch
+    rng = np.random.default_rng(N + count)
+    x, wx, _ = synth.residual_matrix(N, N, N, 0, 200, 900)
+    p, wp, _ = synth.residual_matrix(N, count, N + 1, 2, 250, 31000)
+    for use_idx in (False, True):
+        if use_idx:
+            idx = rng.choice(N, count, replace=count > N // 2).astype(np.int32)
+        else:
+            if count != N:
+                continue
+            idx = np.arange(N, dtype=np.int32)
+        vals_x = x.astype(np.int32) + int(wx[0])
+        vals_p = p.astype(np.int32) + int(wp[0])
+        prod = oracle_mod.minplus(vals_x[idx], vals_p)
+        ref = min(oracle_mod.trace_min(prod), INF)
+        ldx = (N + ld_pad - 1) // ld_pad * ld_pad
+        ldp = (count + ld_pad - 1) // ld_pad * ld_pad
+        X8 = torch.zeros((N, ldx), dtype=torch.uint8, device="cuda")
+        P8 = torch.zeros((N, ldp), dtype=torch.uint8, device="cuda")
+        X8[:, :N] = torch.from_numpy(x).cuda()
+        P8[:, :count] = torch.from_numpy(p).cuda()
+        bx, bp = torch.from_numpy(wx).cuda(), torch.from_numpy(wp).cuda()
+        di = torch.from_numpy(idx).cuda() if use_idx else None
+        got = int(tp.tp_compact_shared_select_trace(X8, bx, P8[:, :count], bp, di).item())
+        assert got == ref, (N, count, ld_pad, use_idx)
+        # saturation: bases whose sum passes INF give INF
+        big = torch.tensor([40000, 0], dtype=torch.int32, device="cuda")
+        got = int(tp.tp_compact_shared_select_trace(X8, big, P8[:, :count], big, di).item())
+        assert got == INF
+
+
+def test_shared_select_trace_arguments(tp):
+    import torch
+    X8 = torch.zeros((10, 16), dtype=torch.uint8, device="cuda")
+    b = torch.zeros(2, dtype=torch.int32, device="cuda")
+    out = tp.tp_compact_shared_select_trace(X8[:0, :0], b, X8[:0, :0], b)
+    assert int(out.item()) == INF  # no entry: INF
+    f = tp.lib.tp_compact_shared_select_trace
+    p, pb, po = X8.data_ptr(), b.data_ptr(), out.data_ptr()
+    assert f(10, 11, None, p, 16, pb, p, 16, pb, po, None) == tp.TP_EINVAL  # count > N, no list
+    assert f(10, 10, None, p, 9, pb, p, 16, pb, po, None) == tp.TP_EINVAL   # ldx < N
+    assert f(10, 10, None, p, 16, pb, p, 16, None, po, None) == tp.TP_EINVAL
+    assert f(10, 10, None, p, 16, pb, p, 16, pb, None, None) == tp.TP_EINVAL
