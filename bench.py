@@ -9,7 +9,8 @@ algorithmic work = N^3 (min,+) operations per step.
 Prints one JSON line with the throughput, the kernel's roofline position and
 the CPU oracle timed on a bounded sample of the same product.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-suite]
+       [--no-serve]
 """
 from __future__ import annotations
 
@@ -50,8 +51,8 @@ def parse():
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-suite", action="store_true",
                     help="skip timing gamma_2 queries (plain per-query path vs batched)")
-    ap.add_argument("--serve", action="store_true",
-                    help="also run the serving stream (about two minutes)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving stream (about two minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy before the product, as "
                          "the reference point for HBM byte counters")
@@ -173,19 +174,19 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
-    if not args.no_suite or args.serve:
+    if not args.no_suite or not args.no_serve:
         del dA, dB, dC
         torch.cuda.empty_cache()
     if not args.no_suite:
         line["queries"] = query_suite(tp, synth)
         line["recurrence"] = recurrence_suite(tp)
-    if args.serve:
+    if not args.no_serve:
         line["serving"] = serve_suite(tp, synth)
     print(json.dumps(line), flush=True)
 
 
 # Total running time of the paper's whole pipeline (50 powers, Algorithms 3,
-# 4 and 5) in its fastest version, by path order (Table 7), in seconds.
+# 4 and 5) in its fastest version, by path order (Table 5), in seconds.
 PAPER_TOTAL_S = {8: 0.6, 9: 3.5, 10: 32.5, 11: 6 * 60 + 32, 12: 3600 + 29 * 60 + 58}
 
 
@@ -209,29 +210,45 @@ def recurrence_suite(tp):
 
 def serve_suite(tp, synth, count=2000):
     """Serving: a Poisson stream of `count` queries, n in 6..12 weighted by
-    2^-(n-6), m uniform in 3..500 (seed 0), on one server (resident powers in
-    HBM, memory admission, continuous batching, n = 12 in a sweep lane).
+    2^-(n-6), m uniform in 3..500 (seed 0), on one server: two batch contexts
+    (two waves in flight) for n <= 9 and resident compact lanes for n = 10..12,
+    admission by HBM.
 
-    saturation: every query submitted at once (cold server, then again warm);
-    replay: the stream at 70 % of the warm saturation rate, p50/p99 latency;
+    saturation: every query submitted at once, on a cold server (nothing
+    resident), then again warm (the powers the first pass left resident);
+    replay: the stream at 70 % of the warm saturation rate, p50/p99 latency
+    over all queries and per n;
     plain: tp_tropical_power_trace one query at a time, estimated as the mean
     time of a stratified sample per n times that n's count in the stream
-    (answers of the sample are compared with the served ones)."""
+    (answers of the sample are compared with the served ones); served vs
+    plain from the cold and from the warm pass."""
+    import numpy as np
     import torch
 
     from paper_2409_17688_amd import serve
     free, _ = torch.cuda.mem_get_info()
     budget = max(8 << 30, free - (48 << 30))
     unit = synth.serve_stream(seed=0, count=count, qps=1.0)
-    ex = serve.GpuExecutor(budget)
+    ex = serve.GpuExecutor(budget, slots=2)
     srv = serve.Server(ex, max_wave=1024)
-    out = {"queries": count, "budget_bytes": int(budget)}
+    out = {"queries": count, "budget_bytes": int(budget), "slots": ex.nslots,
+           "lane_orders": sorted(srv.lane_n)}
+
+    def lat_stats(reqs, prefix):
+        lat = [r.latency for r in reqs]
+        by_n = {}
+        for r in reqs:
+            by_n.setdefault(r.n, []).append(r.latency)
+        return {f"{prefix}_p50_ms": round(serve.percentile(lat, 50) * 1e3, 2),
+                f"{prefix}_p99_ms": round(serve.percentile(lat, 99) * 1e3, 2),
+                f"{prefix}_p99_ms_by_n": {str(n): round(serve.percentile(v, 99) * 1e3, 1)
+                                          for n, v in sorted(by_n.items())}}
     try:
         def burst():
             t0 = time.perf_counter()
-            reqs = [srv.submit(n, m) for _, n, m in unit]
+            reqs = [srv.submit(n, m, t_arrive=t0) for _, n, m in unit]
             for r in reqs:
-                r.wait(600)
+                r.wait(900)
             return reqs, time.perf_counter() - t0
 
         reqs, t_cold = burst()
@@ -240,7 +257,11 @@ def serve_suite(tp, synth, count=2000):
         if bad:
             print(f"serving failed: {bad[0].n} {bad[0].m} {bad[0].error}", file=sys.stderr)
             sys.exit(1)
-        _, t_warm = burst()
+        out.update(lat_stats(reqs, "cold_burst"))
+        reqs, t_warm = burst()
+        if any(r.status != serve.TP_OK or r.gamma2 != served[(r.n, r.m)] for r in reqs):
+            print("serving: warm pass differs from the cold pass", file=sys.stderr)
+            sys.exit(1)
         qps = 0.7 * count / t_warm
         t0 = time.perf_counter()
         reqs = []
@@ -250,28 +271,29 @@ def serve_suite(tp, synth, count=2000):
                 time.sleep(delay)
             reqs.append(srv.submit(n, m))
         for r in reqs:
-            r.wait(600)
+            r.wait(900)
         t_replay = time.perf_counter() - t0
-        lat = [r.latency for r in reqs]
+        if any(r.status != serve.TP_OK or r.gamma2 != served[(r.n, r.m)] for r in reqs):
+            print("serving: replay differs from the cold pass", file=sys.stderr)
+            sys.exit(1)
         out.update({"saturation_qps_cold": round(count / t_cold, 1),
                     "saturation_qps_warm": round(count / t_warm, 1),
                     "replay_qps": round(qps, 1),
-                    "replay_p50_ms": round(serve.percentile(lat, 50) * 1e3, 2),
-                    "replay_p99_ms": round(serve.percentile(lat, 99) * 1e3, 2),
-                    "replay_seconds": round(t_replay, 1),
-                    "waves": srv.waves,
-                    "resident_bytes": ex.resident_bytes()})
-        by_n = {}
-        for r in reqs:
-            by_n.setdefault(r.n, []).append(r.latency)
-        out["p99_ms_by_n"] = {str(n): round(serve.percentile(v, 99) * 1e3, 1)
-                              for n, v in sorted(by_n.items())}
+                    "replay_seconds": round(t_replay, 1)})
+        out.update(lat_stats(reqs, "replay"))
+        out.update({"waves": srv.waves, "max_waves_in_flight": srv.max_in_flight,
+                    "resident_bytes": int(ex.resident_bytes()),
+                    "lanes": {str(l.n): {"level": l.level, "panels": len(l.panels),
+                                         "trace_answers": l.trace_answers,
+                                         "plain_answers": l.plain_answers,
+                                         "reserved_bytes": int(l.reserved_bytes)}
+                              for l in ex.lanes}})
     finally:
         srv.close()
         ex.close()
     torch.cuda.empty_cache()
     # plain path on a stratified sample
-    rng = __import__("numpy").random.default_rng(1)
+    rng = np.random.default_rng(1)
     counts, plain_total = {}, 0.0
     for _, n, m in unit:
         counts[n] = counts.get(n, 0) + 1
@@ -288,7 +310,8 @@ def serve_suite(tp, synth, count=2000):
                 sys.exit(1)
         plain_total += (time.perf_counter() - t0) / len(pick) * cnt
     out["plain_qps_estimate"] = round(count / plain_total, 2)
-    out["served_vs_plain"] = round((count / t_warm) / (count / plain_total), 1)
+    out["served_vs_plain_cold"] = round((count / t_cold) / (count / plain_total), 1)
+    out["served_vs_plain_warm"] = round((count / t_warm) / (count / plain_total), 1)
     # recurrence mode, reported apart from the served path: one recurrence of
     # the powers per path order of the stream (K = 50), then every query from
     # Theorem 3's solution on the host

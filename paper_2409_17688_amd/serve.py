@@ -1,29 +1,44 @@
 """Serving gamma_2(P_n x C_m) queries on one GPU with continuous batching.
 
-Queries (n, m) arrive at any time.  They are answered from powers of the
-state matrix A(D_n) kept resident in HBM (Theorem 2: gamma_2 is the trace of
-A^a x A^b for any a + b = m):
+Queries (n, m) arrive at any time and are answered from powers of the state
+matrix A(D_n) kept resident in HBM (Theorem 2: gamma_2 is the least diagonal
+entry of A^m, i.e. the trace of A^a x A^b for any a + b = m).
 
-* path orders below ``sweep_n`` go to a batch context (``tp_ctx_*``): the
-  scheduler thread collects whatever is pending into a *wave*, admits queries
-  in arrival order while the powers they would add fit in the context's HBM
-  budget (evicting the resident powers of the least recently used path orders
-  when the head of the queue does not fit), and runs the wave as one
-  persistent launch.  Queries that arrive while a wave runs join the next
-  wave as soon as it ends, so the device goes from one wave to the next
-  without idling; inside a wave all admitted queries' work overlaps.
-* path orders from ``sweep_n`` on (n = 12 by default: one power is 5.6 GB and
-  a dense product takes seconds) go to a *sweep lane*: one shared chain
-  A^k = A x A^(k-1) (Algorithm 2) advanced on its own stream with three
-  buffers; every query with ceil(m/2) = k is answered by one trace of a
-  product when the chain passes level k (floor(m/2) is k or k - 1).  Queries
-  for a level the chain has passed wait for the next sweep.  The lane runs
-  concurrently with the waves on the device.
+* Path orders below the lane orders go to batch contexts (``tp_ctx_*``).
+  The executor holds ``slots`` contexts, each with its own stream and worker
+  thread, so up to ``slots`` waves are in flight on the device at once.  A
+  path order's resident powers live in one context (its *owner*); the
+  scheduler forms a wave for every idle slot from the pending queries whose
+  path order that slot owns or nobody owns yet, in arrival order, while the
+  powers they would add fit in the HBM budget (what every context and lane
+  holds plus what the waves in flight may still add).  When the oldest
+  admissible query does not fit, the least recently used path orders of idle
+  slots are released one at a time until it does; if it still does not fit
+  the wave stops there, so later queries never overtake it (no starvation);
+  a query that cannot fit even then, with nothing else in flight, fails with
+  TP_ENOMEM.  A query that arrives while its owner's wave runs joins that
+  slot's next wave; one for another path order is admitted into the other
+  slot at once and overlaps the running wave on the device.
+* The lane orders (n = 10, 11, 12 by default: one power is 0.15 to 5.6 GB in
+  16 bits) each get a *resident lane* on its own stream and thread.  It keeps
+  shared-base compact powers (8-bit residuals over one base, half the bytes
+  of 16 bits): whole powers A^r for r = 3..c+2 (the babies) and, for every
+  j >= 1, the columns S of A^(jc) (the giant panels), S the states with at
+  most k zeros, chained from the columns S of A by the sparse left step.  A
+  query is then one trace of a product: of two babies when m <= 2(c+2), else
+  of the rows S of A^r with the panel of A^(jc), m = jc + r, read on the
+  diagonal entries of S.  The second is exact whenever the value v found has
+  floor(v/m) <= k: every optimal closed walk of length m passes through a
+  state with at most floor(gamma_2/m) zeros (its label is the sum of the zero
+  counts of the m states it visits, Section 2.2), and rotating the cycle
+  starts it there.  Otherwise, and for m outside the lane's reach, the lane
+  answers by the plain per-query path.  Panels are computed as queries need
+  them; once built they stay, so later queries cost one trace.
 
 A failing wave fails only its own queries; the loop keeps serving.  The
 scheduler does not depend on the GPU: any object with the executor methods
 used below can drive it (the tests use fakes to force admission limits,
-errors and cancellation).
+errors, overlap and cancellation).
 """
 from __future__ import annotations
 
@@ -38,6 +53,8 @@ TP_ENOMEM = -2
 TP_EOVERFLOW = -3
 TP_EHIP = -4
 TP_ECANCELED = -6
+
+LANE_ORDERS = (10, 11, 12)
 
 
 @dataclass
@@ -79,71 +96,55 @@ def validate(n: int, m: int):
     return None
 
 
-class GpuExecutor:
-    """Runs waves on a batch context and sweep lanes on their own streams."""
-
-    def __init__(self, hbm_budget_bytes: int, tuning: dict | None = None):
-        import torch
-
-        from . import _lib as tp
-        self.tp = tp
-        self.torch = torch
-        self.budget = int(hbm_budget_bytes)
-        self.ctx = tp.tp_ctx_create(self.budget)
-        self.stream = torch.cuda.Stream()
-        for key, val in (tuning or {}).items():
-            param, n = key
-            tp.tp_ctx_set_param(self.ctx, param + n, val)
-
-    def need_bytes(self, ns, ms) -> int:
-        return self.tp.tp_ctx_need_bytes(self.ctx, ns, ms)
-
-    def resident_bytes(self) -> int:
-        return self.tp.tp_ctx_resident_bytes(self.ctx)
-
-    def release(self, n: int) -> None:
-        self.tp.tp_ctx_release(self.ctx, n, stream=self.stream)
-
-    def run_wave(self, ns, ms):
-        with self.torch.cuda.stream(self.stream):
-            out = self.tp.tp_batch_power_trace(self.ctx, ns, ms, stream=self.stream)
-            self.tp.tp_ctx_check(self.ctx, stream=self.stream)
-            return out.cpu().tolist()
-
-    def make_lane(self, n: int) -> "SweepLane":
-        return SweepLane(n, self.tp, self.torch)
-
-    def close(self) -> None:
-        if self.ctx:
-            self.torch.cuda.synchronize()
-            self.tp.tp_ctx_destroy(self.ctx)
-            self.ctx = None
+def _ld(cols: int) -> int:
+    return max((cols + 63) // 64 * 64, 64)
 
 
-class SweepLane:
-    """One shared power chain for path order n on its own stream."""
+class ResidentLane:
+    """Resident shared-base compact powers of one path order n on their own
+    stream and thread; each query is answered by one trace of a product once
+    the powers it needs exist (see the module docstring)."""
 
-    def __init__(self, n: int, tp, torch):
+    def __init__(self, n: int, tp, torch, c: int = 10, m_cap: int = 512,
+                 max_zeros: int | None = None):
+        if c < 3:
+            raise ValueError("the baby powers start at A^3: c >= 3")
         self.n, self.tp, self.torch = n, tp, torch
+        self.c, self.m_cap = c, m_cap
+        self.k = (n + 2) // 3 if max_zeros is None else max_zeros
         self.N = tp.tp_state_dim(n)
-        ld = (self.N + 63) // 64 * 64
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
-            self.bufs = [torch.empty((self.N, ld), dtype=torch.uint16, device="cuda")[:, :self.N]
-                         for _ in range(3)]
-        tp.tp_state_nnz(n)  # builds (and caches) the state's sparse forms
+            self.S = tp.tp_state_select(n, self.k, stream=self.stream)
+        self.count = int(self.S.numel())
+        self.J = max(0, (m_cap - 3) // c)  # panels j = 1..J serve m <= m_cap
+        N, ld, lds = self.N, _ld(self.N), _ld(self.count)
+        # steady-state bytes: babies, panels and two chain buffers (the build
+        # also holds three 16-bit powers for a moment)
+        self.reserved_bytes = c * N * ld + (self.J + 2) * N * lds + 3 * 2 * N * ld
+        self.babies: dict[int, tuple] = {}
+        self.panels: dict[int, tuple] = {}
+        self.level = 0          # highest power whose columns S the chain holds
+        self.chain = None       # (x8, base) of that power
+        self.spare = None       # (x8, base) buffer the next step writes
+        self.broken = ""        # set when a power cannot be held compact
         self.lock = threading.Condition()
-        self.pending = collections.defaultdict(list)  # level a -> requests
+        self.pending: list[Request] = []
         self.stop = False
-        self.sweeps = 0
-        self.levels = 0
-        self.thread = threading.Thread(target=self._run, name=f"sweep-n{n}", daemon=True)
+        self.plain_answers = 0
+        self.trace_answers = 0
+        self.thread = threading.Thread(target=self._run, name=f"lane-n{n}", daemon=True)
         self.thread.start()
 
-    def submit(self, req: Request) -> None:
+    # ------------------------------------------------------------- public --
+
+    def submit(self, req: Request) -> bool:
         with self.lock:
-            self.pending[(req.m + 1) // 2].append(req)
+            if self.stop:
+                return False
+            self.pending.append(req)
             self.lock.notify()
+        return True
 
     def close(self) -> None:
         with self.lock:
@@ -151,84 +152,241 @@ class SweepLane:
             self.lock.notify()
         self.thread.join()
         with self.lock:
-            for reqs in self.pending.values():
-                for r in reqs:
-                    r._finish(status=TP_ECANCELED, error="server closed")
+            for r in self.pending:
+                r._finish(status=TP_ECANCELED, error="server closed")
             self.pending.clear()
 
-    def _answer(self, k: int, X: dict) -> None:
-        with self.lock:
-            reqs = self.pending.pop(k, [])
-        if not reqs:
-            return
-        tp, torch = self.tp, self.torch
-        outs = []
-        with torch.cuda.stream(self.stream):
-            for r in reqs:
+    # --------------------------------------------------------------- plan --
+
+    def _plan(self, m: int):
+        """('babies', a, b) | ('panel', r, j) | ('plain',)."""
+        c = self.c
+        if self.broken or m < 6 or m > self.m_cap:
+            return ("plain",)
+        if m <= 2 * (c + 2):
+            return ("babies", (m + 1) // 2, m // 2)
+        j = (m - 3) // c
+        return ("panel", m - j * c, j)
+
+    # -------------------------------------------------------------- build --
+
+    def _u8(self, cols):
+        return self.torch.empty((self.N, _ld(cols)), dtype=self.torch.uint8,
+                                device="cuda")[:, :cols]
+
+    def _base(self):
+        return self.torch.zeros(2, dtype=self.torch.int32, device="cuda")
+
+    def _build_babies(self):
+        tp, torch, n, N, s = self.tp, self.torch, self.n, self.N, self.stream
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        A = torch.empty((N, _ld(N)), dtype=torch.uint16, device="cuda")[:, :N]
+        B = torch.empty_like(A)
+        tp.tp_build_state_matrix(n, tp.TP_U16, out=A, stream=s)
+        tp.tp_state_left_mul(n, A, B, stream=s)          # A^2
+        tp.tp_state_left_mul(n, B, A, stream=s)          # A^3
+        x, b = self._u8(N), self._base()
+        tp.tp_compact_shared_from_u16(A, x, b, st, stream=s)
+        del A, B
+        self.babies[3] = (x, b)
+        for r in range(4, self.c + 3):
+            y, by = self._u8(N), self._base()
+            tp.tp_compact_shared_step(n, x, b, N, y, by, st, stream=s)
+            self.babies[r] = (y, by)
+            x, b = y, by
+        # the panel chain starts at the columns S of A^3
+        P = torch.empty((N, _ld(self.count)), dtype=torch.uint16, device="cuda")[:, :self.count]
+        Q = torch.empty_like(P)
+        tp.tp_build_state_columns(n, self.S, out=P, stream=s)
+        tp.tp_state_left_mul(n, P, Q, stream=s)
+        tp.tp_state_left_mul(n, Q, P, stream=s)
+        x, b = self._u8(self.count), self._base()
+        tp.tp_compact_shared_from_u16(P, x, b, st, stream=s)
+        del P, Q
+        self.chain, self.spare, self.level = (x, b), (self._u8(self.count), self._base()), 3
+        self.status = st
+        s.synchronize()
+        if int(st.item()) != 0:
+            self.broken = "a power of A(D_n) did not fit the compact form"
+
+    def _advance(self):
+        """One chain step of the panel; keeps it when the level is jc."""
+        tp, s = self.tp, self.stream
+        (x, b), (y, by) = self.chain, self.spare
+        tp.tp_compact_shared_step(self.n, x, b, self.count, y, by, self.status, stream=s)
+        self.level += 1
+        if self.level % self.c == 0:
+            self.panels[self.level // self.c] = (y, by)
+            self.chain, self.spare = (y, by), (self._u8(self.count), self._base())
+        else:
+            self.chain, self.spare = (y, by), (x, b)
+
+    # ------------------------------------------------------------- answer --
+
+    def _ready(self, plan) -> bool:
+        return plan[0] != "panel" or plan[2] in self.panels
+
+    def _answer(self, reqs):
+        tp, torch, s = self.tp, self.torch, self.stream
+        outs = torch.empty(max(len(reqs), 1), dtype=torch.int32, device="cuda")
+        plans = []
+        with torch.cuda.stream(s):
+            for i, r in enumerate(reqs):
                 r.t_start = r.t_start or time.perf_counter()
-                b = r.m - k
-                outs.append(tp.tp_trace_of_product(X[k], X[b], stream=self.stream))
-            vals = [int(o.item()) for o in outs]
-        for r, v in zip(reqs, vals):
-            r._finish(gamma2=v)
+                p = self._plan(r.m)
+                plans.append(p)
+                if p[0] == "babies":
+                    (xa, ba), (xb, bb) = self.babies[p[1]], self.babies[p[2]]
+                    tp.tp_compact_shared_select_trace(xa, ba, xb, bb, None, out=outs[i:i + 1],
+                                                      stream=s)
+                elif p[0] == "panel":
+                    (xr, br), (g, bg) = self.babies[p[1]], self.panels[p[2]]
+                    tp.tp_compact_shared_select_trace(xr, br, g, bg, self.S, out=outs[i:i + 1],
+                                                      stream=s)
+            vals = outs.cpu().tolist()
+        for r, p, v in zip(reqs, plans, vals):
+            if p[0] == "panel" and v // r.m > self.k:
+                p = ("plain",)  # the pruned diagonal cannot vouch for this value
+            if p[0] == "plain":
+                with torch.cuda.stream(s):
+                    v = tp.tp_tropical_power_trace(r.n, r.m, stream=s)
+                self.plain_answers += 1
+            else:
+                self.trace_answers += 1
+            r._finish(gamma2=int(v))
 
     def _run(self) -> None:
-        tp, torch = self.tp, self.torch
+        built = False
         while True:
             with self.lock:
                 while not self.pending and not self.stop:
                     self.lock.wait()
                 if self.stop:
                     return
-            # one sweep: level 1 upwards while some pending query needs a level ahead
-            self.sweeps += 1
             try:
-                with torch.cuda.stream(self.stream):
-                    X = {1: tp.tp_build_state_matrix(self.n, tp.TP_U16, out=self.bufs[1],
-                                                     stream=self.stream)}
-                    k = 1
-                    while True:
-                        self._answer(k, X)
-                        with self.lock:
-                            ahead = [a for a in self.pending if a > k]
-                            if self.stop:
-                                return
-                        if not ahead:
-                            break
-                        Y = self.bufs[(k + 1) % 3]
-                        tp.tp_state_left_mul(self.n, X[k], Y, stream=self.stream)
-                        k += 1
-                        self.levels += 1
-                        X[k] = Y
-                        X.pop(k - 2, None)
+                if not built:
+                    with self.torch.cuda.stream(self.stream):
+                        self._build_babies()
+                    built = True
+                while True:
+                    with self.lock:
+                        if self.stop:
+                            return
+                        ready = [r for r in self.pending if self._ready(self._plan(r.m))]
+                        self.pending = [r for r in self.pending if r not in ready]
+                        need = [self._plan(r.m)[2] for r in self.pending]
+                    if ready:
+                        self._answer(ready)
+                    if not need:
+                        break
+                    with self.torch.cuda.stream(self.stream):
+                        self._advance()
+                        if self.level % self.c == 0:
+                            self.stream.synchronize()
+                            if int(self.status.item()) != 0:
+                                self.broken = "a power of A(D_n) did not fit the compact form"
             except Exception as e:  # fail what is waiting, keep the lane alive
                 with self.lock:
-                    failed = [r for reqs in self.pending.values() for r in reqs]
-                    self.pending.clear()
+                    failed, self.pending = self.pending, []
                 for r in failed:
-                    r._finish(status=TP_EHIP, error=str(e))
+                    r._finish(status=getattr(e, "status", TP_EHIP), error=str(e))
+
+
+class GpuExecutor:
+    """Batch contexts (one stream each) for the waves, resident lanes for the
+    lane orders."""
+
+    def __init__(self, hbm_budget_bytes: int, slots: int = 2, tuning: dict | None = None,
+                 lane_c: int = 10, lane_m_cap: int = 512):
+        import torch
+
+        from . import _lib as tp
+        self.tp = tp
+        self.torch = torch
+        self.budget = int(hbm_budget_bytes)
+        self.nslots = int(slots)
+        self.ctxs = [tp.tp_ctx_create(self.budget) for _ in range(self.nslots)]
+        self.streams = [torch.cuda.Stream() for _ in range(self.nslots)]
+        self._resident = [0] * self.nslots  # bytes per context, read after each change
+        self.lanes: list[ResidentLane] = []
+        self.lane_c, self.lane_m_cap = lane_c, lane_m_cap
+        # each context's persistent launch takes at most its share of the
+        # chip's workgroup slots (4 per CU at the batch kernel's register
+        # budget), so a long wave on one slot leaves room for the other's
+        cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        share = max(8, cus * 4 // self.nslots) if self.nslots > 1 else 0
+        for ctx in self.ctxs:
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_GRID, share)
+            for key, val in (tuning or {}).items():
+                param, n = key
+                tp.tp_ctx_set_param(ctx, param + n, val)
+
+    def need_bytes(self, slot, ns, ms) -> int:
+        return self.tp.tp_ctx_need_bytes(self.ctxs[slot], ns, ms)
+
+    def resident_bytes(self) -> int:
+        # cached per context: asking a context whose wave runs would wait for it
+        return sum(self._resident) + sum(l.reserved_bytes for l in self.lanes)
+
+    def release(self, slot: int, n: int) -> None:
+        self.tp.tp_ctx_release(self.ctxs[slot], n, stream=self.streams[slot])
+        self._resident[slot] = self.tp.tp_ctx_resident_bytes(self.ctxs[slot])
+
+    def run_wave(self, slot: int, ns, ms):
+        ctx, st = self.ctxs[slot], self.streams[slot]
+        try:
+            with self.torch.cuda.stream(st):
+                out = self.tp.tp_batch_power_trace(ctx, ns, ms, stream=st)
+                self.tp.tp_ctx_check(ctx, stream=st)
+                return out.cpu().tolist()
+        finally:
+            self._resident[slot] = self.tp.tp_ctx_resident_bytes(ctx)
+
+    def make_lane(self, n: int) -> ResidentLane:
+        lane = ResidentLane(n, self.tp, self.torch, c=self.lane_c, m_cap=self.lane_m_cap)
+        self.lanes.append(lane)
+        return lane
+
+    def close(self) -> None:
+        self.torch.cuda.synchronize()
+        for ctx in self.ctxs:
+            if ctx:
+                self.tp.tp_ctx_destroy(ctx)
+        self.ctxs = []
+        self.lanes = []
 
 
 class Server:
     """Continuous-batching gamma_2 server.
 
-    executor: a GpuExecutor (or any object with need_bytes, resident_bytes,
-    release, run_wave, make_lane and a ``budget`` attribute).
+    executor: a GpuExecutor, or any object with ``budget``, ``nslots``,
+    need_bytes(slot, ns, ms), resident_bytes(), release(slot, n),
+    run_wave(slot, ns, ms) and make_lane(n).
     max_wave: most queries admitted into one wave.
-    sweep_n: path orders >= sweep_n use a sweep lane (None: never).
+    lane_n: path orders served by resident lanes instead of waves.
     """
 
-    def __init__(self, executor, max_wave: int = 1024, sweep_n: int | None = 12):
+    def __init__(self, executor, max_wave: int = 1024, lane_n=LANE_ORDERS):
         self.ex = executor
         self.max_wave = max_wave
-        self.sweep_n = sweep_n
+        self.lane_n = frozenset(lane_n or ())
+        self.nslots = int(getattr(executor, "nslots", 1))
         self.cv = threading.Condition()
         self.pending: collections.deque[Request] = collections.deque()
-        self.lanes: dict[int, SweepLane] = {}
-        self.last_use: dict[int, float] = {}
+        self.lanes: dict[int, object] = {}
+        self.owner: dict[int, int] = {}        # path order -> slot holding its powers
+        self.last_use: dict[int, float] = {}   # path order -> last admission
+        self.busy = [False] * self.nslots
+        self.reserved = [0] * self.nslots      # bytes the wave in flight may add
+        self.jobs: list[list[Request] | None] = [None] * self.nslots
         self.waves = 0
         self.wave_sizes: list[int] = []
+        self.max_in_flight = 0
         self.stop = False
+        self.workers = [threading.Thread(target=self._worker, args=(s,), daemon=True,
+                                         name=f"tropical-slot{s}") for s in range(self.nslots)]
+        for w in self.workers:
+            w.start()
         self.thread = threading.Thread(target=self._loop, name="tropical-scheduler", daemon=True)
         self.thread.start()
 
@@ -240,19 +398,23 @@ class Server:
         if bad:
             req._finish(status=bad[0], error=bad[1])
             return req
-        if self.sweep_n is not None and req.n >= self.sweep_n:
-            with self.cv:
-                lane = self.lanes.get(req.n)
-                if lane is None:
-                    lane = self.lanes[req.n] = self.ex.make_lane(req.n)
-            lane.submit(req)
-            return req
         with self.cv:
             if self.stop:
                 req._finish(status=TP_ECANCELED, error="server closed")
                 return req
+            if req.n in self.lane_n:
+                lane = self.lanes.get(req.n)
+                if lane is None:
+                    try:
+                        lane = self.lanes[req.n] = self.ex.make_lane(req.n)
+                    except Exception as e:
+                        req._finish(status=getattr(e, "status", TP_EHIP), error=str(e))
+                        return req
+                if not lane.submit(req):
+                    req._finish(status=TP_ECANCELED, error="server closed")
+                return req
             self.pending.append(req)
-            self.cv.notify()
+            self.cv.notify_all()
         return req
 
     def cancel(self, req: Request) -> bool:
@@ -268,8 +430,10 @@ class Server:
     def close(self) -> None:
         with self.cv:
             self.stop = True
-            self.cv.notify()
+            self.cv.notify_all()
         self.thread.join()
+        for w in self.workers:
+            w.join()
         for lane in self.lanes.values():
             lane.close()
         with self.cv:
@@ -278,66 +442,111 @@ class Server:
 
     # ---------------------------------------------------------- scheduler --
 
-    def _admit(self, cands):
-        """Largest arrival-order prefix-compatible set that fits the budget."""
-        admitted, deferred = [], []
-        for r in cands:
-            trial = admitted + [r]
-            need = self.ex.need_bytes([q.n for q in trial], [q.m for q in trial])
-            if self.ex.resident_bytes() + need <= self.ex.budget:
-                admitted.append(r)
-            else:
-                deferred.append(r)
-        return admitted, deferred
+    def _free_bytes(self, planned: int) -> int:
+        return self.ex.budget - self.ex.resident_bytes() - sum(self.reserved) - planned
 
-    def _evict_for(self, keep):
-        """Releases least recently used path orders not in keep; True if any."""
-        victims = sorted((t, n) for n, t in self.last_use.items() if n not in keep)
-        for _, n in victims:
-            self.ex.release(n)
-            del self.last_use[n]
-        return bool(victims)
+    def _evict_one(self, keep) -> bool:
+        """Releases the least recently used path order held by an idle slot
+        and not in keep; False when there is none."""
+        cands = [(t, n) for n, t in self.last_use.items()
+                 if n not in keep and n in self.owner and not self.busy[self.owner[n]]]
+        if not cands:
+            return False
+        _, n = min(cands)
+        self.ex.release(self.owner[n], n)
+        del self.owner[n]
+        del self.last_use[n]
+        return True
+
+    def _form_waves(self) -> bool:
+        """Admits pending queries into waves for the idle slots (caller holds
+        cv); True when a wave was handed to a worker."""
+        idle = [s for s in range(self.nslots) if not self.busy[s]]
+        if not idle or not self.pending:
+            return False
+        plans = {s: [] for s in idle}
+        ms_of = {s: {} for s in idle}      # n -> m values planned on s
+        need_of = {s: {} for s in idle}    # n -> bytes those add on s
+        slot_of: dict[int, int] = {}       # unowned n -> slot chosen this round
+        planned = 0
+        admitted = set()
+        for r in list(self.pending):
+            s = self.owner.get(r.n, slot_of.get(r.n))
+            if s is None:
+                s = min(idle, key=lambda x: len(plans[x]))
+            if self.busy[s]:
+                continue  # joins its owner's next wave
+            if len(plans[s]) >= self.max_wave:
+                continue
+            ms = ms_of[s].get(r.n, []) + [r.m]
+            delta = self.ex.need_bytes(s, [r.n] * len(ms), ms) - need_of[s].get(r.n, 0)
+            keep = {q.n for p in plans.values() for q in p} | {r.n}
+            while delta > self._free_bytes(planned) and self._evict_one(keep):
+                pass
+            if delta > self._free_bytes(planned):
+                if not any(plans.values()) and not any(self.busy):
+                    # even with everything else released it does not fit
+                    self.pending.remove(r)
+                    r._finish(status=TP_ENOMEM,
+                              error=f"needs more than the {self.ex.budget}-byte budget")
+                    continue
+                break  # later queries wait behind it
+            plans[s].append(r)
+            ms_of[s][r.n] = ms
+            need_of[s][r.n] = need_of[s].get(r.n, 0) + delta
+            slot_of[r.n] = s
+            planned += delta
+            admitted.add(id(r))
+        if not admitted:
+            return False
+        self.pending = collections.deque(r for r in self.pending if id(r) not in admitted)
+        t0 = time.perf_counter()
+        for s, plan in plans.items():
+            if not plan:
+                continue
+            for r in plan:
+                r.t_start = t0
+                self.owner[r.n] = s
+                self.last_use[r.n] = t0
+            self.busy[s] = True
+            self.reserved[s] = sum(need_of[s].values())
+            self.jobs[s] = plan
+            self.waves += 1
+            self.wave_sizes.append(len(plan))
+        self.max_in_flight = max(self.max_in_flight, sum(self.busy))
+        self.cv.notify_all()
+        return True
 
     def _loop(self) -> None:
-        while True:
-            with self.cv:
-                while not self.pending and not self.stop:
-                    self.cv.wait()
-                if self.stop and not self.pending:
-                    return
+        with self.cv:
+            while True:
                 if self.stop:
                     return
-                cands = [self.pending.popleft()
-                         for _ in range(min(self.max_wave, len(self.pending)))]
-            admitted, deferred = self._admit(cands)
-            if not admitted and self._evict_for({r.n for r in cands}):
-                admitted, deferred = self._admit(cands)
-            if not admitted and self._evict_for(set()):
-                admitted, deferred = self._admit(cands)
-            if not admitted:
-                # even an empty context cannot hold what the head query needs
-                head = deferred.pop(0)
-                head._finish(status=TP_ENOMEM,
-                             error=f"needs more than the {self.ex.budget}-byte budget")
+                if not self._form_waves():
+                    self.cv.wait()
+
+    def _worker(self, s: int) -> None:
+        while True:
             with self.cv:
-                self.pending.extendleft(reversed(deferred))
-            if not admitted:
-                continue
-            t0 = time.perf_counter()
-            for r in admitted:
-                r.t_start = t0
-                self.last_use[r.n] = t0
-            self.waves += 1
-            self.wave_sizes.append(len(admitted))
+                while self.jobs[s] is None and not self.stop:
+                    self.cv.wait()
+                if self.jobs[s] is None:
+                    return
+                plan = self.jobs[s]
             try:
-                vals = self.ex.run_wave([r.n for r in admitted], [r.m for r in admitted])
+                vals = self.ex.run_wave(s, [r.n for r in plan], [r.m for r in plan])
             except Exception as e:  # this wave fails; the server keeps going
                 code = getattr(e, "status", TP_EHIP)
-                for r in admitted:
+                for r in plan:
                     r._finish(status=code, error=str(e))
-                continue
-            for r, v in zip(admitted, vals):
-                r._finish(gamma2=int(v))
+            else:
+                for r, v in zip(plan, vals):
+                    r._finish(gamma2=int(v))
+            with self.cv:
+                self.jobs[s] = None
+                self.busy[s] = False
+                self.reserved[s] = 0
+                self.cv.notify_all()
 
 
 def percentile(values, q: float) -> float:
