@@ -40,6 +40,11 @@ KERNEL_SHAPES = {0: "128,128,32,8,8,4", 1: "128,256,32,8,16,3", 2: "256,128,32,1
                  3: "64,64,32,4,4,4", 4: "256,256,32,16,16,2"}
 
 
+def note(msg):
+    """A progress line on stderr as each leg ends (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,16 +177,21 @@ def main():
                      "kernel": kernel + (f" x{ksplit} K slices" if ksplit > 1 else "")},
         "kernel_ms": round(avg_kernel_s * 1e3, 3),
     }
+    note(f"product timed: {avg_kernel_s * 1e3:.3f} ms per launch")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+        note("cpu baseline done")
     if not args.no_suite or not args.no_serve:
         del dA, dB, dC
         torch.cuda.empty_cache()
     if not args.no_suite:
         line["queries"] = query_suite(tp, synth)
+        note("query suite done")
         line["recurrence"] = recurrence_suite(tp)
+        note("recurrence suite done")
     if not args.no_serve:
         line["serving"] = serve_suite(tp, synth)
+        note("serving done")
     print(json.dumps(line), flush=True)
 
 
@@ -252,6 +262,7 @@ def serve_suite(tp, synth, count=2000):
             return reqs, time.perf_counter() - t0
 
         reqs, t_cold = burst()
+        note(f"serving: cold pass {t_cold:.1f} s")
         served = {(r.n, r.m): r.gamma2 for r in reqs}
         bad = [r for r in reqs if r.status != serve.TP_OK]
         if bad:
@@ -259,6 +270,7 @@ def serve_suite(tp, synth, count=2000):
             sys.exit(1)
         out.update(lat_stats(reqs, "cold_burst"))
         reqs, t_warm = burst()
+        note(f"serving: warm pass {t_warm:.1f} s")
         if any(r.status != serve.TP_OK or r.gamma2 != served[(r.n, r.m)] for r in reqs):
             print("serving: warm pass differs from the cold pass", file=sys.stderr)
             sys.exit(1)
@@ -273,6 +285,7 @@ def serve_suite(tp, synth, count=2000):
         for r in reqs:
             r.wait(900)
         t_replay = time.perf_counter() - t0
+        note(f"serving: replay {t_replay:.1f} s")
         if any(r.status != serve.TP_OK or r.gamma2 != served[(r.n, r.m)] for r in reqs):
             print("serving: replay differs from the cold pass", file=sys.stderr)
             sys.exit(1)

@@ -8,8 +8,11 @@ The arithmetic lives in two plain C files compiled with gcc:
 
 * ``oracle.c``   -- correct words and arcs (Section 2.2), the state matrix
   (Algorithm 1), the (min,+) product (Section 1), the power chain
-  (Algorithm 2), gamma_2 as the diagonal minimum (Theorem 2, Algorithm 5) and
-  the recurrence search (Algorithms 3 and 4);
+  (Algorithm 2), gamma_2 as the diagonal minimum (Theorem 2, Algorithm 5),
+  the recurrence search (Algorithms 3 and 4) and the complementary
+  construction (columns that are copies of the cycle, an open walk along the
+  path by (min,+) vector-matrix products: the small-cycle / any-path problem
+  Section 1 names, on the general construction of Section 2.1);
 * ``brute2dom.c`` -- exhaustive search for minimum 2-dominating sets straight
   from the definition (Section 1), used as an independent pin.
 
@@ -81,6 +84,22 @@ def _load():
     lib.oracle_apsp.restype = None
     lib.oracle_constant_difference.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_int32, i64p]
     lib.oracle_constant_difference.restype = ctypes.c_int
+    lib.oracle_is_correct_cyclic_word.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_is_correct_cyclic_word.restype = ctypes.c_int
+    lib.oracle_cyclic_words.argtypes = [ctypes.c_int, u32p]
+    lib.oracle_cyclic_words.restype = ctypes.c_int64
+    lib.oracle_cyclic_follows.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
+    lib.oracle_cyclic_follows.restype = ctypes.c_int
+    lib.oracle_cyclic_can_start.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_cyclic_can_start.restype = ctypes.c_int
+    lib.oracle_cyclic_can_end.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_cyclic_can_end.restype = ctypes.c_int
+    lib.oracle_cyclic_state_matrix.argtypes = [ctypes.c_int, ctypes.c_int32, i32p]
+    lib.oracle_cyclic_state_matrix.restype = ctypes.c_int64
+    lib.oracle_cyclic_boundary.argtypes = [ctypes.c_int, ctypes.c_int32, i32p, i32p]
+    lib.oracle_cyclic_boundary.restype = ctypes.c_int64
+    lib.oracle_path_gamma2_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int32, i32p]
+    lib.oracle_path_gamma2_sweep.restype = ctypes.c_int64
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
     lib.brute_is_2dominating.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
@@ -227,6 +246,69 @@ def constant_difference(X: np.ndarray, Y: np.ndarray, inf: int = INF16):
     b = ctypes.c_int64(0)
     ok = _load().oracle_constant_difference(X.size, _i32(X), _i32(Y), inf, ctypes.byref(b))
     return bool(ok), int(b.value)
+
+
+# -- columns that are copies of the cycle (small cycle, any path) -----------
+
+def cyclic_word_count(m: int) -> int:
+    """Number of correct cyclic words of length m (column C_m, m >= 3)."""
+    r = int(_load().oracle_cyclic_words(m, None))
+    if r < 0:
+        raise ValueError("the cycle order m must be in 3..16")
+    return r
+
+
+def cyclic_words(m: int) -> np.ndarray:
+    """Base-3 codes of the correct cyclic words, increasing."""
+    N = cyclic_word_count(m)
+    out = np.zeros(N, dtype=np.uint32)
+    _load().oracle_cyclic_words(m, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return out
+
+
+def is_correct_cyclic_word(m: int, code: int) -> bool:
+    return bool(_load().oracle_is_correct_cyclic_word(m, code))
+
+
+def cyclic_follows(m: int, q: int, p: int) -> bool:
+    """True when cyclic word p can follow cyclic word q along the path."""
+    return bool(_load().oracle_cyclic_follows(m, q, p))
+
+
+def cyclic_can_start(m: int, p: int) -> bool:
+    return bool(_load().oracle_cyclic_can_start(m, p))
+
+
+def cyclic_can_end(m: int, p: int) -> bool:
+    return bool(_load().oracle_cyclic_can_end(m, p))
+
+
+def cyclic_state_matrix(m: int, inf: int = INF16) -> np.ndarray:
+    """The column digraph's matrix for cyclic columns, N x N int32."""
+    N = cyclic_word_count(m)
+    A = np.empty((N, N), dtype=np.int32)
+    _load().oracle_cyclic_state_matrix(m, inf, _i32(A))
+    return A
+
+
+def cyclic_boundary(m: int, inf: int = INF16):
+    """(start, end) vectors of the open walk along the path, int32."""
+    N = cyclic_word_count(m)
+    s = np.empty(N, dtype=np.int32)
+    e = np.empty(N, dtype=np.int32)
+    _load().oracle_cyclic_boundary(m, inf, _i32(s), _i32(e))
+    return s, e
+
+
+def path_gamma2_sweep(m: int, nmax: int, inf: int = INF16) -> np.ndarray:
+    """g[n-1] = gamma_2(P_n x C_m) for n = 1..nmax, by the vector chain over
+    cyclic columns (start vector, then x <- x (x) A, end vector)."""
+    if nmax < 1:
+        raise ValueError("nmax must be at least 1")
+    cyclic_word_count(m)
+    g = np.empty(nmax, dtype=np.int32)
+    _load().oracle_path_gamma2_sweep(m, nmax, inf, _i32(g))
+    return g
 
 
 def threads() -> int:

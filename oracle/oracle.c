@@ -25,7 +25,11 @@
  *     semiring applied to another workload;
  *   - recurrence search (Algorithm 3) and its minimal start (Algorithm 4),
  *     with "A^i - A^j is constant" read as A^i = b x A^j exactly (same INF
- *     pattern, every finite difference equal to one b).
+ *     pattern, every finite difference equal to one b);
+ *   - the complementary construction: columns that are copies of the cycle,
+ *     the rules of Section 2.2 read around the cycle, an open walk along the
+ *     path with a start and an end vector, by (min,+) vector-matrix products
+ *     (the small-cycle / any-path problem of Section 1, on Section 2.1).
  * The only liberty taken is skipping k when a_ik is INF, which cannot change
  * the result because every such sum is INF.  The row loop of the product is
  * split over OpenMP threads, as in the paper's multicore version (Section 3).
@@ -376,4 +380,193 @@ int oracle_recurrence(int n, int K, int32_t inf, int64_t *out)
     out[2] = b;
     out[3] = m0;
     return found;
+}
+
+/* ------------------------------------------------------------------------
+ * The complementary construction: columns that are copies of the cycle.
+ *
+ * Section 1 names the problem of a small cycle and any path, solved in the
+ * companion work with (min,+) matrix-vector products; Section 2.1 gives the
+ * general column digraph for any Cartesian product with a column structure.
+ * Here a column is the cycle C_m (m >= 3) and the columns follow each other
+ * along the path P_n, so a 2-dominating set is an open walk of n columns.
+ * The letters and the three rules of Section 2.2 stay as they are, with the
+ * neighbours of letter i inside the column taken modulo m (letters i - 1 and
+ * i + 1 around the cycle).  The path has ends, so two boundary conditions
+ * replace the closing arc of Theorem 2:
+ *   - the first column has no column before it: its letters are labelled from
+ *     their column alone (q_i counts as neither 0 nor 2);
+ *   - the last column has no column after it, which is the only place a
+ *     letter 2 could find its missing neighbour: it holds no 2.
+ * gamma_2(P_n x C_m) is then the least label of such a walk: with s the start
+ * vector (zeros(p) where p may open the walk, else INF) and e the end vector
+ * (0 where p may close it, else INF), it is min_p (s x A^(n-1))_p + e_p.
+ * ------------------------------------------------------------------------ */
+
+/* Letters w[0..m-1] of a cyclic word are decoded as for the path words. */
+
+/* A cyclic word is correct when no letter breaks a rule that its column
+ * alone already decides, read around the cycle: no 2 with both column
+ * neighbours 0 (the 020 window), no 1 with both column neighbours nonzero
+ * (the 111, 211, 112, 212 windows).  There are no start or end windows. */
+int oracle_is_correct_cyclic_word(int m, uint32_t code)
+{
+    int w[MAXN];
+    if (m < 3 || m > MAXN)
+        return 0;
+    decode(code, m, w);
+    for (int i = 0; i < m; ++i) {
+        int left = w[(i + m - 1) % m], right = w[(i + 1) % m];
+        if (w[i] == 2 && left == 0 && right == 0)
+            return 0;
+        if (w[i] == 1 && left != 0 && right != 0)
+            return 0;
+    }
+    return 1;
+}
+
+/* Number of correct cyclic words of length m; with codes != NULL also their
+ * base-3 codes in increasing order (the index order of the matrix below). */
+int64_t oracle_cyclic_words(int m, uint32_t *codes)
+{
+    if (m < 3 || m > MAXN)
+        return -1;
+    uint32_t total = 1;
+    for (int i = 0; i < m; ++i)
+        total *= 3u;
+    int64_t cnt = 0;
+    for (uint32_t x = 0; x < total; ++x) {
+        if (oracle_is_correct_cyclic_word(m, x)) {
+            if (codes)
+                codes[cnt] = x;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+/* "p can follow q" for cyclic columns: the rules of Section 2.2 with the
+ * column neighbours of letter i taken modulo m.  q = NULL stands for the
+ * missing column before the first one (no 0 and no 2 in it). */
+static int cyclic_follows_letters(int m, const int *q, const int *p)
+{
+    for (int i = 0; i < m; ++i) {
+        int qi = q ? q[i] : 1;
+        if (qi == 2 && p[i] != 0)
+            return 0;
+        int zeros = (qi == 0) + (p[(i + m - 1) % m] == 0) + (p[(i + 1) % m] == 0);
+        if (p[i] == 2 && zeros != 1)
+            return 0;
+        if (p[i] == 1 && zeros < 2)
+            return 0;
+    }
+    return 1;
+}
+
+int oracle_cyclic_follows(int m, uint32_t q_code, uint32_t p_code)
+{
+    int q[MAXN], p[MAXN];
+    if (m < 3 || m > MAXN)
+        return 0;
+    decode(q_code, m, q);
+    decode(p_code, m, p);
+    return cyclic_follows_letters(m, q, p);
+}
+
+/* The first column of the walk: p labelled from its own column only. */
+int oracle_cyclic_can_start(int m, uint32_t p_code)
+{
+    int p[MAXN];
+    if (m < 3 || m > MAXN)
+        return 0;
+    decode(p_code, m, p);
+    return cyclic_follows_letters(m, NULL, p);
+}
+
+/* The last column of the walk: no letter 2. */
+int oracle_cyclic_can_end(int m, uint32_t p_code)
+{
+    int p[MAXN];
+    if (m < 3 || m > MAXN)
+        return 0;
+    decode(p_code, m, p);
+    for (int i = 0; i < m; ++i)
+        if (p[i] == 2)
+            return 0;
+    return 1;
+}
+
+/* The column digraph's matrix for cyclic columns (Algorithm 1 with the rules
+ * above): A[q][p] = zeros(p) if p can follow q, else INF; N x N int32,
+ * leading dimension N.  Returns N, or -1 on bad m. */
+int64_t oracle_cyclic_state_matrix(int m, int32_t inf, int32_t *A)
+{
+    int64_t N = oracle_cyclic_words(m, NULL);
+    if (N < 0)
+        return -1;
+    uint32_t *w = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    oracle_cyclic_words(m, w);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j)
+            A[i * N + j] = oracle_cyclic_follows(m, w[i], w[j]) ? oracle_zeros(m, w[j]) : inf;
+    free(w);
+    return N;
+}
+
+/* The boundary vectors of the open walk: start[p] = zeros(p) if p may be the
+ * first column, else INF; end[p] = 0 if p may be the last column, else INF.
+ * Returns N, or -1 on bad m. */
+int64_t oracle_cyclic_boundary(int m, int32_t inf, int32_t *start, int32_t *end)
+{
+    int64_t N = oracle_cyclic_words(m, NULL);
+    if (N < 0)
+        return -1;
+    uint32_t *w = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    oracle_cyclic_words(m, w);
+    for (int64_t j = 0; j < N; ++j) {
+        start[j] = oracle_cyclic_can_start(m, w[j]) ? oracle_zeros(m, w[j]) : inf;
+        end[j] = oracle_cyclic_can_end(m, w[j]) ? 0 : inf;
+    }
+    free(w);
+    return N;
+}
+
+/* gamma_2(P_k x C_m) for k = 1..nmax by the vector chain x_1 = start,
+ * x_(k+1) = x_k x A (a 1 x N by N x N product of Section 1), each answer
+ * min_p x_k[p] + end[p] saturated at INF.  Returns N, or -1 on bad
+ * arguments. */
+int64_t oracle_path_gamma2_sweep(int m, int nmax, int32_t inf, int32_t *gam)
+{
+    int64_t N = oracle_cyclic_words(m, NULL);
+    if (N < 0 || nmax < 1)
+        return -1;
+    int32_t *A = (int32_t *)malloc((size_t)N * (size_t)N * sizeof(int32_t));
+    int32_t *x = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    int32_t *y = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    int32_t *e = (int32_t *)malloc((size_t)N * sizeof(int32_t));
+    oracle_cyclic_state_matrix(m, inf, A);
+    oracle_cyclic_boundary(m, inf, x, e);
+    for (int k = 1; k <= nmax; ++k) {
+        if (k > 1) {
+            oracle_minplus(1, N, N, x, N, A, N, y, N, inf);
+            int32_t *t = x;
+            x = y;
+            y = t;
+        }
+        int32_t best = inf;
+        for (int64_t j = 0; j < N; ++j) {
+            int32_t s = x[j] + e[j];
+            if (s > inf)
+                s = inf;
+            if (s < best)
+                best = s;
+        }
+        gam[k - 1] = best;
+    }
+    free(A);
+    free(x);
+    free(y);
+    free(e);
+    return N;
 }
