@@ -190,7 +190,8 @@ int tp_minplus_spmm(int dtype, int64_t rows, int64_t K, const int64_t *d_rowptr,
  * tp_minplus_spmm with the CSR of tp_build_state_csr; TP_STEP_AUTO takes
  * the form tp_tune_step set for n, else row blocks from n = 11 on (measured
  * faster there) and the CSR gather below.  X and Y must not overlap.
- * Leading dimensions in elements.  TP_EINVAL on a bad n, form or size. */
+ * Leading dimensions in elements; 1 <= n <= 13.  TP_EINVAL on a bad n, form
+ * or size. */
 int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, int64_t ldy,
                       int64_t ncols, hipStream_t stream);
 
@@ -485,6 +486,65 @@ int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *
  * exceeded the wait limit (the kernel then drains without computing, the
  * results are invalid and the levels it was to compute are dropped). */
 int tp_ctx_check(void *ctx, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Small cycle, any path.  Section 1 names the complementary problem (a       */
+/* small cycle and a path of any order, by (min,+) matrix-vector products);   */
+/* Section 2.1's column digraph applies with columns that are copies of the   */
+/* cycle C_m, the rules of Section 2.2 read around the cycle (letter i's      */
+/* column neighbours are i - 1 and i + 1 modulo m), and an open walk of n     */
+/* columns along the path.  The first column is labelled from its own column  */
+/* (no column before it); the last holds no 2 (no column after it gives a 2   */
+/* its second neighbour).  Then                                               */
+/*   gamma_2(P_n x C_m) = min_p (start x A^(n-1))_p + end_p,                  */
+/* start_p = zeros(p) where p may open the walk (else INF), end_p = 0 where   */
+/* p may close it (else INF), A[q][p] = zeros(p) if p can follow q, else INF. */
+/* Cyclic words are indexed in increasing base-3 value (first letter most     */
+/* significant).  3 <= m <= 12 (N < 65536); TP_EINVAL otherwise.              */
+/* ------------------------------------------------------------------------ */
+
+/* Number of correct cyclic words of length m (host count, no GPU work). */
+int64_t tp_cyclic_dim(int m);
+
+/* Number of arcs (non-INF entries of A); the first call for m builds the
+ * cyclic digraph on the current device and blocks; later calls are cached. */
+int64_t tp_cyclic_nnz(int m);
+
+/* d_codes[0..N-1] = base-3 codes of the correct cyclic words, increasing
+ * (device uint32_t array of N = tp_cyclic_dim(m) entries). */
+int tp_cyclic_words(int m, uint32_t *d_codes, hipStream_t stream);
+
+/* The N x N matrix A of the cyclic column digraph, dtype TP_U8 or TP_U16,
+ * row-major with leading dimension lda >= N (device memory of the caller). */
+int tp_build_cyclic_matrix(int m, int dtype, void *d_A, int64_t lda, hipStream_t stream);
+
+/* The walk's boundary vectors (N entries each, dtype TP_U8 or TP_U16):
+ * d_start[p] = zeros(p) if p may be the first column else INF; d_end[p] = 0
+ * if p may be the last column else INF.  Either pointer may be NULL (that
+ * vector is not written), not both. */
+int tp_build_cyclic_boundary(int m, int dtype, void *d_start, void *d_end, hipStream_t stream);
+
+/* gamma_2(P_n x C_m) into *gamma2_host for n >= 1, blocking: the walk as
+ * n - 1 dense vector-matrix products x <- x x A (the kernel of
+ * tp_minplus_gemv with trans = 1, on a cached u16 copy of A) and the end
+ * vector.  TP_EOVERFLOW when n*m >= 65535.  The cache (digraph, dense A,
+ * level vectors) lives on the current device until tp_release_cache. */
+int tp_cyclic_walk_gamma2(int64_t n, int m, int32_t *gamma2_host, hipStream_t stream);
+
+/* Forms of the sweep below; every form gives the same numbers. */
+#define TP_WALK_AUTO 0  /* the one-workgroup walk where it fits, else TP_WALK_STEPS */
+#define TP_WALK_CHAIN 1 /* the whole walk in one launch of one workgroup, level
+                         * vectors in LDS (N <= 10752, m <= 10) */
+#define TP_WALK_STEPS 2 /* one full-chip launch per level: a wave per column
+                         * gathers the minimum over its predecessors */
+#define TP_WALK_GEMV 3  /* one dense vector-matrix product per level */
+
+/* d_gamma2[k - 1] (device int32) = gamma_2(P_k x C_m) for k = 1..nmax: one
+ * walk whose every level is read by the end vector.  TP_WALK_CHAIN returns
+ * without waiting; the other forms use the cache's level vectors and block
+ * until done.  TP_EOVERFLOW when nmax*m >= 65535; TP_EINVAL when
+ * TP_WALK_CHAIN is asked for an m whose words do not fit. */
+int tp_cyclic_walk_sweep(int m, int64_t nmax, int32_t *d_gamma2, int form, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -34,6 +34,10 @@ TP_PARAM_BABY_STEPS = 32
 TP_STEP_AUTO = 0
 TP_STEP_CSR = 1
 TP_STEP_BLOCKED = 2
+TP_WALK_AUTO = 0
+TP_WALK_CHAIN = 1
+TP_WALK_STEPS = 2
+TP_WALK_GEMV = 3
 
 INF = {TP_U8: 255, TP_U16: 65535}
 
@@ -117,6 +121,13 @@ _SIGS = {
     "tp_ctx_release": ([_p, _i, _p], _i),
     "tp_batch_power_trace": ([_p, _i, _p, _p, _p, _p], _i),
     "tp_ctx_check": ([_p, _p], _i),
+    "tp_cyclic_dim": ([_i], _i64),
+    "tp_cyclic_nnz": ([_i], _i64),
+    "tp_cyclic_words": ([_i, _p, _p], _i),
+    "tp_build_cyclic_matrix": ([_i, _i, _p, _i64, _p], _i),
+    "tp_build_cyclic_boundary": ([_i, _i, _p, _p, _p], _i),
+    "tp_cyclic_walk_gamma2": ([_i64, _i, ctypes.POINTER(ctypes.c_int32), _p], _i),
+    "tp_cyclic_walk_sweep": ([_i, _i64, _p, _i, _p], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -759,3 +770,67 @@ def tp_batch_power_trace(ctx: int, ns, ms, out: torch.Tensor | None = None,
 
 def tp_ctx_check(ctx: int, stream=None) -> None:
     _check(lib.tp_ctx_check(ctx, _stream(stream)))
+
+
+# -- small cycle, any path: columns that are copies of C_m ------------------
+
+def tp_cyclic_dim(m: int) -> int:
+    """Number of correct cyclic words of length m (3 <= m <= 12)."""
+    return _check(int(lib.tp_cyclic_dim(m)))
+
+
+def tp_cyclic_nnz(m: int) -> int:
+    return _check(int(lib.tp_cyclic_nnz(m)))
+
+
+def tp_cyclic_words(m: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Base-3 codes of the correct cyclic words (int32 tensor holding uint32)."""
+    N = tp_cyclic_dim(m)
+    if out is None:
+        out = torch.empty(N, dtype=torch.int32, device="cuda")
+    if out.dtype != torch.int32 or out.numel() < N or not out.is_cuda:
+        raise ValueError("out must be a cuda int32 tensor of at least N entries")
+    _check(lib.tp_cyclic_words(m, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def tp_build_cyclic_matrix(m: int, dtype: int = TP_U16, out: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+    """The cyclic column digraph's N x N matrix in 8 or 16 bits."""
+    N = tp_cyclic_dim(m)
+    if out is None:
+        out = torch.empty((N, N), dtype=_torch_dtype(dtype), device="cuda")
+    ptr, r, c, ld = _mat(out, "out")
+    if r < N or c < N or _dtype_code(out) != dtype:
+        raise ValueError("out must be at least N x N of the requested dtype")
+    _check(lib.tp_build_cyclic_matrix(m, dtype, ptr, ld, _stream(stream)))
+    return out
+
+
+def tp_build_cyclic_boundary(m: int, dtype: int = TP_U16, stream=None):
+    """(start, end) vectors of the walk along the path, N entries each."""
+    N = tp_cyclic_dim(m)
+    start = torch.empty(N, dtype=_torch_dtype(dtype), device="cuda")
+    end = torch.empty(N, dtype=_torch_dtype(dtype), device="cuda")
+    _check(lib.tp_build_cyclic_boundary(m, dtype, start.data_ptr(), end.data_ptr(),
+                                        _stream(stream)))
+    return start, end
+
+
+def tp_cyclic_walk_gamma2(n: int, m: int, stream=None) -> int:
+    """gamma_2(P_n x C_m) by n - 1 dense vector-matrix products over cyclic
+    columns; blocks."""
+    res = ctypes.c_int32(-1)
+    _check(lib.tp_cyclic_walk_gamma2(n, m, ctypes.byref(res), _stream(stream)))
+    return int(res.value)
+
+
+def tp_cyclic_walk_sweep(m: int, nmax: int, out: torch.Tensor | None = None,
+                         form: int = TP_WALK_AUTO, stream=None) -> torch.Tensor:
+    """out[k - 1] (device int32) = gamma_2(P_k x C_m) for k = 1..nmax."""
+    if out is None:
+        out = torch.empty(max(nmax, 1), dtype=torch.int32, device="cuda")
+    if out.dtype != torch.int32 or out.numel() < nmax or not out.is_cuda:
+        raise ValueError("out must be a cuda int32 tensor of at least nmax entries")
+    _check(lib.tp_cyclic_walk_sweep(m, nmax, out.data_ptr(), form, _stream(stream)))
+    return out

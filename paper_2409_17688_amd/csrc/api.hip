@@ -150,9 +150,13 @@ int get_state(int n, hipStream_t s, State **out) {
         return bp[a + 1] - bp[a] > bp[c + 1] - bp[c];
       });
       TP_HIP_CHECK(ensure(st.border, std::max<size_t>(bo.size(), 1) * sizeof(int32_t)));
-      if (nb > 0)
-        TP_HIP_CHECK(hipMemcpy(st.border.ptr, bo.data(), bo.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice));
+      // on the call's stream: a synchronous copy would wait for the work
+      // other streams have in flight
+      if (nb > 0) {
+        TP_HIP_CHECK(hipMemcpyAsync(st.border.ptr, bo.data(), bo.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s));
+        TP_HIP_CHECK(hipStreamSynchronize(s));
+      }
     }
     st.zh.assign((size_t)N, 0);
     TP_HIP_CHECK(hipMemcpyAsync(st.zh.data(), st.z.ptr, (size_t)N, hipMemcpyDeviceToHost, s));
@@ -173,9 +177,11 @@ int get_state(int n, hipStream_t s, State **out) {
       return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
     });
     TP_HIP_CHECK(ensure(st.order, std::max<size_t>(ord.size(), 1) * sizeof(int32_t)));
-    if (N > 0)
-      TP_HIP_CHECK(hipMemcpy(st.order.ptr, ord.data(), ord.size() * sizeof(int32_t),
-                             hipMemcpyHostToDevice));
+    if (N > 0) {
+      TP_HIP_CHECK(hipMemcpyAsync(st.order.ptr, ord.data(), ord.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
+      TP_HIP_CHECK(hipStreamSynchronize(s));
+    }
     st.csr_ready = true;
   }
   *out = &st;
@@ -748,7 +754,7 @@ int tp_trace_of_product(int dtype, int64_t N, const void *d_X, int64_t ldx, cons
 
 int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, int64_t ldy,
                       int64_t ncols, hipStream_t stream) {
-  TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
+  TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
   TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED,
              "form %d is not TP_STEP_AUTO, TP_STEP_CSR or TP_STEP_BLOCKED", form);
   TP_REQUIRE(ncols >= 0, "negative size");
@@ -870,6 +876,7 @@ int tp_release_cache(void) {
     release(kv.second.scalar);
   }
   g_ws.clear();
+  cyclic_release_cache();
   return TP_OK;
 }
 

@@ -353,30 +353,32 @@ struct Buf {
   size_t bytes = 0;
 };
 
-hipError_t grow(Buf &b, size_t bytes) {
+// A buffer that has to grow is replaced by one at least twice its size and
+// the old one is kept until the context is destroyed: hipFree and
+// hipHostFree wait for the whole device, so freeing here would make a batch
+// on this context wait for the batches other contexts have in flight.
+hipError_t grow(Buf &b, size_t bytes, std::vector<void *> &retired) {
   if (b.p && b.bytes >= bytes) return hipSuccess;
-  if (b.p) {
-    hipError_t e = hipFree(b.p);
-    if (e != hipSuccess) return e;
-  }
-  b.p = nullptr;
-  b.bytes = 0;
-  hipError_t e = hipMalloc(&b.p, bytes);
-  if (e == hipSuccess) b.bytes = bytes;
-  return e;
+  const size_t want = std::max(bytes, 2 * b.bytes);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) return e;
+  if (b.p) retired.push_back(b.p);
+  b.p = p;
+  b.bytes = want;
+  return hipSuccess;
 }
 
-hipError_t grow_host(Buf &b, size_t bytes) {
+hipError_t grow_host(Buf &b, size_t bytes, std::vector<void *> &retired) {
   if (b.p && b.bytes >= bytes) return hipSuccess;
-  if (b.p) {
-    hipError_t e = hipHostFree(b.p);
-    if (e != hipSuccess) return e;
-  }
-  b.p = nullptr;
-  b.bytes = 0;
-  hipError_t e = hipHostMalloc(&b.p, bytes, hipHostMallocDefault);
-  if (e == hipSuccess) b.bytes = bytes;
-  return e;
+  const size_t want = std::max(bytes, 2 * b.bytes);
+  void *p = nullptr;
+  hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  if (b.p) retired.push_back(b.p);
+  b.p = p;
+  b.bytes = want;
+  return hipSuccess;
 }
 
 struct PowerSet {
@@ -410,6 +412,9 @@ struct Ctx {
   int grid_override = 0;
   bool pending = false;                      // a batch was queued and not yet checked
   std::map<int, std::set<int>> pending_new;  // exponents that batch computes, by n
+  // buffers and graphs replaced while the context lives, freed with it
+  std::vector<void *> retired_dev, retired_host;
+  std::vector<hipGraphExec_t> retired_exec;
   std::mutex mu;
 };
 
@@ -489,7 +494,8 @@ void batch_needs(const std::vector<int64_t> &ms, int c, int *chain_top, std::set
 
 int capture_graph(Ctx *c, int grid) {
   if (c->exec) {
-    (void)hipGraphExecDestroy(c->exec);
+    // a batch queued earlier may still run it; destroyed with the context
+    c->retired_exec.push_back(c->exec);
     c->exec = nullptr;
   }
   if (!c->cap_stream) TP_HIP_CHECK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -880,24 +886,25 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   const size_t tbytes = tasks.size() * sizeof(Task);
   const size_t ptr_stride = (size_t)maxexp + 1;
   const size_t nptr = ptr_stride * nslots;
-  TP_HIP_CHECK(grow_host(c->h_tasks, std::max<size_t>(tbytes, sizeof(Task))));
-  TP_HIP_CHECK(grow_host(c->h_slots, kMaxSlots * sizeof(Slot)));
-  TP_HIP_CHECK(grow_host(c->h_ptrs, nptr * sizeof(void *)));
-  TP_HIP_CHECK(grow_host(c->h_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_tasks, std::max<size_t>(tbytes, sizeof(Task))));
-  TP_HIP_CHECK(grow(c->d_slots, kMaxSlots * sizeof(Slot)));
-  TP_HIP_CHECK(grow(c->d_ptrs, nptr * sizeof(void *)));
-  TP_HIP_CHECK(grow(c->d_ctl, sizeof(Control)));
-  TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max<int64_t>(counter_words, 1) * sizeof(int32_t)));
-  TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t)));
+  TP_HIP_CHECK(grow_host(c->h_tasks, std::max<size_t>(tbytes, sizeof(Task)), c->retired_host));
+  TP_HIP_CHECK(grow_host(c->h_slots, kMaxSlots * sizeof(Slot), c->retired_host));
+  TP_HIP_CHECK(grow_host(c->h_ptrs, nptr * sizeof(void *), c->retired_host));
+  TP_HIP_CHECK(grow_host(c->h_ctl, sizeof(Control), c->retired_host));
+  TP_HIP_CHECK(grow(c->d_tasks, std::max<size_t>(tbytes, sizeof(Task)), c->retired_dev));
+  TP_HIP_CHECK(grow(c->d_slots, kMaxSlots * sizeof(Slot), c->retired_dev));
+  TP_HIP_CHECK(grow(c->d_ptrs, nptr * sizeof(void *), c->retired_dev));
+  TP_HIP_CHECK(grow(c->d_ctl, sizeof(Control), c->retired_dev));
+  TP_HIP_CHECK(grow(c->d_counters, (size_t)std::max<int64_t>(counter_words, 1) * sizeof(int32_t),
+                    c->retired_dev));
+  TP_HIP_CHECK(grow(c->d_results, (size_t)std::max(count, 1) * sizeof(int32_t), c->retired_dev));
   const size_t lbytes = levels.size() * sizeof(Level);
   const size_t ibytes = items.size() * sizeof(uint32_t);
   if (lbytes) {
-    TP_HIP_CHECK(grow_host(c->h_levels, lbytes));
-    TP_HIP_CHECK(grow(c->d_levels, lbytes));
+    TP_HIP_CHECK(grow_host(c->h_levels, lbytes, c->retired_host));
+    TP_HIP_CHECK(grow(c->d_levels, lbytes, c->retired_dev));
     memcpy(c->h_levels.p, levels.data(), lbytes);
-    TP_HIP_CHECK(grow_host(c->h_items, ibytes));
-    TP_HIP_CHECK(grow(c->d_items, ibytes));
+    TP_HIP_CHECK(grow_host(c->h_items, ibytes, c->retired_host));
+    TP_HIP_CHECK(grow(c->d_items, ibytes, c->retired_dev));
     memcpy(c->h_items.p, items.data(), ibytes);
   }
 
@@ -992,9 +999,13 @@ int ctx_check(Ctx *c, hipStream_t stream) {
   if (!c->pending) return TP_OK;
   c->pending = false;
   int32_t abort = 0;
-  if (c->d_ctl.p)
-    TP_HIP_CHECK(hipMemcpy(&abort, (char *)c->d_ctl.p + offsetof(Control, abort), sizeof(int32_t),
-                           hipMemcpyDeviceToHost));
+  if (c->d_ctl.p) {
+    // on the batch's stream (a synchronous copy would also wait for other
+    // contexts' batches)
+    TP_HIP_CHECK(hipMemcpyAsync(&abort, (char *)c->d_ctl.p + offsetof(Control, abort),
+                                sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    TP_HIP_CHECK(hipStreamSynchronize(stream));
+  }
   if (abort) {
     // nothing the aborted batches were to compute can be trusted
     for (auto &kv : c->pending_new)
@@ -1025,6 +1036,9 @@ void ctx_free(Ctx *c) {
   Buf *host[] = {&c->h_tasks, &c->h_slots, &c->h_ptrs, &c->h_ctl, &c->h_levels, &c->h_items};
   for (Buf *b : host)
     if (b->p) (void)hipHostFree(b->p);
+  for (hipGraphExec_t g : c->retired_exec) (void)hipGraphExecDestroy(g);
+  for (void *p : c->retired_dev) (void)hipFree(p);
+  for (void *p : c->retired_host) (void)hipHostFree(p);
 }
 
 }  // namespace tp

@@ -179,6 +179,32 @@ int gemm_tune_set(int dtype, int64_t max_dim, int config, int ksplit);
 void gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *ksplit);
 int gemm_config_count();
 
+// cyclic.hip: columns that are copies of the cycle C_m (3 <= m <= 12)
+int64_t cyclic_count_host(int m);
+hipError_t launch_cyclic_words(int m, uint32_t *codes, uint8_t *zeros, uint32_t *masks,
+                               hipStream_t s);
+hipError_t launch_cyclic_dense(int m, int64_t N, const uint32_t *masks, int dtype, void *A,
+                               int64_t lda, hipStream_t s);
+hipError_t launch_cyclic_boundary(int m, int64_t N, const uint32_t *masks, int dtype, void *start,
+                                  void *end, hipStream_t s);
+hipError_t launch_cyclic_pred_count(int m, int64_t N, const uint32_t *masks, int64_t *predptr,
+                                    hipStream_t s);
+hipError_t launch_cyclic_pred_fill(int m, int64_t N, const uint32_t *masks, const int64_t *predptr,
+                                   uint16_t *pred, hipStream_t s);
+int64_t cyclic_strip_length(int64_t nnz);
+hipError_t launch_cyclic_strips(int64_t N, int64_t nnz, const int64_t *predptr,
+                                const uint16_t *pred, uint32_t *strips, hipStream_t s);
+hipError_t launch_cyclic_chain(int64_t N, int64_t nnz, int64_t nmax, const uint32_t *strips,
+                               const uint8_t *z, const uint16_t *start, const uint16_t *end,
+                               int32_t *out, hipStream_t s);
+hipError_t launch_cyclic_step(int64_t N, const int64_t *predptr, const uint16_t *pred,
+                              const int32_t *order, const uint8_t *z, const uint16_t *end,
+                              const uint16_t *x, uint16_t *y, int32_t *out, hipStream_t s);
+hipError_t launch_cyclic_answer(int64_t N, const uint16_t *x, const uint16_t *end, int32_t *out,
+                                hipStream_t s);
+// cyclic_api.hip: frees the cache of cyclic column digraphs
+void cyclic_release_cache();
+
 // gemv.hip
 hipError_t launch_gemv(int dtype, int64_t M, int64_t K, const void *A, int64_t lda,
                        const void *x, void *y, int trans, hipStream_t s);

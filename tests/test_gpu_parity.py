@@ -308,7 +308,9 @@ def test_state_left_mul_rejects_bad_arguments(tp):
     with pytest.raises(TypeError):
         tp.tp_state_left_mul(4, X.to(torch.uint8))
     p = X.data_ptr()
-    assert tp.lib.tp_state_left_mul(13, 0, p, 5, p, 5, 5, None) == tp.TP_EINVAL
+    # path orders outside 1..13 are rejected before anything is read
+    assert tp.lib.tp_state_left_mul(14, 0, p, 5, p, 5, 5, None) == tp.TP_EINVAL
+    assert tp.lib.tp_state_left_mul(0, 0, p, 5, p, 5, 5, None) == tp.TP_EINVAL
     assert tp.lib.tp_state_left_mul(4, 0, p, 4, p, 5, 5, None) == tp.TP_EINVAL
     assert tp.lib.tp_state_left_mul(4, 3, p, 5, p, 5, 5, None) == tp.TP_EINVAL
 

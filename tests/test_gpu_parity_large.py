@@ -60,10 +60,11 @@ def rows_of(t, rows):
     import torch
     torch.cuda.synchronize()
     idx = torch.from_numpy(rows).cuda()
-    r = t[idx]
-    if r.dtype == torch.uint16:
-        return r.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.int64)
-    return r.cpu().numpy().astype(np.int64)
+    if t.dtype == torch.uint16:
+        # torch has no uint16 gather: the rows of the same bits viewed as int16
+        r = t.view(torch.int16)[idx]
+        return r.cpu().numpy().view(np.uint16).astype(np.int64)
+    return t[idx].cpu().numpy().astype(np.int64)
 
 
 @pytest.mark.parametrize("n", [10, 11, 12, 13])
