@@ -210,16 +210,18 @@ class ResidentLane:
             self.broken = "a power of A(D_n) did not fit the compact form"
 
     def _advance(self):
-        """One chain step of the panel; keeps it when the level is jc."""
+        """One chain step of the panel; keeps it when the level is jc.  The
+        buffer the step read becomes the next step's output unless it holds a
+        kept panel (the level before was jc), which is never written again."""
         tp, s = self.tp, self.stream
         (x, b), (y, by) = self.chain, self.spare
         tp.tp_compact_shared_step(self.n, x, b, self.count, y, by, self.status, stream=s)
         self.level += 1
         if self.level % self.c == 0:
             self.panels[self.level // self.c] = (y, by)
-            self.chain, self.spare = (y, by), (self._u8(self.count), self._base())
-        else:
-            self.chain, self.spare = (y, by), (x, b)
+        x_kept = any(px is x for px, _ in self.panels.values())
+        self.chain = (y, by)
+        self.spare = (self._u8(self.count), self._base()) if x_kept else (x, b)
 
     # ------------------------------------------------------------- answer --
 

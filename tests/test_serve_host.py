@@ -286,6 +286,34 @@ def test_lane_plan_covers_every_m():
     assert lane._plan(100) == ("plain",)
 
 
+def test_lane_chain_never_writes_a_kept_panel():
+    """The panel chain's ping-pong (no GPU: buffers are plain objects and the
+    step records its level into the buffer it writes): after many steps every
+    kept panel still holds the level jc it was kept at."""
+    class Buf:
+        def __init__(self):
+            self.level = None
+
+    class FakeTp:
+        def tp_compact_shared_step(self, n, x, b, count, y, by, status, stream=None):
+            y.level = x.level + 1
+
+    lane = serve.ResidentLane.__new__(serve.ResidentLane)
+    lane.tp, lane.stream, lane.n, lane.count, lane.status = FakeTp(), None, 10, 7, None
+    lane.c, lane.panels = 10, {}
+    lane._u8 = lambda cols: Buf()
+    lane._base = lambda: None
+    first = Buf()
+    first.level = 3
+    lane.chain, lane.spare, lane.level = (first, None), (Buf(), None), 3
+    for _ in range(3, 257):
+        lane._advance()
+        assert lane.chain[0].level == lane.level
+        for j, (p, _) in lane.panels.items():
+            assert p.level == 10 * j, (j, p.level, lane.level)
+    assert sorted(lane.panels) == list(range(1, 26))
+
+
 def test_percentile_nearest_rank():
     assert serve.percentile(list(range(1, 101)), 50) == 50
     assert serve.percentile(list(range(1, 101)), 99) == 99
