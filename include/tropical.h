@@ -128,6 +128,25 @@ int tp_minplus_gemm_ex(int dtype, int64_t M, int64_t N, int64_t K, const void *d
                        const void *d_B, int64_t ldb, void *d_C, int64_t ldc, int accumulate,
                        int config, int ksplit, hipStream_t stream);
 
+/* Bytes of the fixed split-K scratch of tp_minplus_gemm_ex_noalloc. */
+#define TP_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* tp_minplus_gemm_ex for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same product, kernels and result, with the split-K
+ * partials in a fixed buffer of TP_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends, instead of
+ * scratch it allocates.  Allocates nothing and frees nothing.  The partials
+ * of S slices take S * M * (N rounded up to 64) elements; a product whose
+ * partials exceed the buffer is rejected with TP_EINVAL (nothing queued).
+ * Every call on one device shares that buffer: calls that overlap on one
+ * device (concurrent streams, or threads) race and must be ordered by the
+ * caller.  Without a split (ksplit 1, or K <= 64) no scratch is used. */
+int tp_minplus_gemm_ex_noalloc(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A,
+                               int64_t lda, const void *d_B, int64_t ldb, void *d_C,
+                               int64_t ldc, int accumulate, int config, int ksplit,
+                               hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tuning tables (filled by the autotuner; the library has built-in          */
 /* defaults).  None of them changes a result, only which kernel shape runs.  */

@@ -78,6 +78,8 @@ _SIGS = {
                                _i),
     "tp_minplus_gemm_ex": ([_i, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i, _i, _i,
                             _p], _i),
+    "tp_minplus_gemm_ex_noalloc": ([_i, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i, _i,
+                                    _i, _p], _i),
     "tp_tune_gemm": ([_i, _i64, _i, _i], _i),
     "tp_gemm_choice": ([_i, _i64, _i64, _i64, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "tp_tune_planner": ([_i, ctypes.c_double, ctypes.c_double], _i),

@@ -665,6 +665,19 @@ int tp_minplus_gemm_ex(int dtype, int64_t M, int64_t N, int64_t K, const void *d
   return TP_OK;
 }
 
+int tp_minplus_gemm_ex_noalloc(int dtype, int64_t M, int64_t N, int64_t K, const void *d_A,
+                               int64_t lda, const void *d_B, int64_t ldb, void *d_C,
+                               int64_t ldc, int accumulate, int config, int ksplit,
+                               hipStream_t stream) {
+  int rc = check_gemm(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc);
+  if (rc != TP_OK) return rc;
+  TP_REQUIRE(config >= 0 && config < gemm_config_count(), "config %d outside 0..%d", config,
+             gemm_config_count() - 1);
+  TP_REQUIRE(ksplit >= 1 && ksplit <= 64, "ksplit %d outside 1..64", ksplit);
+  return launch_gemm_fixed(dtype, M, N, K, d_A, lda, d_B, ldb, d_C, ldc, accumulate, config,
+                           ksplit, stream);
+}
+
 int tp_gemm_config_count(void) { return gemm_config_count(); }
 
 int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s) {

@@ -174,6 +174,12 @@ hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent
 hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
                        const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
                        int config, int ksplit, hipStream_t s);
+// the same into the fixed per-device scratch (allocates nothing); a status:
+// TP_EINVAL when the partials need more than kFixedScratchBytes
+constexpr size_t kFixedScratchBytes = TP_NOALLOC_SCRATCH_BYTES;
+int launch_gemm_fixed(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
+                      int config, int ksplit, hipStream_t s);
 // tuning table of the default (config < 0) choice; max_dim < 0 clears it
 int gemm_tune_set(int dtype, int64_t max_dim, int config, int ksplit);
 void gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *ksplit);

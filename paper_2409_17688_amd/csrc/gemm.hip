@@ -236,6 +236,40 @@ void gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int *k
 
 int gemm_config_count() { return kNumConfigs; }
 
+namespace {
+
+// Slices of a multiple of 64 columns (keeps the slices' 16-byte alignment).
+void split_of(int64_t K, int ksplit, int *S, int64_t *kslice) {
+  *S = 1;
+  *kslice = K;
+  if (ksplit > 1 && K > 64) {
+    *kslice = ((K + ksplit - 1) / ksplit + 63) / 64 * 64;
+    *S = (int)((K + *kslice - 1) / *kslice);
+  }
+}
+
+int64_t partial_ld(int64_t N) { return (N + 63) / 64 * 64; }
+
+size_t partial_bytes(int dtype, int64_t M, int64_t N, int S) {
+  return (size_t)S * (size_t)M * (size_t)partial_ld(N) * (dtype == TP_U16 ? 2 : 1);
+}
+
+// The product with S slices of kslice columns, partials (S > 1) in W.
+hipError_t launch_split(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
+                        const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
+                        int config, int S, int64_t kslice, void *W, hipStream_t s) {
+  const int64_t ldw = S > 1 ? partial_ld(N) : 0, stride = S > 1 ? M * ldw : 0;
+  if (dtype == TP_U16)
+    return launch_typed<uint16_t>(M, N, K, (const uint16_t *)A, lda, (const uint16_t *)B, ldb,
+                                  (uint16_t *)C, ldc, accumulate, config, S, kslice,
+                                  (uint16_t *)W, ldw, stride, s);
+  return launch_typed<uint8_t>(M, N, K, (const uint8_t *)A, lda, (const uint8_t *)B, ldb,
+                               (uint8_t *)C, ldc, accumulate, config, S, kslice, (uint8_t *)W,
+                               ldw, stride, s);
+}
+
+}  // namespace
+
 hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
                        const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
                        int config, int ksplit, hipStream_t s) {
@@ -246,29 +280,70 @@ hipError_t launch_gemm(int dtype, int64_t M, int64_t N, int64_t K, const void *A
     gemm_choice(dtype, M, N, K, &config, &tuned_split);
     ksplit = ksplit == 0 ? 1 : tuned_split;
   }
-  // slices of a multiple of 64 columns (keeps the slices' 16-byte alignment)
   int S = 1;
   int64_t kslice = K;
-  if (ksplit > 1 && K > 64) {
-    kslice = ((K + ksplit - 1) / ksplit + 63) / 64 * 64;
-    S = (int)((K + kslice - 1) / kslice);
-  }
+  split_of(K, ksplit, &S, &kslice);
   void *W = nullptr;
-  int64_t ldw = 0, stride = 0;
   if (S > 1) {
-    const size_t es = dtype == TP_U16 ? 2 : 1;
-    ldw = (N + 63) / 64 * 64;
-    stride = M * ldw;
-    hipError_t e = scratch_for(s, (size_t)S * (size_t)stride * es, &W);
+    hipError_t e = scratch_for(s, partial_bytes(dtype, M, N, S), &W);
     if (e != hipSuccess) return e;
   }
-  if (dtype == TP_U16)
-    return launch_typed<uint16_t>(M, N, K, (const uint16_t *)A, lda, (const uint16_t *)B, ldb,
-                                  (uint16_t *)C, ldc, accumulate, config, S, kslice,
-                                  (uint16_t *)W, ldw, stride, s);
-  return launch_typed<uint8_t>(M, N, K, (const uint8_t *)A, lda, (const uint8_t *)B, ldb,
-                               (uint8_t *)C, ldc, accumulate, config, S, kslice, (uint8_t *)W,
-                               ldw, stride, s);
+  return launch_split(dtype, M, N, K, A, lda, B, ldb, C, ldc, accumulate, config, S, kslice, W,
+                      s);
+}
+
+// --------------------------------------------------------------------------
+// Fixed scratch for callers that cannot allocate (code under graph capture,
+// tight serving loops): the split-K partials go to this file-scope array,
+// one copy per device, held until the process ends.  Its name on the host is
+// a stand-in for the symbol, not a device address: host code reaches the
+// memory only through the address hipGetSymbolAddress gives for the current
+// device, kept per device below.
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {nullptr};
+
+hipError_t fixed_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_fixed_ptr[dev] = p;
+  }
+  *out = g_fixed_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+int launch_gemm_fixed(int dtype, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, void *C, int64_t ldc, int accumulate,
+                      int config, int ksplit, hipStream_t s) {
+  int S = 1;
+  int64_t kslice = K;
+  split_of(K, ksplit, &S, &kslice);
+  void *W = nullptr;
+  if (S > 1 && M > 0 && N > 0) {
+    const size_t need = partial_bytes(dtype, M, N, S);
+    if (need > kFixedScratchBytes) {
+      set_error("%d K slices of a %lld x %lld product need %zu bytes of scratch; the fixed "
+                "buffer holds %zu",
+                S, (long long)M, (long long)N, need, kFixedScratchBytes);
+      return TP_EINVAL;
+    }
+    TP_HIP_CHECK(fixed_scratch(&W));
+  }
+  if (M == 0 || N == 0) return TP_OK;
+  TP_HIP_CHECK(launch_split(dtype, M, N, K, A, lda, B, ldb, C, ldc, accumulate, config, S, kslice,
+                            W, s));
+  return TP_OK;
 }
 
 }  // namespace tp
