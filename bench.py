@@ -64,29 +64,88 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, B, target_s):
     """The CPU oracle on a bounded sample of the same product: a block of rows
-    of C = A x B (each row is an independent (min,+) vector-matrix product)."""
+    of C = A x B (each row is an independent (min,+) vector-matrix product),
+    on every host core the oracle's OpenMP loop takes, then on one core."""
     import numpy as np
 
     import oracle
     Ai = A.astype(np.int32)
     Bi = B.astype(np.int32)
     N = A.shape[0]
-    rows, dt = 16, 0.0
-    while dt < 0.2 * target_s and rows < N:
-        rows = min(N, rows * 2)
+
+    def sample(seconds):
+        rows, dt = 16, 0.0
+        while dt < 0.2 * seconds and rows < N:
+            rows = min(N, rows * 2)
+            t0 = time.perf_counter()
+            oracle.minplus(Ai[:rows], Bi)
+            dt = time.perf_counter() - t0
+        rows = int(max(16, min(N, rows * seconds / max(dt, 1e-6))))
         t0 = time.perf_counter()
         oracle.minplus(Ai[:rows], Bi)
-        dt = time.perf_counter() - t0
-    rows = int(max(16, min(N, rows * target_s / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.minplus(Ai[:rows], Bi)
-    dt = time.perf_counter() - t0
-    ops = float(rows) * N * N
-    return {"value": ops / dt / 1e9, "unit": "Gminplus-ops/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{rows} of {N} rows of C = A x B (same inputs), {dt:.1f} s"}
+        return rows, time.perf_counter() - t0
+
+    cores = oracle.threads()
+    rows, dt = sample(target_s)
+    oracle.set_threads(1)
+    try:
+        rows1, dt1 = sample(max(1.0, target_s / 4))
+    finally:
+        oracle.set_threads(cores)
+    inf_a = float((A >= 65535).mean())
+    return {"value": float(rows) * N * N / dt / 1e9, "unit": "Gminplus-ops/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{rows} of {N} rows of C = A x B (same inputs), {dt:.1f} s",
+            "one_core_value": round(float(rows1) * N * N / dt1 / 1e9, 2),
+            "one_core_sample": f"{rows1} rows, {dt1:.1f} s",
+            "note": (f"credited N^3 per product; the oracle skips k where a_ik = INF "
+                     f"({100 * inf_a:.0f} % of A), so it executes about "
+                     f"{100 * (1 - inf_a):.0f} % of those operations")}
+
+
+def oracle_query_baseline(synth, budget_s=12.0):
+    """The oracle timed on the mixed 64-instance batch, bounded: per path order
+    of the batch, the time of one step of its power chain (Algorithm 2, a dense
+    N^3 product) measured on a short chain less the time of building its state
+    matrix, times the m - 1 steps each instance needs (the oracle answers
+    gamma_2(n, m) by m - 1 steps)."""
+    import oracle
+    inst = synth.batch_instances(seed=0)
+    per_step = {}
+    spent = 0.0
+    for n in sorted({n for n, _ in inst}):
+        t0 = time.perf_counter()
+        oracle.gamma2_sweep(n, 1)  # the state matrix and one trace, no product
+        base = time.perf_counter() - t0
+        k = 2
+        while True:
+            t0 = time.perf_counter()
+            oracle.gamma2_sweep(n, k)
+            dt = time.perf_counter() - t0
+            if dt > 1.0 or k >= 64 or spent + dt > budget_s:
+                break
+            k *= 2
+        spent += dt + base
+        per_step[n] = max(dt - base, 1e-9) / (k - 1)
+    est = sum((m - 1) * per_step[n] for n, m in inst)
+    return {"value": round(len(inst) / est, 3), "unit": "queries/s", "cores": oracle.threads(),
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": ("mixed 64 instances: per-n step time of the oracle's power chain "
+                       f"(measured on chains of up to 64 powers, {spent:.1f} s) times the "
+                       f"m - 1 steps of each instance; estimated {est:.0f} s for the batch")}
 
 
 def main():
@@ -187,6 +246,11 @@ def main():
     if not args.no_suite:
         line["queries"] = query_suite(tp, synth)
         note("query suite done")
+        if not args.no_cpu:
+            line["queries"]["mixed64"]["cpu_baseline"] = oracle_query_baseline(synth)
+            note("oracle query baseline done")
+        line["cyclic_walk"] = cyclic_suite(tp)
+        note("cyclic walk suite done")
         line["recurrence"] = recurrence_suite(tp)
         note("recurrence suite done")
     if not args.no_serve:
@@ -226,12 +290,17 @@ def serve_suite(tp, synth, count=2000):
 
     saturation: every query submitted at once, on a cold server (nothing
     resident), then again warm (the powers the first pass left resident);
-    replay: the stream at 70 % of the warm saturation rate, p50/p99 latency
-    over all queries and per n;
+    warm replay: the stream at 70 % of the warm saturation rate, p50/p99
+    latency over all queries and per n;
+    cold replay: a fresh server fed the stream at 70 % of the cold saturation
+    rate, so the latencies include building the resident powers as queries
+    need them;
     plain: tp_tropical_power_trace one query at a time, estimated as the mean
     time of a stratified sample per n times that n's count in the stream
     (answers of the sample are compared with the served ones); served vs
     plain from the cold and from the warm pass."""
+    import gc
+
     import numpy as np
     import torch
 
@@ -239,10 +308,8 @@ def serve_suite(tp, synth, count=2000):
     free, _ = torch.cuda.mem_get_info()
     budget = max(8 << 30, free - (48 << 30))
     unit = synth.serve_stream(seed=0, count=count, qps=1.0)
-    ex = serve.GpuExecutor(budget, slots=2)
-    srv = serve.Server(ex, max_wave=1024)
-    out = {"queries": count, "budget_bytes": int(budget), "slots": ex.nslots,
-           "lane_orders": sorted(srv.lane_n)}
+    out = {"queries": count, "budget_bytes": int(budget), "slots": 2,
+           "lane_orders": sorted(serve.LANE_ORDERS)}
 
     def lat_stats(reqs, prefix):
         lat = [r.latency for r in reqs]
@@ -253,28 +320,15 @@ def serve_suite(tp, synth, count=2000):
                 f"{prefix}_p99_ms": round(serve.percentile(lat, 99) * 1e3, 2),
                 f"{prefix}_p99_ms_by_n": {str(n): round(serve.percentile(v, 99) * 1e3, 1)
                                           for n, v in sorted(by_n.items())}}
-    try:
-        def burst():
-            t0 = time.perf_counter()
-            reqs = [srv.submit(n, m, t_arrive=t0) for _, n, m in unit]
-            for r in reqs:
-                r.wait(900)
-            return reqs, time.perf_counter() - t0
 
-        reqs, t_cold = burst()
-        note(f"serving: cold pass {t_cold:.1f} s")
-        served = {(r.n, r.m): r.gamma2 for r in reqs}
-        bad = [r for r in reqs if r.status != serve.TP_OK]
-        if bad:
-            print(f"serving failed: {bad[0].n} {bad[0].m} {bad[0].error}", file=sys.stderr)
-            sys.exit(1)
-        out.update(lat_stats(reqs, "cold_burst"))
-        reqs, t_warm = burst()
-        note(f"serving: warm pass {t_warm:.1f} s")
-        if any(r.status != serve.TP_OK or r.gamma2 != served[(r.n, r.m)] for r in reqs):
-            print("serving: warm pass differs from the cold pass", file=sys.stderr)
-            sys.exit(1)
-        qps = 0.7 * count / t_warm
+    def burst(srv):
+        t0 = time.perf_counter()
+        reqs = [srv.submit(n, m, t_arrive=t0) for _, n, m in unit]
+        for r in reqs:
+            r.wait(900)
+        return reqs, time.perf_counter() - t0
+
+    def replay(srv, qps):
         t0 = time.perf_counter()
         reqs = []
         for t, n, m in unit:
@@ -284,15 +338,35 @@ def serve_suite(tp, synth, count=2000):
             reqs.append(srv.submit(n, m))
         for r in reqs:
             r.wait(900)
-        t_replay = time.perf_counter() - t0
-        note(f"serving: replay {t_replay:.1f} s")
+        return reqs, time.perf_counter() - t0
+
+    def check(reqs, what):
         if any(r.status != serve.TP_OK or r.gamma2 != served[(r.n, r.m)] for r in reqs):
-            print("serving: replay differs from the cold pass", file=sys.stderr)
+            print(f"serving: {what} differs from the cold pass", file=sys.stderr)
             sys.exit(1)
+
+    ex = serve.GpuExecutor(budget, slots=2)
+    srv = serve.Server(ex, max_wave=1024)
+    try:
+        reqs, t_cold = burst(srv)
+        note(f"serving: cold pass {t_cold:.1f} s")
+        served = {(r.n, r.m): r.gamma2 for r in reqs}
+        bad = [r for r in reqs if r.status != serve.TP_OK]
+        if bad:
+            print(f"serving failed: {bad[0].n} {bad[0].m} {bad[0].error}", file=sys.stderr)
+            sys.exit(1)
+        out.update(lat_stats(reqs, "cold_burst"))
+        reqs, t_warm = burst(srv)
+        note(f"serving: warm pass {t_warm:.1f} s")
+        check(reqs, "warm pass")
+        qps = 0.7 * count / t_warm
+        reqs, t_replay = replay(srv, qps)
+        note(f"serving: warm replay {t_replay:.1f} s")
+        check(reqs, "warm replay")
         out.update({"saturation_qps_cold": round(count / t_cold, 1),
                     "saturation_qps_warm": round(count / t_warm, 1),
                     "replay_qps": round(qps, 1),
-                    "replay_seconds": round(t_replay, 1)})
+                    "replay_seconds": round(t_replay, 2)})
         out.update(lat_stats(reqs, "replay"))
         out.update({"waves": srv.waves, "max_waves_in_flight": srv.max_in_flight,
                     "resident_bytes": int(ex.resident_bytes()),
@@ -304,6 +378,26 @@ def serve_suite(tp, synth, count=2000):
     finally:
         srv.close()
         ex.close()
+    del srv, ex
+    gc.collect()
+    torch.cuda.empty_cache()
+    # a fresh server fed at 70 % of the cold saturation rate
+    ex = serve.GpuExecutor(budget, slots=2)
+    srv = serve.Server(ex, max_wave=1024)
+    try:
+        qps_c = 0.7 * count / t_cold
+        reqs, t_creplay = replay(srv, qps_c)
+        note(f"serving: cold replay {t_creplay:.1f} s")
+        check(reqs, "cold replay")
+        out.update({"cold_replay_qps": round(qps_c, 1),
+                    "cold_replay_seconds": round(t_creplay, 2)})
+        out.update(lat_stats(reqs, "cold_replay"))
+        out["cold_replay_max_waves_in_flight"] = srv.max_in_flight
+    finally:
+        srv.close()
+        ex.close()
+    del srv, ex
+    gc.collect()
     torch.cuda.empty_cache()
     # plain path on a stratified sample
     rng = np.random.default_rng(1)
@@ -342,6 +436,51 @@ def serve_suite(tp, synth, count=2000):
     return out
 
 
+def cyclic_suite(tp, nmax=200, ms=range(3, 9)):
+    """Small cycle, any path: gamma_2(P_n x C_m) for m = 3..8 and every
+    n = 1..nmax.  'plain' answers one query by tp_cyclic_walk_gamma2 (n - 1
+    dense vector-matrix products), timed on a sample of n per m and scaled to
+    the nmax queries of that m; 'sweep' answers all nmax of one m by a single
+    tp_cyclic_walk_sweep (one walk, every level read by the end vector).
+    Sampled plain answers are compared with the sweep's."""
+    import torch
+    total_plain, total_sweep, per_m = 0.0, 0.0, {}
+    for m in ms:
+        tp.tp_cyclic_walk_sweep(m, 2)  # the digraph of m in the library's cache
+        tp.tp_cyclic_walk_gamma2(2, m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sweep = tp.tp_cyclic_walk_sweep(m, nmax).cpu().numpy()
+        t_sweep = time.perf_counter() - t0
+        sample = sorted({1, nmax // 3, 2 * nmax // 3, nmax})
+        t0 = time.perf_counter()
+        for n in sample:
+            if tp.tp_cyclic_walk_gamma2(n, m) != int(sweep[n - 1]):
+                print(f"MISMATCH cyclic walk at ({n},{m})", file=sys.stderr)
+                sys.exit(1)
+        t_plain = (time.perf_counter() - t0) / len(sample) * nmax
+        total_plain += t_plain
+        total_sweep += t_sweep
+        per_m[str(m)] = {"N": tp.tp_cyclic_dim(m), "nnz": tp.tp_cyclic_nnz(m),
+                         "sweep_ms": round(t_sweep * 1e3, 3),
+                         "plain_ms_estimate": round(t_plain * 1e3, 2)}
+    q = nmax * len(list(ms))
+    return {"queries": q, "plain_qps_estimate": round(q / total_plain, 1),
+            "sweep_qps": round(q / total_sweep, 1),
+            "sweep_speedup": round(total_plain / total_sweep, 1), "by_m": per_m}
+
+
+def batch_roofline(work, ms):
+    """Aggregate position of a cold batch (chain levels, dense products and
+    traces between two events on its stream) against the packed-u16 VALU
+    peak and HBM."""
+    t = ms / 1e3
+    return {"bound": "alu", "achieved": round(work["ops"] / t / 1e12, 3),
+            "peak": round(PEAK_MINPLUS / 1e12, 3), "unit": "Tminplus-ops/s",
+            "frac": round(work["ops"] / t / PEAK_MINPLUS, 4),
+            "GBs_algorithmic": round(work["bytes"] / t / 1e9, 1)}
+
+
 def query_suite(tp, synth):
     """gamma_2 queries, plain per-query path vs batched (one persistent launch).
 
@@ -378,15 +517,22 @@ def query_suite(tp, synth):
             tp.tp_ctx_destroy(ctx)
         # cold: a fresh context (every power allocated and computed), median
         # of three; warm: the same batch again on the last context
-        t_colds = []
+        t_colds, dev_ms = [], []
         for rep in range(3):
             ctx = tp.tp_ctx_create(64 << 30)
             try:
                 torch.cuda.synchronize()
+                stream = torch.cuda.current_stream()
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
                 t0 = time.perf_counter()
-                res = tp.tp_batch_power_trace(ctx, ns, ms)
+                ev0.record(stream)
+                res = tp.tp_batch_power_trace(ctx, ns, ms, stream=stream)
+                ev1.record(stream)
                 tp.tp_ctx_check(ctx)
                 t_colds.append(time.perf_counter() - t0)
+                dev_ms.append(ev0.elapsed_time(ev1))
+                work = tp.tp_ctx_last_work(ctx)
                 cold = res.cpu().numpy().tolist()
                 if rep < 2:
                     continue
@@ -423,6 +569,9 @@ def query_suite(tp, synth):
                      "batched_warm_qps": round(k / t_warm, 1),
                      "fused_cold_qps": round(k / t_fused, 1),
                      "cold_speedup": round(t_plain / t_cold, 2),
+                     "cold_batch_device_ms": round(sorted(dev_ms)[1], 3),
+                     "cold_batch_work": {k: float(f"{v:.4g}") for k, v in work.items()},
+                     "cold_batch_roofline": batch_roofline(work, sorted(dev_ms)[1]),
                      "fused_cold_speedup": round(t_plain / t_fused, 2),
                      "warm_speedup": round(t_plain / t_warm, 2)}
         if name == "sweep_n8":

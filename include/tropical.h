@@ -500,6 +500,15 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
 int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *m,
                          int32_t *gamma2_dev, hipStream_t stream);
 
+/* The algorithmic work of the last batch queued on ctx, for roofline
+ * accounting: ops[0] = (min,+) operations of its chain levels (nnz(A(D_n)) * N
+ * per level computed), ops[1] = of its dense giant products (N^3 each),
+ * ops[2] = of its traces of products (N^2 per instance); *bytes = the bytes
+ * those must move at the least with 16-bit entries (4 N^2 per level, 6 N^2
+ * per product, 4 N^2 per trace, 2 N^2 for A^1).  Work that resident powers
+ * made unnecessary is not counted.  Host pointers; no GPU work. */
+int tp_ctx_last_work(void *ctx, double *ops, double *bytes);
+
 /* Waits for `stream` and reports whether the batches queued since the last
  * check completed: TP_OK, or TP_ECANCELED when a task's wait for its inputs
  * exceeded the wait limit (the kernel then drains without computing, the

@@ -102,6 +102,8 @@ def _load():
     lib.oracle_path_gamma2_sweep.restype = ctypes.c_int64
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.brute_is_2dominating.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
     lib.brute_is_2dominating.restype = ctypes.c_int
     lib.brute_gamma2.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -314,6 +316,12 @@ def path_gamma2_sweep(m: int, nmax: int, inf: int = INF16) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads the oracle's row-parallel loops use."""
     return int(_load().oracle_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads for the oracle's later calls (timing only; results do not
+    depend on it)."""
+    _load().oracle_set_threads(int(t))
 
 
 def brute_gamma2(n: int, m: int) -> int:

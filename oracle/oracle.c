@@ -53,6 +53,18 @@ int oracle_threads(void)
 #endif
 }
 
+/* sets the number of threads for later calls (a timing knob; no result
+ * depends on it) */
+void oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0)
+        omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* letters w[0..n-1] of a base-3 code, w[0] = p^1 (most significant) */
 static void decode(uint32_t code, int n, int *w)
 {

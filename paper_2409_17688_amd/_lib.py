@@ -123,6 +123,8 @@ _SIGS = {
     "tp_ctx_release": ([_p, _i, _p], _i),
     "tp_batch_power_trace": ([_p, _i, _p, _p, _p, _p], _i),
     "tp_ctx_check": ([_p, _p], _i),
+    "tp_ctx_last_work": ([_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                         _i),
     "tp_cyclic_dim": ([_i], _i64),
     "tp_cyclic_nnz": ([_i], _i64),
     "tp_cyclic_words": ([_i, _p, _p], _i),
@@ -836,3 +838,13 @@ def tp_cyclic_walk_sweep(m: int, nmax: int, out: torch.Tensor | None = None,
         raise ValueError("out must be a cuda int32 tensor of at least nmax entries")
     _check(lib.tp_cyclic_walk_sweep(m, nmax, out.data_ptr(), form, _stream(stream)))
     return out
+
+
+def tp_ctx_last_work(ctx) -> dict:
+    """Algorithmic work of the last batch queued on ctx: (min,+) operations of
+    its chain levels, dense products and traces, and their least bytes."""
+    ops = (ctypes.c_double * 3)()
+    nbytes = ctypes.c_double(0)
+    _check(lib.tp_ctx_last_work(ctx, ops, ctypes.byref(nbytes)))
+    return {"chain_ops": ops[0], "product_ops": ops[1], "trace_ops": ops[2],
+            "ops": ops[0] + ops[1] + ops[2], "bytes": nbytes.value}

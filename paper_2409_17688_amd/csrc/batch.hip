@@ -412,6 +412,9 @@ struct Ctx {
   int grid_override = 0;
   bool pending = false;                      // a batch was queued and not yet checked
   std::map<int, std::set<int>> pending_new;  // exponents that batch computes, by n
+  // algorithmic work of the last batch queued: (min,+) operations of its
+  // chain levels, dense products and traces, and their bytes (16-bit entries)
+  double work_ops[3] = {0, 0, 0}, work_bytes = 0;
   // buffers and graphs replaced while the context lives, freed with it
   std::vector<void *> retired_dev, retired_host;
   std::vector<hipGraphExec_t> retired_exec;
@@ -737,6 +740,30 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   }
   auto is_new_giant = [&](int s, int e) { return gbase.count({s, e}) != 0; };
   auto pending = [&](int s, int e) { return is_new_giant(s, e); };
+
+  // the batch's algorithmic work: a chain level nnz(A) * N operations over
+  // 4 N^2 bytes (X read, Y written), a dense product N^3 over 6 N^2, a trace
+  // N^2 over 4 N^2
+  c->work_ops[0] = c->work_ops[1] = c->work_ops[2] = 0;
+  c->work_bytes = 0;
+  for (int s = 0; s < nslots; ++s) {
+    const double N = (double)plans[s].view.N, nnz = (double)plans[s].view.nnz;
+    for (int k = std::max(k0[s], 2); k <= plans[s].chain_top; ++k) {
+      c->work_ops[0] += nnz * N;
+      c->work_bytes += 4 * N * N;
+    }
+    if (k0[s] <= 1 && plans[s].chain_top >= 1) c->work_bytes += 2 * N * N;  // A^1 written
+  }
+  for (const auto &kv : gbase) {
+    const double N = (double)plans[kv.first.first].view.N;
+    c->work_ops[1] += N * N * N;
+    c->work_bytes += 6 * N * N;
+  }
+  for (int j = 0; j < count; ++j) {
+    const double N = (double)plans[slot_of[ns[j]]].view.N;
+    c->work_ops[2] += N * N;
+    c->work_bytes += 4 * N * N;
+  }
 
   std::vector<Task> tasks;
   // dependency on rows [r0, r0 + 128) (all columns) of exponent e
@@ -1179,6 +1206,15 @@ int tp_batch_power_trace(void *ctx, int count, const int32_t *n, const int64_t *
   Ctx *c = (Ctx *)ctx;
   std::lock_guard<std::mutex> lk(c->mu);
   return batch_run(c, count, n, m, gamma2_dev, stream);
+}
+
+int tp_ctx_last_work(void *ctx, double *ops, double *bytes) {
+  TP_REQUIRE(ctx != nullptr && ops != nullptr && bytes != nullptr, "NULL pointer");
+  Ctx *c = (Ctx *)ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int i = 0; i < 3; ++i) ops[i] = c->work_ops[i];
+  *bytes = c->work_bytes;
+  return TP_OK;
 }
 
 int tp_tune_batch(int n, int baby_steps, int fused_baby_steps) {

@@ -290,3 +290,31 @@ def test_fused_batches_of_two_contexts_on_two_streams(tp, oracle_table):
     finally:
         for c in ctxs:
             tp.tp_ctx_destroy(c)
+
+
+def test_last_work_counts_what_the_batch_computes(tp):
+    """tp_ctx_last_work: a cold batch of one instance (n = 4, m = 5, baby
+    steps 16, so A^3 x A^2 closes it: levels 2 and 3 of the chain, no
+    product, one trace) counts 2 nnz N + N^2 operations and 2 N^2 + 2 * 4 N^2
+    + 4 N^2 bytes; the same batch again computes only its trace; a giant
+    adds N^3."""
+    say("last work")
+    N, nnz = tp.tp_state_dim(4), tp.tp_state_nnz(4)
+    ctx = tp.tp_ctx_create(1 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + 4, 16)
+        _run(tp, ctx, [(4, 5)])
+        w = tp.tp_ctx_last_work(ctx)
+        assert w["chain_ops"] == 2 * nnz * N and w["product_ops"] == 0
+        assert w["trace_ops"] == N * N
+        assert w["bytes"] == 2 * N * N + 2 * 4 * N * N + 4 * N * N
+        _run(tp, ctx, [(4, 5)])
+        w = tp.tp_ctx_last_work(ctx)
+        assert w["chain_ops"] == 0 and w["product_ops"] == 0 and w["trace_ops"] == N * N
+        # m = 40 > 2c: the pair (32, 8), giant 2 = A^16 x A^16 and the rest
+        # of the chain to A^16
+        _run(tp, ctx, [(4, 40)])
+        w = tp.tp_ctx_last_work(ctx)
+        assert w["product_ops"] == N ** 3 and w["chain_ops"] == 13 * nnz * N
+    finally:
+        tp.tp_ctx_destroy(ctx)
