@@ -198,9 +198,12 @@ int tp_minplus_spmm(int dtype, int64_t rows, int64_t K, const int64_t *d_rowptr,
 #define TP_STEP_AUTO 0    /* the tuned (or built-in) choice for n */
 #define TP_STEP_CSR 1     /* one wave per row gathering its successors' rows */
 #define TP_STEP_BLOCKED 2 /* the union of the successor lists of 16
-                           * consecutive rows, walked once per block and
-                           * applied to the rows that have each successor, so
+                           * consecutive rows, walked once per block a run of
+                           * successors shared by the same rows at a time (one
+                           * minimum per run, then applied to those rows), so
                            * each gathered row of X is read once per block */
+#define TP_STEP_BLOCKED_ENTRIES 3 /* the same union, each successor applied
+                                   * to its rows on its own */
 
 /* Y (N x ncols, u16) = A(D_n) x X (X: N x ncols, u16), N = tp_state_dim(n):
  * the left multiplication of Algorithm 2's power chain by the state matrix
@@ -305,8 +308,12 @@ int tp_compact_shared_select_trace(int64_t N, int64_t count, const int32_t *d_id
                                    const void *d_P, int64_t ldp, const int32_t *d_bp,
                                    int32_t *d_out, hipStream_t stream);
 
-/* Gathers per round in tp_compact_step and tp_compact_shared_step (4, the
- * default, or 8).  Changes speed only. */
+/* Gathers per round in tp_compact_step and tp_compact_shared_step (4 or 8),
+ * optionally | TP_COMPACT_GROUPED: the shared-base step then takes each row
+ * block's successors a mask group at a time (one minimum per run of
+ * successors shared by the same rows, then applied to those rows).  0
+ * restores the default, 4 | TP_COMPACT_GROUPED.  Changes speed only. */
+#define TP_COMPACT_GROUPED 0x100
 int tp_tune_compact_step(int unroll);
 
 /* All-pairs shortest paths by (min,+) squaring, the same semiring (Section 1)

@@ -34,10 +34,12 @@ TP_PARAM_BABY_STEPS = 32
 TP_STEP_AUTO = 0
 TP_STEP_CSR = 1
 TP_STEP_BLOCKED = 2
+TP_STEP_BLOCKED_ENTRIES = 3
 TP_WALK_AUTO = 0
 TP_WALK_CHAIN = 1
 TP_WALK_STEPS = 2
 TP_WALK_GEMV = 3
+TP_COMPACT_GROUPED = 0x100
 
 INF = {TP_U8: 255, TP_U16: 65535}
 

@@ -144,6 +144,46 @@ int get_state(int n, hipStream_t s, State **out) {
       TP_HIP_CHECK(hipMemcpyAsync(bp.data(), st.bptr.ptr, bp.size() * sizeof(int64_t),
                                   hipMemcpyDeviceToHost, s));
       TP_HIP_CHECK(hipStreamSynchronize(s));
+      // within each block, entries grouped by their row mask (then by p),
+      // the last entry of each group flagged in bit 48: rows with the same
+      // successors take one combined minimum per group (the grouped step);
+      // every other reader ignores the order and bit 48
+      if (nent > 0) {
+        std::vector<uint64_t> e((size_t)nent);
+        TP_HIP_CHECK(hipMemcpyAsync(e.data(), st.bent.ptr, e.size() * sizeof(uint64_t),
+                                    hipMemcpyDeviceToHost, s));
+        TP_HIP_CHECK(hipStreamSynchronize(s));
+        // groups in the order of their least successor, so a block still
+        // sweeps X roughly by increasing row (the rows it gathers come from
+        // HBM in fewer, longer runs)
+        auto key = [](uint64_t x) { return ((x >> 32) & 0xFFFFull) << 24 | (x & 0xFFFFFFull); };
+        std::vector<uint64_t> tmp;
+        std::vector<std::pair<uint64_t, int64_t>> runs;  // (least p, start), then its end
+        for (int64_t b = 0; b < nb; ++b) {
+          auto first = e.begin() + bp[b], last = e.begin() + bp[b + 1];
+          std::sort(first, last, [&](uint64_t a, uint64_t c) { return key(a) < key(c); });
+          runs.clear();
+          for (int64_t i = bp[b]; i < bp[b + 1]; ++i)
+            if (i == bp[b] || ((e[i - 1] ^ e[i]) >> 32 & 0xFFFFull) != 0)
+              runs.push_back({e[i] & 0xFFFFFFull, i});
+          std::vector<int64_t> ends(runs.size());
+          for (size_t g = 0; g < runs.size(); ++g)
+            ends[g] = g + 1 < runs.size() ? runs[g + 1].second : bp[b + 1];
+          std::vector<size_t> ord(runs.size());
+          for (size_t g = 0; g < ord.size(); ++g) ord[g] = g;
+          std::sort(ord.begin(), ord.end(),
+                    [&](size_t a, size_t c) { return runs[a].first < runs[c].first; });
+          tmp.clear();
+          for (size_t g : ord) {
+            for (int64_t i = runs[g].second; i < ends[g]; ++i) tmp.push_back(e[i]);
+            tmp.back() |= kGroupEnd;
+          }
+          std::copy(tmp.begin(), tmp.end(), first);
+        }
+        TP_HIP_CHECK(hipMemcpyAsync(st.bent.ptr, e.data(), e.size() * sizeof(uint64_t),
+                                    hipMemcpyHostToDevice, s));
+        TP_HIP_CHECK(hipStreamSynchronize(s));
+      }
       std::vector<int32_t> bo((size_t)nb);
       for (int64_t b = 0; b < nb; ++b) bo[b] = (int32_t)b;
       std::stable_sort(bo.begin(), bo.end(), [&](int32_t a, int32_t c) {
@@ -204,24 +244,28 @@ double g_spmm_rate[13] = {0, 1e10, 1e10, 2e10, 5e10, 1e11, 5e10, 2.5e11,
 double g_gemm_rate[13] = {0, 1e9, 1e9, 1e10, 5e10, 1e11, 3e11, 2e12,
                           1.45e13, 2.6e13, 3.37e13, 3.4e13, 3.4e13};
 // Form of the sparse left step by n when TP_STEP_AUTO is asked for (0: the
-// built-in rule, row blocks from n = 11 on, where they were measured faster:
-// at n = 12 53 ms against 101 ms per step; the CSR gather wins up to n = 10).
+// built-in rule, row blocks taken a mask group at a time from n = 8 on,
+// where they were measured faster: n = 12 40.7 ms against 101 ms for the
+// per-row gather, n = 10 0.51 against 0.92 ms, n = 9 0.057 against 0.104 ms
+// and n = 8 21 against 27 us with a workgroup's waves sharing each block;
+// the gather wins below).
 // Guarded by g_mu.
 int g_step_form[14] = {0};  // n = 1..13
 
 int step_form(int n, int form) {
   if (form != TP_STEP_AUTO) return form;
   if (g_step_form[n] != TP_STEP_AUTO) return g_step_form[n];
-  return n >= 11 ? TP_STEP_BLOCKED : TP_STEP_CSR;
+  return n >= 8 ? TP_STEP_BLOCKED : TP_STEP_CSR;
 }
 
 // Y = A(D_n) x X (u16) with the state's CSR or blocked form.  Caller holds g_mu.
 hipError_t state_step(const State *st, int form, const uint16_t *X, int64_t ldx, uint16_t *Y,
                       int64_t ldy, int64_t ncols, hipStream_t s) {
-  if (step_form(st->n, form) == TP_STEP_BLOCKED)
+  const int f = step_form(st->n, form);
+  if (f == TP_STEP_BLOCKED || f == TP_STEP_BLOCKED_ENTRIES)
     return launch_block_step(st->N, (const int64_t *)st->bptr.ptr,
                              (const uint64_t *)st->bent.ptr, (const int32_t *)st->border.ptr, X,
-                             ldx, Y, ldy, ncols, s);
+                             ldx, Y, ldy, ncols, f == TP_STEP_BLOCKED, s);
   if (state_gather_fits(X, ldx, Y, ldy, ncols))
     return launch_state_gather(st->N, (const int64_t *)st->rowptr.ptr,
                                (const uint32_t *)st->colz.ptr, (const int32_t *)st->order.ptr, X,
@@ -519,8 +563,9 @@ hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, u
     std::lock_guard<std::mutex> lk(g_mu);
     form = step_form(v.n, TP_STEP_AUTO);
   }
-  if (form == TP_STEP_BLOCKED)
-    return launch_block_step(v.N, v.bptr, v.bent, v.border, X, ldx, Y, ldy, ncols, s);
+  if (form == TP_STEP_BLOCKED || form == TP_STEP_BLOCKED_ENTRIES)
+    return launch_block_step(v.N, v.bptr, v.bent, v.border, X, ldx, Y, ldy, ncols,
+                             form == TP_STEP_BLOCKED, s);
   if (state_gather_fits(X, ldx, Y, ldy, ncols))
     return launch_state_gather(v.N, v.rowptr, v.colz, v.order, X, ldx, Y, ldy, ncols, s);
   return launch_spmm(TP_U16, v.N, v.rowptr, v.col, v.z, X, ldx, Y, ldy, ncols, s);
@@ -768,8 +813,10 @@ int tp_trace_of_product(int dtype, int64_t N, const void *d_X, int64_t ldx, cons
 int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, int64_t ldy,
                       int64_t ncols, hipStream_t stream) {
   TP_REQUIRE(n >= 1 && n <= 13, "n = %d outside 1..13", n);
-  TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED,
-             "form %d is not TP_STEP_AUTO, TP_STEP_CSR or TP_STEP_BLOCKED", form);
+  TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED ||
+                 form == TP_STEP_BLOCKED_ENTRIES,
+             "form %d is not TP_STEP_AUTO, TP_STEP_CSR, TP_STEP_BLOCKED or "
+             "TP_STEP_BLOCKED_ENTRIES", form);
   TP_REQUIRE(ncols >= 0, "negative size");
   TP_REQUIRE(ldx >= (ncols > 0 ? ncols : 1) && ldy >= (ncols > 0 ? ncols : 1),
              "leading dimension < ncols");
@@ -785,8 +832,10 @@ int tp_state_left_mul(int n, int form, const void *d_X, int64_t ldx, void *d_Y, 
 
 int tp_tune_step(int n, int form) {
   TP_REQUIRE(n >= 1 && n <= 12, "n = %d outside 1..12", n);
-  TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED,
-             "form %d is not TP_STEP_AUTO, TP_STEP_CSR or TP_STEP_BLOCKED", form);
+  TP_REQUIRE(form == TP_STEP_AUTO || form == TP_STEP_CSR || form == TP_STEP_BLOCKED ||
+                 form == TP_STEP_BLOCKED_ENTRIES,
+             "form %d is not TP_STEP_AUTO, TP_STEP_CSR, TP_STEP_BLOCKED or "
+             "TP_STEP_BLOCKED_ENTRIES", form);
   std::lock_guard<std::mutex> lk(g_mu);
   g_step_form[n] = form;
   return TP_OK;

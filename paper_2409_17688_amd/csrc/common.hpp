@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "tropical.h"
 
 namespace tp {
@@ -156,16 +158,21 @@ hipError_t launch_state_gather(int64_t rows, const int64_t *rowptr, const uint32
                                int64_t ldy, int64_t ncols, hipStream_t s);
 bool state_gather_fits(const void *X, int64_t ldx, const void *Y, int64_t ldy, int64_t ncols);
 
-// blockstep.hip: the sparse left step over blocks of 16 rows
+// blockstep.hip: the sparse left step over blocks of 16 rows.  An entry of a
+// block is p (bits 0..23), z_p (24..31), the mask of the block's rows that
+// have p as a successor (32..47) and, in bit 48, the end of a run of entries
+// with one mask (entries of a block are grouped by mask, then ordered by p)
+constexpr uint64_t kGroupEnd = 1ull << 48;
 int64_t block_count_host(int64_t N);
 hipError_t launch_block_count(int64_t N, int n, const uint32_t *masks, int64_t *bptr,
                               hipStream_t s);
 hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int64_t *bptr,
                              uint64_t *ent, hipStream_t s);
 // blocks in `border` (a permutation of the blocks) when it is not NULL
+// (grouped: the entries a mask group at a time)
 hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
                              const int32_t *border, const uint16_t *X, int64_t ldx, uint16_t *Y,
-                             int64_t ldy, int64_t ncols, hipStream_t s);
+                             int64_t ldy, int64_t ncols, bool grouped, hipStream_t s);
 
 // gemm.hip
 // config >= 0: that tile configuration with ksplit slices (>= 1); config < 0:
@@ -203,9 +210,14 @@ hipError_t launch_cyclic_strips(int64_t N, int64_t nnz, const int64_t *predptr,
 hipError_t launch_cyclic_chain(int64_t N, int64_t nnz, int64_t nmax, const uint32_t *strips,
                                const uint8_t *z, const uint16_t *start, const uint16_t *end,
                                int32_t *out, hipStream_t s);
-hipError_t launch_cyclic_step(int64_t N, const int64_t *predptr, const uint16_t *pred,
-                              const int32_t *order, const uint8_t *z, const uint16_t *end,
+// the step form's work items (predecessor lists cut into pieces, longest
+// lists first), as bytes to upload; returns their count
+int64_t cyclic_items_host(int64_t N, const int64_t *predptr, const int32_t *order,
+                          std::vector<char> *bytes);
+hipError_t launch_cyclic_step(int64_t N, int64_t nitems, const void *items, const uint16_t *pred,
+                              const uint8_t *z, const uint16_t *end, uint32_t *ym,
                               const uint16_t *x, uint16_t *y, int32_t *out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s);
 hipError_t launch_cyclic_answer(int64_t N, const uint16_t *x, const uint16_t *end, int32_t *out,
                                 hipStream_t s);
 // cyclic_api.hip: frees the cache of cyclic column digraphs

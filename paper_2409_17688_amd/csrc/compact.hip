@@ -38,7 +38,8 @@ constexpr int32_t kMaxGap = 0xFF00;      // largest offset gap inside a block
 constexpr int32_t kStatusRange = 1;      // a residual above 254 or a gap above kMaxGap
 constexpr int32_t kStatusMixed = 2;      // a row with finite and INF entries
 
-std::atomic<int> g_unroll{4};  // entries per round of the step (4 or 8)
+std::atomic<int> g_unroll{8};   // entries per round of the step (4 or 8)
+std::atomic<int> g_grouped{1};  // shared-base step: block entries a mask group at a time
 
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 #pragma unroll
@@ -315,7 +316,13 @@ __global__ void shared_prepare_kernel(const int32_t *bx, int32_t *by) {
   }
 }
 
-template <int U>
+// GROUPED: the block's entries a mask group at a time (the layout of
+// blockstep.hip): each entry's z_p + x[p] goes into one group minimum (4
+// packed mins per lane, no row tests) and the flagged last entry of a group
+// applies it to the rows of its mask.  At n = 12 the 5.2e6 block entries
+// form 8.2e4 groups, so the row tests and branches, which bound the kernel
+// entry at a time on the scalar unit, run once per 64 entries.
+template <int U, bool GROUPED>
 __global__ void __launch_bounds__(256) shared_step_kernel(
     int64_t N, const int64_t *__restrict__ bptr, const uint64_t *__restrict__ ent,
     const int32_t *__restrict__ border, const uint8_t *__restrict__ X, int64_t ldx,
@@ -341,6 +348,7 @@ __global__ void __launch_bounds__(256) shared_step_kernel(
   for (int r = 0; r < kRows; ++r)
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[r][k] = splat(0xFFFFu);
+  u16x2 g[4] = {splat(0xFFFFu), splat(0xFFFFu), splat(0xFFFFu), splat(0xFFFFu)};
 
   const int64_t e0 = bp[b], e1 = bp[b + 1];
   if (e0 < e1) {
@@ -350,7 +358,9 @@ __global__ void __launch_bounds__(256) shared_step_kernel(
       for (int u = 0; u < U; ++u) {
         const int64_t k = i + u;
         const uint64_t x = en[k < last ? k : last];
-        w[u] = k <= last ? x : (x & 0xFFFFFFFFull);  // past the end: no rows
+        // past the end: no rows and no group end (the last entry's group was
+        // applied, so what it adds to the group minimum is never used)
+        w[u] = k <= last ? x : (x & 0xFFFFFFFFull);
         v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ld8 + off];
       }
     };
@@ -360,7 +370,25 @@ __global__ void __launch_bounds__(256) shared_step_kernel(
         u16x2 row[4];
         unpack8(v[u].x, row[0], row[1]);
         unpack8(v[u].y, row[2], row[3]);
-        apply_entry(acc, (uint32_t)(w[u] >> 32), splat((uint16_t)((w[u] >> 24) & 0xFFu)), row);
+        const u16x2 lab = splat((uint16_t)((w[u] >> 24) & 0xFFu));
+        if constexpr (GROUPED) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) g[k] = pk_min(g[k], pk_add_sat(lab, row[k]));
+          if (w[u] & kGroupEnd) {
+            const uint32_t m = (uint32_t)(w[u] >> 32);
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+              if (m & (1u << r)) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[r][k] = pk_min(acc[r][k], g[k]);
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g[k] = splat(0xFFFFu);
+          }
+        } else {
+          apply_entry(acc, (uint32_t)(w[u] >> 32), lab, row);
+        }
       }
     };
     uint64_t wa[U], wb[U];
@@ -636,11 +664,18 @@ hipError_t launch_shared_step(const StateView &v, const uint8_t *X, int64_t ldx,
   const int64_t nblocks = (N + kRows - 1) / kRows;
   const int64_t panels = (ncols + 511) / 512;
   const dim3 grid((unsigned)(((nblocks + 3) / 4) * panels));
-  if (g_unroll == 8)
-    hipLaunchKernelGGL((shared_step_kernel<8>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
+  const bool grouped = g_grouped != 0, eight = g_unroll == 8;
+  if (grouped && eight)
+    hipLaunchKernelGGL((shared_step_kernel<8, true>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
+                       v.border, X, ldx, bx, Y, ldy, by, ncols, status);
+  else if (grouped)
+    hipLaunchKernelGGL((shared_step_kernel<4, true>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
+                       v.border, X, ldx, bx, Y, ldy, by, ncols, status);
+  else if (eight)
+    hipLaunchKernelGGL((shared_step_kernel<8, false>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
                        v.border, X, ldx, bx, Y, ldy, by, ncols, status);
   else
-    hipLaunchKernelGGL((shared_step_kernel<4>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
+    hipLaunchKernelGGL((shared_step_kernel<4, false>), grid, dim3(256), 0, s, N, v.bptr, v.bent,
                        v.border, X, ldx, bx, Y, ldy, by, ncols, status);
   return hipGetLastError();
 }
@@ -831,8 +866,11 @@ int tp_tune_compact_chains(int compact_from_n) {
 }
 
 int tp_tune_compact_step(int unroll) {
-  TP_REQUIRE(unroll == 4 || unroll == 8, "unroll %d is not 4 or 8", unroll);
-  g_unroll = unroll;
+  const int u = unroll & ~TP_COMPACT_GROUPED;
+  TP_REQUIRE(unroll == 0 || u == 4 || u == 8, "unroll %d is not 0, 4 or 8 (| TP_COMPACT_GROUPED)",
+             unroll);
+  g_unroll = unroll == 0 ? 8 : u;
+  g_grouped = unroll == 0 || (unroll & TP_COMPACT_GROUPED) != 0;
   return TP_OK;
 }
 

@@ -25,6 +25,7 @@
 // x_q, so a step is a gather-min over predecessor lists (kept as a CSR of
 // the columns of A, 16-bit indices: N < 65536 for m <= 12) and one add.
 #include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 
@@ -256,17 +257,30 @@ __global__ void __launch_bounds__(kChainThreads)
   if (tid == 0) out[0] = (int32_t)best;
   for (int64_t k = 2; k <= nmax; ++k) {
     __syncthreads();
+    // the strip's entries eight at a time: the loads first, then the LDS
+    // reads, then the column breaks (padding, 0xFFFFFFFF, only ends a strip
+    // and reads x[0xFFFF & ...] of no column: its column 0xFFFF never matches)
     uint32_t cur_p = 0xFFFFFFFFu, cur = 0xFFFFu;
-    for (int64_t i = 0; i < per; ++i) {
-      const uint32_t e = strips[i * kChainThreads + tid];
-      if (e == 0xFFFFFFFFu) break;  // padding only follows padding in a strip
-      const uint32_t p = e >> 16, v = x[e & 0xFFFFu];
-      if (p != cur_p) {
-        if (cur_p != 0xFFFFFFFFu) atomicMin(&y[cur_p], cur);
-        cur_p = p;
-        cur = v;
-      } else {
-        cur = min(cur, v);
+    for (int64_t i0 = 0; i0 < per; i0 += 8) {
+      uint32_t e[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        e[j] = i0 + j < per ? strips[(i0 + j) * kChainThreads + tid] : 0xFFFFFFFFu;
+      if (e[0] == 0xFFFFFFFFu) break;
+      uint32_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = e[j] == 0xFFFFFFFFu ? 0xFFFFu : (uint32_t)x[e[j] & 0xFFFFu];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (e[j] == 0xFFFFFFFFu) break;
+        const uint32_t p = e[j] >> 16;
+        if (p != cur_p) {
+          if (cur_p != 0xFFFFFFFFu) atomicMin(&y[cur_p], cur);
+          cur_p = p;
+          cur = v[j];
+        } else {
+          cur = min(cur, v[j]);
+        }
       }
     }
     if (cur_p != 0xFFFFFFFFu) atomicMin(&y[cur_p], cur);
@@ -283,29 +297,56 @@ __global__ void __launch_bounds__(kChainThreads)
   }
 }
 
-// One level of the walk as a full-chip launch: one wave per column p (in
-// `order`, longest predecessor list first), lanes stride the list;
-// y_p = z_p + min x_q, and the level's answer min_p y_p + end_p folds into
-// *out with one atomic per wave.
+// One level of the walk as two full-chip launches.  The predecessor lists
+// are cut into items of at most kItemLen entries (the all-zero word alone has
+// every word as a predecessor), one wave per item, longest lists first; a
+// wave gathers its item's x_q with all its loads in flight and folds the
+// least into ym[p] (32 bits, INF between levels) with one atomic.  Then
+// y_p = z_p + ym[p] (saturating), ym[p] goes back to INF, and the level's
+// answer min_p y_p + end_p folds into *out with one atomic per wave.
+struct WalkItem {
+  int64_t begin;
+  int32_t p, len;
+};
+
+constexpr int kItemLen = 256;
+
 __global__ void __launch_bounds__(256)
-    cyclic_step_kernel(int64_t N, const int64_t *__restrict__ predptr,
-                       const uint16_t *__restrict__ pred, const int32_t *__restrict__ order,
-                       const uint8_t *__restrict__ z, const uint16_t *__restrict__ end,
-                       const uint16_t *__restrict__ x, uint16_t *__restrict__ y,
-                       int32_t *__restrict__ out) {
+    cyclic_items_kernel(int64_t nitems, const WalkItem *__restrict__ items,
+                        const uint16_t *__restrict__ pred, const uint16_t *__restrict__ x,
+                        uint32_t *__restrict__ ym) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (w >= N) return;
-  const int64_t p = order ? order[w] : w;
-  uint32_t best = 0xFFFFu;
-  const int64_t b = predptr[p], e = predptr[p + 1];
-  for (int64_t i = b + lane; i < e; i += 64) best = min(best, (uint32_t)x[pred[i]]);
-  for (int off = 32; off > 0; off >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, off));
-  if (lane == 0) {
-    const uint32_t v = min(best + (uint32_t)z[p], 0xFFFFu);
-    y[p] = (uint16_t)v;
-    if (out) atomicMin(out, (int32_t)min(v + (uint32_t)end[p], 0xFFFFu));
+  if (w >= nitems) return;
+  const WalkItem it = items[w];
+  uint16_t q[kItemLen / 64];
+#pragma unroll
+  for (int j = 0; j < kItemLen / 64; ++j) {
+    const int i = lane + 64 * j;
+    q[j] = i < it.len ? pred[it.begin + i] : (uint16_t)0xFFFFu;
   }
+  uint32_t best = 0xFFFFu;
+#pragma unroll
+  for (int j = 0; j < kItemLen / 64; ++j)
+    if (q[j] != 0xFFFFu) best = min(best, (uint32_t)x[q[j]]);
+  for (int off = 32; off > 0; off >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, off));
+  if (lane == 0 && best < 0xFFFFu) atomicMin(&ym[it.p], best);
+}
+
+__global__ void __launch_bounds__(256)
+    cyclic_finish_kernel(int64_t N, const uint8_t *__restrict__ z,
+                         const uint16_t *__restrict__ end, uint32_t *__restrict__ ym,
+                         uint16_t *__restrict__ y, int32_t *__restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t best = 0xFFFFu;
+  if (p < N) {
+    const uint32_t v = min(ym[p] + (uint32_t)z[p], 0xFFFFu);
+    ym[p] = 0xFFFFu;
+    y[p] = (uint16_t)v;
+    best = min(v + (uint32_t)end[p], 0xFFFFu);
+  }
+  for (int off = 32; off > 0; off >>= 1) best = min(best, (uint32_t)__shfl_xor((int)best, off));
+  if ((threadIdx.x & 63) == 0 && best < 0xFFFFu) atomicMin(out, (int32_t)best);
 }
 
 // min_p x_p + end_p into *out (one workgroup; u16 vectors).
@@ -413,12 +454,34 @@ hipError_t launch_cyclic_chain(int64_t N, int64_t nnz, int64_t nmax, const uint3
   return hipGetLastError();
 }
 
-hipError_t launch_cyclic_step(int64_t N, const int64_t *predptr, const uint16_t *pred,
-                              const int32_t *order, const uint8_t *z, const uint16_t *end,
+int64_t cyclic_items_host(int64_t N, const int64_t *predptr, const int32_t *order,
+                          std::vector<char> *bytes) {
+  std::vector<WalkItem> items;
+  for (int64_t w = 0; w < N; ++w) {
+    const int32_t p = order[w];
+    for (int64_t b = predptr[p]; b < predptr[p + 1]; b += kItemLen)
+      items.push_back(WalkItem{b, p, (int32_t)std::min<int64_t>(kItemLen, predptr[p + 1] - b)});
+  }
+  bytes->assign((const char *)items.data(), (const char *)(items.data() + items.size()));
+  return (int64_t)items.size();
+}
+
+hipError_t launch_cyclic_step(int64_t N, int64_t nitems, const void *items, const uint16_t *pred,
+                              const uint8_t *z, const uint16_t *end, uint32_t *ym,
                               const uint16_t *x, uint16_t *y, int32_t *out, hipStream_t s) {
   if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(cyclic_step_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, N,
-                     predptr, pred, order, z, end, x, y, out);
+  if (nitems > 0)
+    hipLaunchKernelGGL(cyclic_items_kernel, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s,
+                       nitems, (const WalkItem *)items, pred, x, ym);
+  hipLaunchKernelGGL(cyclic_finish_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N,
+                     z, end, ym, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p,
+                     count, v);
   return hipGetLastError();
 }
 

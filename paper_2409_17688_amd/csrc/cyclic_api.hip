@@ -52,6 +52,8 @@ struct Cyc {
   int m = 0;
   int64_t N = 0, nnz = -1, ld = 0;
   Buf masks, z, predptr, pred, order, strips, start, end, dense, vec[2], scalar;
+  Buf items, ym;  // the step form's work items and 32-bit level minima
+  int64_t nitems = 0;
   bool dense_ready = false;
 };
 
@@ -67,8 +69,10 @@ int device_now() {
 // Largest N whose walk runs inside one workgroup (x in 16 bits and the
 // gathered minima in 32 bits, in 64 KB of LDS with room for the reduction).
 constexpr int64_t kChainMaxN = (65536 - 1024) / 6;
-// Arcs up to which the one-workgroup walk beats a launch per level.
-constexpr int64_t kChainMaxNnz = 1 << 18;
+// Arcs up to which the one-workgroup walk beats two launches per level
+// (measured per level: m = 7, 21,080 arcs: 4.1 against 5.4 us; m = 8, 86,855
+// arcs: 13.5 against 5.5 us).
+constexpr int64_t kChainMaxNnz = 1 << 15;
 
 int get_cyc(int m, hipStream_t s, Cyc **out) {
   Cyc &c = g_cyc[{device_now(), m}];
@@ -108,6 +112,13 @@ int get_cyc(int m, hipStream_t s, Cyc **out) {
     TP_HIP_CHECK(grow(c.order, N * sizeof(int32_t)));
     TP_HIP_CHECK(hipMemcpyAsync(c.order.ptr, ord.data(), ord.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, s));
+    std::vector<char> items;
+    c.nitems = cyclic_items_host(N, pp.data(), ord.data(), &items);
+    TP_HIP_CHECK(grow(c.items, std::max<size_t>(items.size(), 16)));
+    if (!items.empty())
+      TP_HIP_CHECK(hipMemcpyAsync(c.items.ptr, items.data(), items.size(), hipMemcpyHostToDevice,
+                                  s));
+    TP_HIP_CHECK(grow(c.ym, N * sizeof(uint32_t)));
     if (N <= kChainMaxN) {
       const int64_t per = cyclic_strip_length(nnz);
       TP_HIP_CHECK(grow(c.strips, (size_t)per * 1024 * sizeof(uint32_t)));
@@ -143,10 +154,9 @@ int walk_levels(Cyc *c, int64_t nmax, int form, int32_t *out, hipStream_t s) {
       TP_HIP_CHECK(launch_gemv(TP_U16, N, N, c->dense.ptr, c->ld, x, y, 1, s));
       TP_HIP_CHECK(launch_cyclic_answer(N, y, (const uint16_t *)c->end.ptr, out + (k - 1), s));
     } else {
-      TP_HIP_CHECK(launch_cyclic_step(N, (const int64_t *)c->predptr.ptr,
-                                      (const uint16_t *)c->pred.ptr, (const int32_t *)c->order.ptr,
-                                      (const uint8_t *)c->z.ptr, (const uint16_t *)c->end.ptr, x,
-                                      y, out + (k - 1), s));
+      TP_HIP_CHECK(launch_cyclic_step(N, c->nitems, c->items.ptr, (const uint16_t *)c->pred.ptr,
+                                      (const uint8_t *)c->z.ptr, (const uint16_t *)c->end.ptr,
+                                      (uint32_t *)c->ym.ptr, x, y, out + (k - 1), s));
     }
     std::swap(x, y);
   }
@@ -165,7 +175,7 @@ void cyclic_release_cache() {
   for (auto &kv : g_cyc) {
     Cyc &c = kv.second;
     for (Buf *b : {&c.masks, &c.z, &c.predptr, &c.pred, &c.order, &c.strips, &c.start, &c.end,
-                   &c.dense, &c.vec[0], &c.vec[1], &c.scalar})
+                   &c.dense, &c.vec[0], &c.vec[1], &c.scalar, &c.items, &c.ym})
       drop(*b);
   }
   g_cyc.clear();
@@ -289,6 +299,8 @@ int tp_cyclic_walk_sweep(int m, int64_t nmax, int32_t *d_gamma2, int form, hipSt
     if (rc != TP_OK) return rc;
   }
   TP_HIP_CHECK(launch_fill_i32(d_gamma2, nmax, 0xFFFF, stream));
+  if (f == TP_WALK_STEPS)
+    TP_HIP_CHECK(launch_fill_u32((uint32_t *)c->ym.ptr, c->N, 0xFFFFu, stream));
   TP_HIP_CHECK(hipMemcpyAsync(c->vec[0].ptr, c->start.ptr, (size_t)c->N * sizeof(uint16_t),
                               hipMemcpyDeviceToDevice, stream));
   TP_HIP_CHECK(launch_cyclic_answer(c->N, (const uint16_t *)c->vec[0].ptr,

@@ -10,6 +10,8 @@
     python -m paper_2409_17688_amd.kernel_bench --op recurrence --n 12 --window 4
     python -m paper_2409_17688_amd.kernel_bench --op apsp --N 8192
     python -m paper_2409_17688_amd.kernel_bench --op cstep --n 12 --reps 5
+    python -m paper_2409_17688_amd.kernel_bench --op gemv --m 12 --trans 1
+    python -m paper_2409_17688_amd.kernel_bench --op walk --m 8 --nmax 256 --form 1
 
 Matrices use the library's resident layout (rows padded to 64 entries).
 Times come from HIP events on the launch stream; one JSON line per run with
@@ -30,6 +32,11 @@ the algorithmic work of one launch:
   apsp   all-pairs shortest paths on a random digraph of order N (weights
          0..49 on 1 % of the pairs, default_rng(0)): ceil(log2(N-1)) dense
          products of N^3 operations
+  gemv   one (min,+) vector-matrix (--trans 1) or matrix-vector product with
+         the cyclic column digraph's matrix of cycle order m (16 bits, rows
+         padded to 64 entries): 2 N^2 bytes of matrix read per launch
+  walk   tp_cyclic_walk_sweep(m, nmax, form): the walk along the path over
+         cyclic columns, every level read by the end vector; nnz per level
 """
 from __future__ import annotations
 
@@ -60,7 +67,8 @@ def _padded(torch, N):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--op", choices=["spmm", "bstep", "gather", "trace", "gemm", "batch", "cdiff",
-                                     "recurrence", "apsp", "cstep"], required=True)
+                                     "recurrence", "apsp", "cstep", "gemv", "walk"],
+                    required=True)
     ap.add_argument("--n", type=int, default=10)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--config", type=int, default=None, help="dense product tile config")
@@ -70,8 +78,15 @@ def main(argv=None):
     ap.add_argument("--K", type=int, default=50, help="recurrence: powers computed")
     ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
     ap.add_argument("--N", type=int, default=8192, help="apsp: order of the digraph")
-    ap.add_argument("--unroll", type=int, default=4, help="cstep: gathers per round (4 or 8)")
+    ap.add_argument("--unroll", type=int, default=0,
+                    help="cstep: gathers per round (4 or 8, | 256 for mask groups; 0: default)")
     ap.add_argument("--shared", action="store_true", help="cstep: one base per power")
+    ap.add_argument("--entries", action="store_true",
+                    help="bstep: each block entry applied on its own (not by mask group)")
+    ap.add_argument("--m", type=int, default=12, help="gemv, walk: cycle order")
+    ap.add_argument("--trans", type=int, default=1, help="gemv: 1 = x A, 0 = A x")
+    ap.add_argument("--nmax", type=int, default=256, help="walk: path orders swept")
+    ap.add_argument("--form", type=int, default=0, help="walk: TP_WALK_* form")
     args = ap.parse_args(argv)
 
     import torch
@@ -79,7 +94,34 @@ def main(argv=None):
     from . import _lib as tp
     n = args.n
     out = {"op": args.op}
-    if args.op == "apsp":
+    if args.op == "gemv":
+        m = args.m
+        N = tp.tp_cyclic_dim(m)
+        A = _padded(torch, N)
+        tp.tp_build_cyclic_matrix(m, tp.TP_U16, out=A)
+        x, _ = tp.tp_build_cyclic_boundary(m, tp.TP_U16)
+        y = torch.empty_like(x)
+        t = _events(torch, lambda: tp.tp_minplus_gemv(A, x, trans=bool(args.trans), y=y),
+                    args.reps)
+        nbytes = 2.0 * N * N + 4.0 * N
+        out.update({"m": m, "N": N, "trans": args.trans, "ms": t * 1e3, "bytes": nbytes,
+                    "GBs": nbytes / t / 1e9})
+    elif args.op == "walk":
+        m = args.m
+        out_t = torch.empty(args.nmax, dtype=torch.int32, device="cuda")
+        tp.tp_cyclic_walk_sweep(m, args.nmax, out_t, form=args.form)
+        times = []
+        for _ in range(args.reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tp.tp_cyclic_walk_sweep(m, args.nmax, out_t, form=args.form)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = min(times)
+        out.update({"m": m, "N": tp.tp_cyclic_dim(m), "nnz": tp.tp_cyclic_nnz(m),
+                    "nmax": args.nmax, "form": args.form, "ms": t * 1e3,
+                    "us_per_level": t / max(args.nmax - 1, 1) * 1e6})
+    elif args.op == "apsp":
         import numpy as np
         N = args.N
         rng = np.random.default_rng(0)
@@ -147,6 +189,8 @@ def main(argv=None):
         elif args.op in ("bstep", "gather"):
             nnz = tp.tp_state_nnz(n)
             form = tp.TP_STEP_BLOCKED if args.op == "bstep" else tp.TP_STEP_CSR
+            if args.op == "bstep" and args.entries:
+                form = tp.TP_STEP_BLOCKED_ENTRIES
             t = _events(torch, lambda: tp.tp_state_left_mul(n, X, Y, form=form), args.reps)
             out.update({"nnz": nnz, "ms": t * 1e3, "Tminplus_ops": nnz * N / t / 1e12})
         elif args.op == "cdiff":

@@ -102,7 +102,7 @@ def test_compact_chain_matches_u16_chain(tp, n, ncols, unroll):
             X8, Y8, RX, RY = Y8, X8, RY, RX
             assert torch.equal(tp.tp_compact_to_u16(X8, RX, ncols), X), (n, ncols, k)
     finally:
-        tp.tp_tune_compact_step(4)
+        tp.tp_tune_compact_step(0)
     assert int(st.item()) == 0
 
 
@@ -289,8 +289,12 @@ def test_shared_chain_matches_oracle_powers(tp, oracle_mod, n):
 
 
 @pytest.mark.parametrize("n,ncols,unroll", [(8, 1386, 4), (8, 700, 8), (8, 13, 4),
-                                            (9, 3447, 8), (11, 2100, 4)])
+                                            (9, 3447, 8), (11, 2100, 4), (8, 1386, 0x104),
+                                            (8, 13, 0x108), (9, 3447, 0x104), (11, 2100, 0x108),
+                                            (12, 600, 0x104)])
 def test_shared_chain_matches_u16_chain(tp, n, ncols, unroll):
+    """Chains of the shared-base step (entry at a time, 4 or 8 per round, or
+    a mask group at a time: 0x100 | U) equal the 16-bit chain."""
     import torch
     N = tp.tp_state_dim(n)
     A = _padded16(N)
@@ -310,7 +314,7 @@ def test_shared_chain_matches_u16_chain(tp, n, ncols, unroll):
             X8, Y8, bx, by = Y8, X8, by, bx
             assert torch.equal(tp.tp_compact_shared_to_u16(X8, bx, ncols), X), (n, ncols, k)
     finally:
-        tp.tp_tune_compact_step(4)
+        tp.tp_tune_compact_step(0)
     assert int(st.item()) == 0
 
 

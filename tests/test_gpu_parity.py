@@ -220,6 +220,38 @@ def test_gemv(tp, oracle_mod, dtype):
             assert np.array_equal(yt, reft), ("x A", M, K, dist)
 
 
+@pytest.mark.parametrize("M,K", [(1, 8), (7, 9), (130, 512), (517, 1031), (1000, 4104),
+                                 (3, 20000), (2049, 64)])
+def test_gemv_padded_rows(tp, oracle_mod, M, K):
+    """16-bit rows padded to 64 entries (the 16-byte path of both forms),
+    ragged M and K around the 8-entry chunks and 512-column stretches, values
+    that saturate; then the same with vectors one entry off alignment (the
+    element-wise path): both == the oracle."""
+    seed = 1000 + M + K
+    for lo, hi, frac in ((0, 30000, 0.3), (32000, 33000, 0.0), (0, 40, 0.9)):
+        A = synth.stress_matrix(M, K, seed, lo, hi, frac, np.uint16)
+        x = synth.stress_matrix(1, K, seed + 1, lo, hi, frac, np.uint16)[0]
+        xt = synth.stress_matrix(1, M, seed + 2, lo, hi, frac, np.uint16)[0]
+        seed += 3
+        ld = (K + 63) // 64 * 64
+        Ap = np.full((M, ld), 7, dtype=np.uint16)
+        Ap[:, :K] = A
+        Ad = dev(Ap)
+        ref = oracle_mod.minplus(A.astype(np.int32), x.astype(np.int32)[:, None])[:, 0]
+        reft = oracle_mod.minplus(xt.astype(np.int32)[None, :], A.astype(np.int32))[0]
+        say("gemv padded", M, K, lo, hi, frac)
+        for off in (0, 1):
+            xp = np.zeros(K + 8, dtype=np.uint16)
+            xp[off:off + K] = x
+            xtp = np.zeros(M + 8, dtype=np.uint16)
+            xtp[off:off + M] = xt
+            xb, xtb = dev(xp), dev(xtp)
+            y = host(tp.tp_minplus_gemv(Ad[:, :K], xb[off:off + K])).astype(np.int32)
+            assert np.array_equal(y, ref), ("A x", M, K, off)
+            yt = host(tp.tp_minplus_gemv(Ad[:, :K], xtb[off:off + M], trans=True)).astype(np.int32)
+            assert np.array_equal(yt, reft), ("x A", M, K, off)
+
+
 # ------------------------------------------------------------------- spmm --
 
 @pytest.mark.parametrize("dtype", [2, 1])
@@ -265,18 +297,20 @@ def test_state_left_mul_matches_oracle(tp, oracle_mod):
                 X = synth.stress_matrix(N, ncols, n * 1000 + ncols, lo, hi, frac, np.uint16)
                 ref = oracle_mod.minplus(A, X.astype(np.int32))
                 say("state_left_mul", n, ncols, dist)
-                for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_CSR, tp.TP_STEP_AUTO):
+                for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_BLOCKED_ENTRIES, tp.TP_STEP_CSR,
+                             tp.TP_STEP_AUTO):
                     got = host(tp.tp_state_left_mul(n, dev(X), form=form)).astype(np.int32)
                     assert np.array_equal(got, ref), (n, ncols, dist, form)
                 # padded rows (16-byte aligned) and a Y view inside a larger buffer
                 ld = (ncols + 63) // 64 * 64 + 64
                 Xp = torch.zeros((N, ld), dtype=torch.uint16, device="cuda")
                 Xp[:, :ncols] = dev(X)
-                Yp = torch.full((N, ld), 7, dtype=torch.uint16, device="cuda")
-                tp.tp_state_left_mul(n, Xp[:, :ncols], Yp[:, :ncols], form=tp.TP_STEP_BLOCKED)
-                got = host(Yp).astype(np.int32)
-                assert np.array_equal(got[:, :ncols], ref), (n, ncols, dist, "padded")
-                assert (got[:, ncols:] == 7).all(), "wrote outside Y"
+                for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_BLOCKED_ENTRIES):
+                    Yp = torch.full((N, ld), 7, dtype=torch.uint16, device="cuda")
+                    tp.tp_state_left_mul(n, Xp[:, :ncols], Yp[:, :ncols], form=form)
+                    got = host(Yp).astype(np.int32)
+                    assert np.array_equal(got[:, :ncols], ref), (n, ncols, dist, "padded", form)
+                    assert (got[:, ncols:] == 7).all(), "wrote outside Y"
 
 
 def test_state_left_mul_large_n_sampled(tp, oracle_mod):
@@ -288,7 +322,7 @@ def test_state_left_mul_large_n_sampled(tp, oracle_mod):
     X = synth.stress_matrix(N, 300, 10, 0, 30000, 0.3, np.uint16)
     rows = np.sort(rng.choice(N, 64, replace=False))
     ref = oracle_mod.minplus(A10[rows], X.astype(np.int32))
-    for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_CSR):
+    for form in (tp.TP_STEP_BLOCKED, tp.TP_STEP_BLOCKED_ENTRIES, tp.TP_STEP_CSR):
         got = host(tp.tp_state_left_mul(10, dev(X), form=form)).astype(np.int32)
         assert np.array_equal(got[rows], ref), form
     for n in (11, 12):
@@ -312,7 +346,7 @@ def test_state_left_mul_rejects_bad_arguments(tp):
     assert tp.lib.tp_state_left_mul(14, 0, p, 5, p, 5, 5, None) == tp.TP_EINVAL
     assert tp.lib.tp_state_left_mul(0, 0, p, 5, p, 5, 5, None) == tp.TP_EINVAL
     assert tp.lib.tp_state_left_mul(4, 0, p, 4, p, 5, 5, None) == tp.TP_EINVAL
-    assert tp.lib.tp_state_left_mul(4, 3, p, 5, p, 5, 5, None) == tp.TP_EINVAL
+    assert tp.lib.tp_state_left_mul(4, 4, p, 5, p, 5, 5, None) == tp.TP_EINVAL
 
 
 # ----------------------------------------------------------------- traces --

@@ -81,7 +81,7 @@ def test_u16_step_sampled_rows_vs_oracle(tp, oracle_mod, n, dist):
     Xd = dev16(X)
     Xp = padded(N, NCOLS, Xd.dtype)
     Xp.copy_(Xd)
-    forms = [tp.TP_STEP_BLOCKED, tp.TP_STEP_CSR, tp.TP_STEP_AUTO]
+    forms = [tp.TP_STEP_BLOCKED, tp.TP_STEP_BLOCKED_ENTRIES, tp.TP_STEP_CSR, tp.TP_STEP_AUTO]
     for form in forms:
         for src in (Xd, Xp):
             Y = padded(N, NCOLS, Xd.dtype) if src is Xp else None
@@ -109,13 +109,13 @@ def test_shared_base_step_sampled_rows_vs_oracle(tp, oracle_mod, n, lo, hi, base
     bx = torch.from_numpy(word).cuda()
     by = torch.zeros(2, dtype=torch.int32, device="cuda")
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    for unroll in (4, 8):
+    for unroll in (4, 8, 4 | tp.TP_COMPACT_GROUPED, 8 | tp.TP_COMPACT_GROUPED):
         tp.tp_tune_compact_step(unroll)
         try:
             Y8.fill_(0xEE)
             tp.tp_compact_shared_step(n, X8, bx, NCOLS, Y8, by, st)
         finally:
-            tp.tp_tune_compact_step(4)
+            tp.tp_tune_compact_step(0)
         assert int(st.item()) == 0, (n, unroll)
         g = int(by[0].item())
         got = rows_of(Y8, rows) + g
