@@ -489,6 +489,15 @@ int64_t tp_ctx_resident_bytes(void *ctx);
  * waiting for the work queued on `stream`. */
 int tp_ctx_release(void *ctx, int n, hipStream_t stream);
 
+/* Copies the resident power A(D_n)^e of a context (Section 2.2's state
+ * matrix raised in the (min,+) semiring, as the context's batches computed
+ * it) into d_out: device u16, N rows padded to ld >= N entries, N =
+ * tp_state_dim(n); on `stream`, after the work queued there (a batch that
+ * computes the power must be queued on the same stream or finished).
+ * TP_EINVAL when the context holds no such power or ld < N.  The caller owns
+ * d_out. */
+int tp_ctx_copy_power(void *ctx, int n, int e, void *d_out, int64_t ld, hipStream_t stream);
+
 /* Bytes of powers a batch of these instances would add to the context (0
  * when everything it needs is resident); for admission control. */
 int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t *m);

@@ -123,6 +123,7 @@ _SIGS = {
     "tp_ctx_resident_bytes": ([_p], _i64),
     "tp_ctx_need_bytes": ([_p, _i, _p, _p], _i64),
     "tp_ctx_release": ([_p, _i, _p], _i),
+    "tp_ctx_copy_power": ([_p, _i, _i, _p, _i64, _p], _i),
     "tp_batch_power_trace": ([_p, _i, _p, _p, _p, _p], _i),
     "tp_ctx_check": ([_p, _p], _i),
     "tp_ctx_last_work": ([_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
@@ -745,6 +746,20 @@ def tp_ctx_resident_bytes(ctx: int) -> int:
 
 def tp_ctx_release(ctx: int, n: int = 0, stream=None) -> None:
     _check(lib.tp_ctx_release(ctx, int(n), _stream(stream)))
+
+
+def tp_ctx_copy_power(ctx: int, n: int, e: int, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """The context's resident power A(D_n)^e as a device uint16 tensor of
+    shape (N, N) (or into `out`, rows of stride >= N)."""
+    N = tp_state_dim(n)
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.uint16, device="cuda")
+    po, rows, ncols, ld = _mat(out, "out")
+    if (rows, ncols) != (N, N) or out.dtype != torch.uint16:
+        raise ValueError(f"out must be uint16 of shape ({N}, {N})")
+    _check(lib.tp_ctx_copy_power(ctx, int(n), int(e), po, ld, _stream(stream)))
+    return out
 
 
 def tp_ctx_need_bytes(ctx: int, ns, ms) -> int:

@@ -85,6 +85,11 @@ struct State {
   std::vector<int32_t> degh;              // out-degrees on the host
   std::map<int, DevBuf> sel;              // states with <= k zeros (device int32), by k
   std::map<int, int64_t> sel_count;
+  // row blocks cut by rows into parts (the small-n step, the batch kernel's
+  // chain levels)
+  DevBuf fptr, fent, finfo, forder;
+  std::vector<int64_t> fptrh;
+  bool fine_ready = false;
 };
 
 struct Workspace {
@@ -102,8 +107,24 @@ int current_device() {
   return d;
 }
 
+int build_fine(State &st, hipStream_t s);
+
+// The parts of a state as the step launchers take them (nf = 0: not built).
+FineView fine_of(const State &st) {
+  FineView f{};
+  if (!st.fine_ready) return f;
+  f.nf = (int64_t)st.fptrh.size() - 1;
+  f.fptr = (const int64_t *)st.fptr.ptr;
+  f.fent = (const uint64_t *)st.fent.ptr;
+  f.finfo = (const uint32_t *)st.finfo.ptr;
+  f.forder = (const int32_t *)st.forder.ptr;
+  f.fptrh = st.fptrh.data();
+  return f;
+}
+
 // Builds masks, zero counts and the CSR of A(D_n) on `s` (blocking only
-// for the arc count, which sizes the column array).  Caller holds g_mu.
+// for the arc count, which sizes the column array), and for n <= 10 the
+// row-block parts of the small-n step.  Caller holds g_mu.
 int get_state(int n, hipStream_t s, State **out) {
   State &st = g_states[{current_device(), n}];
   if (!st.csr_ready) {
@@ -223,6 +244,10 @@ int get_state(int n, hipStream_t s, State **out) {
       TP_HIP_CHECK(hipStreamSynchronize(s));
     }
     st.csr_ready = true;
+    if (n <= 10) {
+      const int rc = build_fine(st, s);
+      if (rc != TP_OK) return rc;
+    }
   }
   *out = &st;
   return TP_OK;
@@ -262,10 +287,12 @@ int step_form(int n, int form) {
 hipError_t state_step(const State *st, int form, const uint16_t *X, int64_t ldx, uint16_t *Y,
                       int64_t ldy, int64_t ncols, hipStream_t s) {
   const int f = step_form(st->n, form);
-  if (f == TP_STEP_BLOCKED || f == TP_STEP_BLOCKED_ENTRIES)
+  if (f == TP_STEP_BLOCKED || f == TP_STEP_BLOCKED_ENTRIES) {
+    const FineView fine = fine_of(*st);
     return launch_block_step(st->N, (const int64_t *)st->bptr.ptr,
-                             (const uint64_t *)st->bent.ptr, (const int32_t *)st->border.ptr, X,
-                             ldx, Y, ldy, ncols, f == TP_STEP_BLOCKED, s);
+                             (const uint64_t *)st->bent.ptr, (const int32_t *)st->border.ptr,
+                             &fine, X, ldx, Y, ldy, ncols, f == TP_STEP_BLOCKED, s);
+  }
   if (state_gather_fits(X, ldx, Y, ldy, ncols))
     return launch_state_gather(st->N, (const int64_t *)st->rowptr.ptr,
                                (const uint32_t *)st->colz.ptr, (const int32_t *)st->order.ptr, X,
@@ -564,11 +591,132 @@ hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, u
     form = step_form(v.n, TP_STEP_AUTO);
   }
   if (form == TP_STEP_BLOCKED || form == TP_STEP_BLOCKED_ENTRIES)
-    return launch_block_step(v.N, v.bptr, v.bent, v.border, X, ldx, Y, ldy, ncols,
+    return launch_block_step(v.N, v.bptr, v.bent, v.border, &v.fine, X, ldx, Y, ldy, ncols,
                              form == TP_STEP_BLOCKED, s);
   if (state_gather_fits(X, ldx, Y, ldy, ncols))
     return launch_state_gather(v.N, v.rowptr, v.colz, v.order, X, ldx, Y, ldy, ncols, s);
   return launch_spmm(TP_U16, v.N, v.rowptr, v.col, v.z, X, ldx, Y, ldy, ncols, s);
+}
+
+namespace {
+
+// Parts of the row blocks, for the steps that give each (part, 256-column
+// panel) to one workgroup, whose waves split the part's entries, so the
+// longest part bounds the step.  A block with more than T entries is cut
+// into runs of consecutive rows, each run as long as its successors' union
+// stays within T (a single row with more successors is a part of its own);
+// a part keeps the block's entries that reach its rows, with their masks cut
+// to those rows and grouped again by mask.  T is half the longest block (at
+// least 128): the longest runs of entries halve, for about a third more
+// entries in all (n = 8, 9; the rows of a block share most successors).
+int build_fine(State &st, hipStream_t s) {
+  const int64_t N = st.N, nb = (N + 15) / 16, nent = st.nent;
+  std::vector<int64_t> bp((size_t)nb + 1);
+  std::vector<uint64_t> e((size_t)std::max<int64_t>(nent, 1));
+  TP_HIP_CHECK(hipMemcpyAsync(bp.data(), st.bptr.ptr, bp.size() * sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
+  if (nent > 0)
+    TP_HIP_CHECK(hipMemcpyAsync(e.data(), st.bent.ptr, (size_t)nent * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, s));
+  TP_HIP_CHECK(hipStreamSynchronize(s));
+  int64_t longest = 0;
+  for (int64_t b = 0; b < nb; ++b) longest = std::max(longest, bp[b + 1] - bp[b]);
+  const int64_t T = std::max<int64_t>(128, longest / 2);
+  std::vector<int64_t> fp(1, 0);
+  std::vector<uint64_t> fe;
+  std::vector<uint32_t> fi;
+  std::vector<uint64_t> tmp;
+  auto mask_of = [](uint64_t x) { return (uint32_t)((x >> 32) & 0xFFFFull); };
+  auto emit = [&](int64_t b, uint32_t part) {
+    // the block's entries that reach these rows, masks cut to them, grouped
+    // by mask (groups in the order of their least successor)
+    tmp.clear();
+    for (int64_t i = bp[b]; i < bp[b + 1]; ++i) {
+      const uint32_t m = mask_of(e[i]) & part;
+      if (m) tmp.push_back((e[i] & 0xFFFFFFFFull) | ((uint64_t)m << 32));
+    }
+    std::sort(tmp.begin(), tmp.end(), [&](uint64_t a, uint64_t c) {
+      const uint64_t ka = (uint64_t)mask_of(a) << 24 | (a & 0xFFFFFFull);
+      const uint64_t kc = (uint64_t)mask_of(c) << 24 | (c & 0xFFFFFFull);
+      return ka < kc;
+    });
+    std::vector<std::pair<uint64_t, size_t>> runs;  // (least p, start)
+    for (size_t i = 0; i < tmp.size(); ++i)
+      if (i == 0 || mask_of(tmp[i - 1]) != mask_of(tmp[i])) runs.push_back({tmp[i] & 0xFFFFFFull, i});
+    std::sort(runs.begin(), runs.end());
+    for (size_t g = 0; g < runs.size(); ++g) {
+      const uint32_t m = mask_of(tmp[runs[g].second]);
+      size_t i = runs[g].second;
+      for (; i < tmp.size() && mask_of(tmp[i]) == m; ++i) fe.push_back(tmp[i]);
+      fe.back() |= kGroupEnd;
+    }
+    fp.push_back((int64_t)fe.size());
+    fi.push_back((uint32_t)(b << 16) | part);
+  };
+  for (int64_t b = 0; b < nb; ++b) {
+    const int rows = (int)std::min<int64_t>(16, N - b * 16);
+    const uint32_t all = (1u << rows) - 1u;
+    if (bp[b + 1] - bp[b] <= T) {
+      emit(b, all);
+      continue;
+    }
+    auto reach = [&](uint32_t part) {
+      int64_t c = 0;
+      for (int64_t i = bp[b]; i < bp[b + 1]; ++i) c += (mask_of(e[i]) & part) != 0;
+      return c;
+    };
+    uint32_t cur = 0;
+    for (int r = 0; r < rows; ++r) {
+      const uint32_t cand = cur | (1u << r);
+      if (cur != 0 && reach(cand) > T) {
+        emit(b, cur);
+        cur = 1u << r;
+      } else {
+        cur = cand;
+      }
+    }
+    if (cur) emit(b, cur);
+  }
+  const int64_t nf = (int64_t)fi.size();
+  std::vector<int32_t> fo((size_t)nf);
+  for (int64_t f = 0; f < nf; ++f) fo[f] = (int32_t)f;
+  std::stable_sort(fo.begin(), fo.end(), [&](int32_t a, int32_t c) {
+    return fp[a + 1] - fp[a] > fp[c + 1] - fp[c];
+  });
+  TP_HIP_CHECK(ensure(st.forder, std::max<size_t>(fo.size(), 1) * sizeof(int32_t)));
+  TP_HIP_CHECK(ensure(st.fptr, fp.size() * sizeof(int64_t)));
+  TP_HIP_CHECK(ensure(st.fent, std::max<size_t>(fe.size(), 1) * sizeof(uint64_t)));
+  TP_HIP_CHECK(ensure(st.finfo, std::max<size_t>(fi.size(), 1) * sizeof(uint32_t)));
+  TP_HIP_CHECK(hipMemcpyAsync(st.fptr.ptr, fp.data(), fp.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+  if (!fe.empty())
+    TP_HIP_CHECK(hipMemcpyAsync(st.fent.ptr, fe.data(), fe.size() * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, s));
+  if (nf > 0) {
+    TP_HIP_CHECK(hipMemcpyAsync(st.finfo.ptr, fi.data(), fi.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, s));
+    TP_HIP_CHECK(hipMemcpyAsync(st.forder.ptr, fo.data(), fo.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s));
+  }
+  TP_HIP_CHECK(hipStreamSynchronize(s));
+  st.fptrh = std::move(fp);
+  st.fine_ready = true;
+  return TP_OK;
+}
+
+}  // namespace
+
+int state_fine_view(int n, hipStream_t s, FineView *out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  State *st = nullptr;
+  int rc = get_state(n, s, &st);
+  if (rc != TP_OK) return rc;
+  if (!st->fine_ready) {
+    rc = build_fine(*st, s);
+    if (rc != TP_OK) return rc;
+  }
+  *out = fine_of(*st);
+  return TP_OK;
 }
 
 int state_view(int n, hipStream_t s, StateView *out) {
@@ -590,6 +738,7 @@ int state_view(int n, hipStream_t s, StateView *out) {
   out->order = (const int32_t *)st->order.ptr;
   out->border = (const int32_t *)st->border.ptr;
   out->degh = st->degh.data();
+  out->fine = fine_of(*st);
   return TP_OK;
 }
 
@@ -930,6 +1079,10 @@ int tp_release_cache(void) {
     release(kv.second.bent);
     release(kv.second.order);
     release(kv.second.border);
+    release(kv.second.fptr);
+    release(kv.second.fent);
+    release(kv.second.finfo);
+    release(kv.second.forder);
     for (auto &sb : kv.second.sel) release(sb.second);
   }
   g_states.clear();

@@ -27,8 +27,13 @@
 //   fused (TP_PARAM_FUSED_CHAIN)  everything, chain levels included, runs
 //      in the one persistent launch: it first runs the chain level by level
 //      (level k of every n that lacks A^k together), each level spread over
-//      the whole grid one (row, 512-column panel) item per wave, with a
-//      barrier over the grid between levels; then the task list below.  The
+//      the whole grid, with a barrier over the grid between levels; then
+//      the task list below.  A^1 is written from the masks, one (row,
+//      512-column panel) item per wave; a level k >= 2 takes the row blocks
+//      of A (16 rows, the union of their successors grouped by row mask, as
+//      in the library's blocked step) cut by rows into parts of bounded
+//      length, one (part, 256-column panel) item per workgroup, whose four
+//      waves split the part's entries and meet in LDS.  The
 //      barrier needs every workgroup resident at once, so this mode never
 //      launches more workgroups than the chip holds, and such launches of
 //      the process are ordered one after another on each device; a batch
@@ -94,6 +99,11 @@ struct Slot {
   const int64_t *rowptr;
   const uint32_t *colz;     // successors with their labels in the top byte
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
+  // fused mode: row-block parts (entries fptr[f] .. fptr[f+1]-1 of fent,
+  // finfo[f] = block << 16 | row mask)
+  const int64_t *fptr;
+  const uint64_t *fent;
+  const uint32_t *finfo;
 };
 
 constexpr int kQueues = 8;  // one task queue per XCD
@@ -110,12 +120,14 @@ struct Control {
 constexpr int kMaxSlots = 16;
 
 // Fused mode: one chain level (exponent k) of every slot that needs it.  Its
-// work items are (slot, 512-column panel, row) triples packed in 32 bits
-// (slot in bits 28..31, panel in 20..27, row in 0..19), items[off ..
-// off + count) of the launch's item list, ordered by decreasing length of the
-// row's successor list; levels with the same slots share one list.
+// work items are (slot, 512-column panel, r) triples packed in 32 bits (slot
+// in bits 28..31, panel in 20..27, r in 0..19), items[off .. off + count) of
+// the launch's item list.  Level 1 (A^1, from the masks): r is a row, one
+// item per wave.  Levels k >= 2 (`parts` set): r is a part of a row block,
+// one item per workgroup, ordered by decreasing entry count.  Levels of one
+// kind with the same slots share one list.
 struct Level {
-  int32_t k, pad;
+  int32_t k, parts;
   int64_t off, count;
 };
 __host__ __device__ constexpr uint32_t item_code(int slot, int64_t panel, int64_t q) {
@@ -161,6 +173,23 @@ __device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, in
       __builtin_amdgcn_s_sleep(127);  // ~8000 clocks
   }
   return 1;
+}
+
+// Fused mode, chain level k >= 2: the workgroup's item (slot, 256-column
+// panel, part of a row block) of A^k = A x A^(k-1) (part_rows: the four
+// waves split the part's entries and meet in the LDS arena).  Slot fields
+// are made wave-uniform so the entry loads are scalar loads.
+__device__ __forceinline__ void part_item(const Slot *__restrict__ slots, uint32_t item, int lev,
+                                          int wv, int lane, uint32_t *lds_words) {
+  const uint32_t code = __builtin_amdgcn_readfirstlane(item);
+  const Slot &sl = slots[code >> 28];
+  const int64_t N = wave_uniform((int64_t)sl.N), ld = wave_uniform(sl.ld);
+  const int64_t panel = (code >> 20) & 0xFFu, f = code & 0xFFFFFu;
+  uint16_t *const *powers = wave_uniform(sl.powers);
+  part_rows<4, 4>((kconst_i64)wave_uniform(sl.fptr), (kconst_u64)wave_uniform(sl.fent),
+                  (kconst_u32)wave_uniform(sl.finfo), f, wave_uniform(powers[lev - 1]), ld,
+                  wave_uniform(powers[lev]), ld, N, N, panel * kPanel + (int64_t)lane * 8, wv,
+                  lane, (__attribute__((address_space(3))) uint32_t *)lds_words);
 }
 
 __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl,
@@ -209,49 +238,66 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
     const int on_xcc = s_on_xcc, xccs = s_xccs;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     for (int L = 0; L < nlev; ++L) {
-      if (ld_relaxed(&ctl->abort) == 0) {
+      if (threadIdx.x == 0) s_go = ld_relaxed(&ctl->abort) == 0;
+      __syncthreads();
+      const int lgo = __builtin_amdgcn_readfirstlane(s_go);
+      __syncthreads();
+      if (lgo && levels[L].parts) {
+        // one (slot, panel, part) per workgroup, its entries split over the
+        // four waves, whose minima meet in LDS; items dealt to the
+        // workgroups in a snake, longest first
         const Level &lv = levels[L];
-        const int64_t count = lv.count;
-        const kconst_u32 list = (kconst_u32)(items + lv.off);
-        // items longest first, dealt to the waves in a snake (wave w takes
-        // position w of even rounds and W - 1 - w of odd ones), so every
-        // wave's share adds up to about the same length
-        const int32_t W = (int32_t)gridDim.x * 4, w = (int32_t)blockIdx.x * 4 + wv;
+        const int64_t count = wave_uniform(lv.count);
+        const int k = __builtin_amdgcn_readfirstlane(lv.k);
+        const kconst_u32 list = (kconst_u32)wave_uniform(items + lv.off);
+        const int32_t G = (int32_t)gridDim.x, g = (int32_t)blockIdx.x;
         int32_t odd = 0;
-        for (int64_t base = 0; base < count; base += W, odd ^= 1) {
-          const int64_t p = base + (odd ? W - 1 - w : w);
+        for (int64_t base = 0; base < count; base += G, odd ^= 1) {
+          const int64_t p = base + (odd ? G - 1 - g : g);
           if (p >= count) continue;
+          part_item(slots, list[p], k, wv, lane, reinterpret_cast<uint32_t *>(lds));
+        }
+      } else if (lgo) {
+        // A^1 (the only level of row items): row q, this lane's 8 columns,
+        // from the masks; items dealt to the waves in turn
+        const Level &lv = levels[L];
+        const int64_t count = wave_uniform(lv.count);
+        const kconst_u32 list = (kconst_u32)wave_uniform(items + lv.off);
+        const int32_t W = (int32_t)gridDim.x * 4, w = (int32_t)blockIdx.x * 4 + wv;
+        for (int64_t p = w; p < count; p += W) {
           const uint32_t code = list[p];
-          const Slot sl = slots[code >> 28];
-          const int64_t N = sl.N, ld = sl.ld;
+          const Slot &sl = slots[code >> 28];
+          const int64_t N = wave_uniform((int64_t)sl.N), ld = wave_uniform(sl.ld);
+          const uint32_t full = __builtin_amdgcn_readfirstlane(sl.full);
+          const uint32_t *masks = wave_uniform(sl.masks);
           const int64_t panel = (code >> 20) & 0xFFu, q = code & 0xFFFFFu;
           const int64_t c0 = panel * kPanel + (int64_t)lane * 8;
-          if (c0 >= N) {
-            // lanes past the last column of the last panel (their loads
-            // would leave X's rows)
-          } else if (lv.k >= 2) {
-            gather_row_colz<7>((kconst_i64)sl.rowptr, (kconst_u32)sl.colz, sl.powers[lv.k - 1],
-                               ld, sl.powers[lv.k], ld, N, q, c0);
+          // lanes past the last column of the last panel store nothing
+          if (c0 >= N) continue;
+          const uint32_t mq = ((kconst_u32)masks)[q];
+          uint32_t mp[8];
+          if (c0 + 8 <= N) {
+            const u32x4 lo = *(gconst<u32x4>)to_global(masks + c0);
+            const u32x4 hi = *(gconst<u32x4>)to_global(masks + c0 + 4);
+            mp[0] = lo.x; mp[1] = lo.y; mp[2] = lo.z; mp[3] = lo.w;
+            mp[4] = hi.x; mp[5] = hi.y; mp[6] = hi.z; mp[7] = hi.w;
           } else {
-            // A^1: row q, this lane's 8 columns
-            const uint32_t mq = sl.masks[q];
-            uint16_t e[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const int64_t pc = c0 + j;
-              const uint32_t mp = pc < N ? sl.masks[pc] : 0u;
-              e[j] = (pc < N && can_follow(mq, mp, sl.full))
-                         ? (uint16_t)__builtin_popcount(mp & 0xFFFFu)
-                         : kInf;
-            }
-            uint16_t *row = sl.powers[1] + q * ld + c0;
-            if (c0 + 8 <= N) {
-              *(gmut<u32x4>)to_global_mut(row) = u32x4{
-                  (uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
-                  (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
-            } else {
-              for (int j = 0; j < 8 && c0 + j < N; ++j) row[j] = e[j];
-            }
+            for (int j = 0; j < 8; ++j) mp[j] = c0 + j < N ? masks[c0 + j] : 0u;
+          }
+          uint16_t e[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            e[j] = (c0 + j < N && can_follow(mq, mp[j], full))
+                       ? (uint16_t)__builtin_popcount(mp[j] & 0xFFFFu)
+                       : kInf;
+          uint16_t *row = wave_uniform(wave_uniform(sl.powers)[1]) + q * ld + c0;
+          if (c0 + 8 <= N) {
+            *(gmut<u32x4>)to_global_mut(row) = u32x4{
+                (uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+          } else {
+            for (int j = 0; j < 8 && c0 + j < N; ++j) row[j] = e[j];
           }
         }
       }
@@ -547,6 +593,7 @@ struct Plan {
   std::set<int> giants;   // giant indices (units of c)
   std::vector<int> exps;  // every exponent of the batch, increasing
   StateView view{};
+  FineView fine{};        // fused mode: the row-block parts of the chain levels
 };
 
 int baby_of(Ctx *c, int n) {
@@ -676,13 +723,45 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   if (fused) {
     int max_top = 0;
     for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
-    std::vector<int> prev_set;
-    int64_t off = 0, cnt = 0;
+    for (int s = 0; s < nslots; ++s) {
+      if (plans[s].chain_top < std::max(k0[s], 2)) continue;
+      const int rc = state_fine_view(plans[s].n, stream, &plans[s].fine);
+      if (rc != TP_OK) return rc;
+    }
+    std::vector<int> prev_set, prev_part_set;
+    int64_t off = 0, cnt = 0, part_off = 0, part_cnt = 0;
     for (int k = 1; k <= max_top; ++k) {
       std::vector<int> set;
       for (int s = 0; s < nslots; ++s)
         if (k >= k0[s] && k <= plans[s].chain_top) set.push_back(s);
       if (set.empty()) continue;
+      if (k >= 2) {
+        if (set != prev_part_set) {
+          // (slot, panel, part) items by decreasing entry count
+          std::vector<std::pair<int64_t, uint32_t>> by_len;
+          for (int s : set) {
+            const Plan &p = plans[s];
+            const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
+            for (int64_t f = 0; f < p.fine.nf; ++f)
+              for (int64_t P = 0; P < panels; ++P)
+                by_len.push_back({p.fine.fptrh[f + 1] - p.fine.fptrh[f], item_code(s, P, f)});
+          }
+          std::stable_sort(by_len.begin(), by_len.end(),
+                           [](const std::pair<int64_t, uint32_t> &a,
+                              const std::pair<int64_t, uint32_t> &b) { return a.first > b.first; });
+          part_off = (int64_t)items.size();
+          part_cnt = (int64_t)by_len.size();
+          for (const auto &x : by_len) items.push_back(x.second);
+          prev_part_set = set;
+        }
+        Level lv{};
+        lv.k = k;
+        lv.parts = 1;
+        lv.off = part_off;
+        lv.count = part_cnt;
+        levels.push_back(lv);
+        continue;
+      }
       if (set != prev_set) {
         // the items of these slots by decreasing length of the row's
         // successor list (a bucket per out-degree), a row's panels together
@@ -950,6 +1029,9 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.rowptr = p.view.rowptr;
     sl.colz = p.view.colz;
     sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
+    sl.fptr = p.fine.fptr;
+    sl.fent = p.fine.fent;
+    sl.finfo = p.fine.finfo;
     hs[s] = sl;
     for (size_t e = 0; e < ptr_stride; ++e) {
       auto it = ps.pw.find((int)e);
@@ -1156,6 +1238,23 @@ int tp_ctx_release(void *ctx, int n, hipStream_t stream) {
     c->pending_new.erase(it->first);
     it = c->sets.erase(it);
   }
+  return TP_OK;
+}
+
+int tp_ctx_copy_power(void *ctx, int n, int e, void *d_out, int64_t ld, hipStream_t stream) {
+  TP_REQUIRE(ctx != nullptr, "ctx is NULL");
+  TP_REQUIRE(d_out != nullptr, "out is NULL");
+  Ctx *c = (Ctx *)ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->sets.find(n);
+  TP_REQUIRE(it != c->sets.end() && it->second.have.count(e) && it->second.pw.count(e),
+             "the context holds no power %d of A(D_%d)", e, n);
+  const PowerSet &ps = it->second;
+  TP_REQUIRE(ld >= ps.N, "ld = %lld < N = %lld", (long long)ld, (long long)ps.N);
+  if (ps.N == 0) return TP_OK;
+  TP_HIP_CHECK(hipMemcpy2DAsync(d_out, (size_t)ld * sizeof(uint16_t), ps.pw.at(e),
+                                (size_t)ps.ld * sizeof(uint16_t), (size_t)ps.N * sizeof(uint16_t),
+                                (size_t)ps.N, hipMemcpyDeviceToDevice, stream));
   return TP_OK;
 }
 

@@ -34,19 +34,7 @@ namespace tp {
 
 namespace {
 
-constexpr int kRows = 16;  // rows per block
-
-// acc[r] = min(acc[r], g) for the rows r whose bit is set in m.
-__device__ __forceinline__ void apply_group(u16x2 (&acc)[kRows][4], uint32_t m,
-                                            const u16x2 (&g)[4]) {
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    if (m & (1u << r)) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[r][k] = pk_min(acc[r][k], g[k]);
-    }
-  }
-}
+constexpr int kRows = kBlockRows;  // rows per block
 
 // One wave per block: number of distinct successors of its rows.
 __global__ void block_count_kernel(int64_t N, uint32_t full, const uint32_t *__restrict__ masks,
@@ -306,85 +294,56 @@ __global__ void __launch_bounds__(256) block_step_pipe_kernel(
 // Small path orders: a block's entries split across the W waves of one
 // workgroup (a run of at most ceil(E / W) of the E entries each, mask groups
 // as above, the run's last entry closing its group), each wave folding its
-// own minima for the block's 16 rows; the W partial minima meet in LDS (a
-// tree: half the waves hand theirs to the other half each round) and wave 0
-// stores the rows.  With one wave per block, n = 8 (87 blocks, 3
-// panels of 512 columns) left most of the chip idle and made each block's
-// whole entry list one chain of dependent gathers.
-template <int U, int W>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4)))
+// own minima for the block's 16 rows at its lane's 2V columns; the W partial
+// minima meet in LDS (a tree: half the waves hand theirs to the other half
+// each round) and wave 0 stores the rows.  With one wave per block, n = 8 (87
+// blocks, 3 panels of 512 columns) left most of the chip idle and made each
+// block's whole entry list one chain of dependent gathers.  V = 2 (4 columns
+// a lane, 8-byte gathers) halves the minima's registers and the LDS the
+// partial minima pass through, so more workgroups fit a CU and U can grow.
+//
+// With `info` set, the items are the parts of the row blocks instead of the
+// blocks (entries ptr[f] .. ptr[f+1]-1 of part f, info[f] = block << 16 | the
+// part's row mask): a part bound at half the longest block halves the
+// longest run of entries a wave walks, for a few more gathers.
+template <int U, int W, int V, int WPE>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE)))
 block_split_step_kernel(
-    int64_t N, const int64_t *__restrict__ bptr, const uint64_t *__restrict__ ent,
-    const int32_t *__restrict__ border, const uint16_t *__restrict__ X, int64_t ldx,
+    int64_t N, int64_t nitems, const int64_t *__restrict__ bptr,
+    const uint64_t *__restrict__ ent, const int32_t *__restrict__ border,
+    const uint32_t *__restrict__ info, const uint16_t *__restrict__ X, int64_t ldx,
     uint16_t *__restrict__ Y, int64_t ldy, int64_t ncols) {
-  __shared__ uint32_t part[W / 2][kRows * 4][64];
+  typedef typename ChunkOf<V>::type chunk;
+  __shared__ uint32_t part[W / 2][kRows * V][64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nblocks = (N + kRows - 1) / kRows;
   const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t panel = t / nblocks;
-  const int64_t bslot = t - panel * nblocks;
-  const int64_t b = border ? (int64_t)((kconst_i32)border)[bslot] : bslot;
-  const int64_t c0 = (panel * 64 + lane) * 8;
+  const int64_t panel = t / nitems;
+  const int64_t bslot = t - panel * nitems;
+  const int64_t it = border ? (int64_t)((kconst_i32)border)[bslot] : bslot;
+  uint32_t rows = 0xFFFFu;
+  int64_t b = it;
+  if (info) {
+    const uint32_t w = ((kconst_u32)info)[it];
+    b = w >> 16;
+    rows = w & 0xFFFFu;
+  }
+  const int64_t c0 = (panel * 64 + lane) * (2 * V);
   const kconst_i64 bp = (kconst_i64)bptr;
   const kconst_u64 en = (kconst_u64)ent;
-  const gconst<u32x4> Xg = (gconst<u32x4>)to_global(X);
-  const int64_t ld4 = ldx / 8;
-  const uint32_t off = c0 < ncols ? (uint32_t)(c0 / 8) : 0u;
+  const gconst<chunk> Xg = (gconst<chunk>)to_global(X);
+  const int64_t ldc = ldx / (2 * V);
+  const uint32_t off = c0 < ncols ? (uint32_t)(c0 / (2 * V)) : 0u;
 
-  u16x2 acc[kRows][4];
+  u16x2 acc[kRows][V];
 #pragma unroll
   for (int r = 0; r < kRows; ++r)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[r][k] = splat(0xFFFFu);
-  u16x2 g[4] = {splat(0xFFFFu), splat(0xFFFFu), splat(0xFFFFu), splat(0xFFFFu)};
-
-  const int64_t e0 = bp[b], e1 = bp[b + 1];
+    for (int k = 0; k < V; ++k) acc[r][k] = splat(0xFFFFu);
+  const int64_t e0 = bp[it], e1 = bp[it + 1];
   const int64_t per = (e1 - e0 + W - 1) / W;
   const int64_t my0 = e0 + (int64_t)wave * per, my1 = min(e1, my0 + per);
-  if (my0 < my1) {
-    const int64_t last = my1 - 1;
-    auto fetch = [&](int64_t i, uint64_t (&w)[U], u32x4 (&v)[U]) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t k = i + u;
-        const uint64_t x = en[k < last ? k : last];
-        // the run's last entry closes its group; past it: no rows, no group end
-        w[u] = k < last ? x : (k == last ? (x | kGroupEnd) : (x & 0xFFFFFFFFull));
-        v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ld4 + off];
-      }
-    };
-    auto apply = [&](const uint64_t (&w)[U], const u32x4 (&v)[U]) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const u16x2 lab = splat((uint16_t)((w[u] >> 24) & 0xFFu));
-        g[0] = pk_min(g[0], pk_add_sat(lab, as_pk(v[u].x)));
-        g[1] = pk_min(g[1], pk_add_sat(lab, as_pk(v[u].y)));
-        g[2] = pk_min(g[2], pk_add_sat(lab, as_pk(v[u].z)));
-        g[3] = pk_min(g[3], pk_add_sat(lab, as_pk(v[u].w)));
-        if (w[u] & kGroupEnd) {
-          apply_group(acc, (uint32_t)(w[u] >> 32), g);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) g[k] = splat(0xFFFFu);
-        }
-      }
-    };
-    uint64_t wa[U], wb[U];
-    u32x4 va[U], vb[U];
-    fetch(my0, wa, va);
-    for (int64_t i = my0;;) {
-      bool more = i + U <= last;
-      if (more) fetch(i + U, wb, vb);
-      apply(wa, va);
-      i += U;
-      if (!more) break;
-      more = i + U <= last;
-      if (more) fetch(i + U, wa, va);
-      apply(wb, vb);
-      i += U;
-      if (!more) break;
-    }
-  }
+  block_entries<U, V>(en, my0, my1, Xg, ldc, off, acc);
   // the W partial minima meet in LDS, halving the waves each round
 #pragma unroll 1
   for (int half = W / 2; half >= 1; half /= 2) {
@@ -392,15 +351,15 @@ block_split_step_kernel(
 #pragma unroll
       for (int r = 0; r < kRows; ++r)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) part[wave - half][r * 4 + k][lane] = as_u32(acc[r][k]);
+        for (int k = 0; k < V; ++k) part[wave - half][r * V + k][lane] = as_u32(acc[r][k]);
     }
     __syncthreads();
     if (wave < half) {
 #pragma unroll
       for (int r = 0; r < kRows; ++r)
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          acc[r][k] = pk_min(acc[r][k], as_pk(part[wave][r * 4 + k][lane]));
+        for (int k = 0; k < V; ++k)
+          acc[r][k] = pk_min(acc[r][k], as_pk(part[wave][r * V + k][lane]));
     }
     __syncthreads();
   }
@@ -409,14 +368,17 @@ block_split_step_kernel(
   for (int r = 0; r < kRows; ++r) {
     const int64_t q = b * kRows + r;
     if (q >= N) break;
+    if (!(rows & (1u << r))) continue;
     const u16x2 *a = acc[r];
-    if (c0 + 8 <= ncols) {
-      *(gmut<u32x4>)(to_global_mut(Y) + q * ldy + c0) =
-          u32x4{as_u32(a[0]), as_u32(a[1]), as_u32(a[2]), as_u32(a[3])};
+    if (c0 + 2 * V <= ncols) {
+      chunk o;
+#pragma unroll
+      for (int k = 0; k < V; ++k) o[k] = as_u32(a[k]);
+      *(gmut<chunk>)(to_global_mut(Y) + q * ldy + c0) = o;
     } else {
       const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < V; ++k) {
         if (c0 + 2 * k < ncols) y[2 * k] = a[k].x;
         if (c0 + 2 * k + 1 < ncols) y[2 * k + 1] = a[k].y;
       }
@@ -424,10 +386,36 @@ block_split_step_kernel(
   }
 }
 
+// The grouped step on row-block parts (small n): one (part, 256-column
+// panel) item per workgroup of four waves (part_rows), parts by decreasing
+// entry count, each XCD a contiguous range of items.  The parts cap the
+// entries any wave walks at a quarter of the part bound, the 16 rows' minima
+// of 4 columns a lane take 32 registers, and only four partial minima meet
+// in 16 KB of LDS, so a CU holds eight such workgroups: at n = 8 every item
+// is resident at once, where the workgroup-shared blocks (16 waves, 128 KB
+// of LDS, one workgroup per CU) needed two rounds and spent half their time
+// combining the 16 partial minima.
+template <int U>
+__global__ void __launch_bounds__(256) part_step_kernel(
+    int64_t N, int64_t nf, const int64_t *__restrict__ fptr, const uint64_t *__restrict__ fent,
+    const uint32_t *__restrict__ finfo, const int32_t *__restrict__ forder,
+    const uint16_t *__restrict__ X, int64_t ldx, uint16_t *__restrict__ Y, int64_t ldy,
+    int64_t ncols) {
+  __shared__ uint32_t part[2 * kRows * 2 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t panel = t / nf;
+  const int64_t f = ((kconst_i32)forder)[t - panel * nf];
+  part_rows<U, 2>((kconst_i64)fptr, (kconst_u64)fent, (kconst_u32)finfo, f, X, ldx, Y, ldy, N,
+                  ncols, panel * 256 + (int64_t)lane * 4, wv, lane,
+                  (__attribute__((address_space(3))) uint32_t *)part);
+}
+
 hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t *ent,
-                                 const int32_t *border, const uint16_t *X, int64_t ldx,
-                                 uint16_t *Y, int64_t ldy, int64_t ncols, bool grouped,
-                                 hipStream_t s) {
+                                 const int32_t *border, const FineView *fine, const uint16_t *X,
+                                 int64_t ldx, uint16_t *Y, int64_t ldy, int64_t ncols,
+                                 bool grouped, hipStream_t s) {
   constexpr int VE = 8;
   const int64_t nblocks = (N + kRows - 1) / kRows;
   const int64_t panels = (ncols + 64 * VE - 1) / (64 * VE);
@@ -439,15 +427,29 @@ hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t 
   // is as fast as the plain one at n = 12 (45.6 ms) and faster below (n = 11:
   // 5.41 vs 5.58 ms; n = 9: 0.30 vs 0.52 ms)
   // grouped, on 16-byte rows: one wave per (block, panel) where that fills
-  // the chip; below that a workgroup of 8 or 4 waves shares each block
+  // the chip (n >= 10); below that a workgroup of 8 waves shares each block
+  // (n = 9) or part of a block (n = 8); up to n = 7 four waves take each
+  // part at 4 columns a lane
   const int64_t items = nblocks * panels;
   const bool pipe_ok = vec && ldx >= (ncols + 7) / 8 * 8;
-  if (pipe_ok && grouped && items < 1024)
-    hipLaunchKernelGGL((block_split_step_kernel<4, 16>), dim3((unsigned)items), dim3(1024), 0, s,
-                       N, bptr, ent, border, X, ldx, Y, ldy, ncols);
-  else if (pipe_ok && grouped && items < 4096)
-    hipLaunchKernelGGL((block_split_step_kernel<4, 8>), dim3((unsigned)items), dim3(512), 0, s,
-                       N, bptr, ent, border, X, ldx, Y, ldy, ncols);
+  // parts: 8-byte chunks of rows at least ncols rounded up to 4 long
+  const bool parts_ok = fine && fine->nf > 0 && (ldx % 4 == 0) && (ldy % 4 == 0) &&
+                        ((uintptr_t)X % 8 == 0) && ((uintptr_t)Y % 8 == 0) &&
+                        ldx >= (ncols + 3) / 4 * 4;
+  if (parts_ok && grouped && N <= 1024) {
+    const int64_t pitems = fine->nf * ((ncols + 255) / 256);
+    hipLaunchKernelGGL(part_step_kernel<4>, dim3((unsigned)pitems), dim3(256), 0, s, N, fine->nf,
+                       fine->fptr, fine->fent, fine->finfo, fine->forder, X, ldx, Y, ldy, ncols);
+  } else if (pipe_ok && grouped && parts_ok && N <= 2048) {
+    // n = 8: the parts (17.6 us against 18.5 on the blocks, 20.4 with 16
+    // waves a block)
+    const int64_t pitems = fine->nf * panels;
+    hipLaunchKernelGGL((block_split_step_kernel<4, 8, 4, 4>), dim3((unsigned)pitems), dim3(512),
+                       0, s, N, fine->nf, fine->fptr, fine->fent, fine->forder, fine->finfo, X,
+                       ldx, Y, ldy, ncols);
+  } else if (pipe_ok && grouped && items < 4096)
+    hipLaunchKernelGGL((block_split_step_kernel<4, 8, 4, 4>), dim3((unsigned)items), dim3(512), 0,
+                       s, N, nblocks, bptr, ent, border, nullptr, X, ldx, Y, ldy, ncols);
   else if (pipe_ok && grouped)
     hipLaunchKernelGGL((block_step_pipe_kernel<8, true>), grid, dim3(256), 0, s, N, bptr, ent,
                        border, X, ldx, Y, ldy, ncols);
@@ -488,10 +490,11 @@ hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int6
 }
 
 hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
-                             const int32_t *border, const uint16_t *X, int64_t ldx, uint16_t *Y,
-                             int64_t ldy, int64_t ncols, bool grouped, hipStream_t s) {
+                             const int32_t *border, const FineView *fine, const uint16_t *X,
+                             int64_t ldx, uint16_t *Y, int64_t ldy, int64_t ncols, bool grouped,
+                             hipStream_t s) {
   if (N == 0 || ncols == 0) return hipSuccess;
-  return launch_block_step_u16(N, bptr, ent, border, X, ldx, Y, ldy, ncols, grouped, s);
+  return launch_block_step_u16(N, bptr, ent, border, fine, X, ldx, Y, ldy, ncols, grouped, s);
 }
 
 }  // namespace tp

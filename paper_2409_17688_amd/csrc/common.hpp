@@ -58,6 +58,25 @@ typedef const __attribute__((address_space(4))) int32_t *kconst_i32;
 typedef const __attribute__((address_space(4))) uint32_t *kconst_u32;
 typedef const __attribute__((address_space(4))) uint64_t *kconst_u64;
 
+// A value the whole wave holds the same copy of, moved to scalar registers.
+// A pointer loaded from memory (a slot table) lives in vector registers to
+// the compiler even when every lane loaded the same one, and loads through
+// it then stay per-lane vector loads that wait for each other; made scalar,
+// loads through constant-space views of it become scalar loads again.
+template <typename T>
+__device__ __forceinline__ T *wave_uniform(T *p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T *)(uintptr_t)(hi << 32 | lo);
+}
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+  const uint64_t v = (uint64_t)x;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (int64_t)(hi << 32 | lo);
+}
+
 template <typename T>
 __device__ __forceinline__ gconst<T> to_global(const T *p) {
   return (gconst<T>)p;
@@ -101,6 +120,20 @@ int hip_fail(hipError_t e, const char *what);
 // Launchers implemented in the kernel translation units (host functions).
 namespace tp {
 
+// The row blocks of A(D_n) cut by rows into parts of bounded length, for
+// the steps that give each part to one workgroup (the batch kernel's chain
+// levels, the small-n step): part f has entries fptr[f] .. fptr[f+1]-1 of
+// fent (the blocked layout, masks cut to the part's rows and grouped again),
+// finfo[f] = block << 16 | the part's row mask; fptrh is fptr on the host.
+// Built with the state for n <= 10, on first use above, and kept.
+struct FineView {
+  int64_t nf;
+  const int64_t *fptr;
+  const uint64_t *fent;
+  const uint32_t *finfo;
+  const int32_t *forder;  // parts by decreasing entry count (device)
+  const int64_t *fptrh;
+};
 // Device-resident description of A(D_n) from the process-wide cache (api.hip);
 // pointers stay valid until tp_release_cache.
 struct StateView {
@@ -118,8 +151,10 @@ struct StateView {
   const int32_t *order;   // rows by decreasing out-degree
   const int32_t *border;  // row blocks by decreasing entry count
   const int32_t *degh;    // host: out-degree of each row
+  FineView fine;          // row-block parts (nf = 0 when not built)
 };
 int state_view(int n, hipStream_t s, StateView *out);
+int state_fine_view(int n, hipStream_t s, FineView *out);
 // Y = A(D_n) x X (u16) in the form the library picks for n (tp_tune_step).
 hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, uint16_t *Y,
                            int64_t ldy, int64_t ncols, hipStream_t s);
@@ -170,9 +205,12 @@ hipError_t launch_block_fill(int64_t N, int n, const uint32_t *masks, const int6
                              uint64_t *ent, hipStream_t s);
 // blocks in `border` (a permutation of the blocks) when it is not NULL
 // (grouped: the entries a mask group at a time)
+// `fine` (may be null): the row-block parts, which the grouped step takes
+// where the blocks alone would leave the chip short of work (small n).
 hipError_t launch_block_step(int64_t N, const int64_t *bptr, const uint64_t *ent,
-                             const int32_t *border, const uint16_t *X, int64_t ldx, uint16_t *Y,
-                             int64_t ldy, int64_t ncols, bool grouped, hipStream_t s);
+                             const int32_t *border, const FineView *fine, const uint16_t *X,
+                             int64_t ldx, uint16_t *Y, int64_t ldy, int64_t ncols, bool grouped,
+                             hipStream_t s);
 
 // gemm.hip
 // config >= 0: that tile configuration with ksplit slices (>= 1); config < 0:

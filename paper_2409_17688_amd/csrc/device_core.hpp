@@ -202,6 +202,165 @@ __device__ __forceinline__ void gather_row_colz(kconst_i64 rowptr, kconst_u32 co
   }
 }
 
+// Rows per block of the blocked form of A(D_n).
+constexpr int kBlockRows = 16;
+
+// acc[r] = min(acc[r], g) for the rows r whose bit is set in m.
+template <int V>
+__device__ __forceinline__ void apply_group(u16x2 (&acc)[kBlockRows][V], uint32_t m,
+                                            const u16x2 (&g)[V]) {
+#pragma unroll
+  for (int r = 0; r < kBlockRows; ++r) {
+    if (m & (1u << r)) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) acc[r][k] = pk_min(acc[r][k], g[k]);
+    }
+  }
+}
+
+// Entries [i0, i1) of a block's entry list (grouped by row mask, bit 48 on
+// the last entry of each group; entry layout: successor p in bits 0..23, its
+// label z_p in 24..31, row mask in 32..47) folded into acc, the block's rows
+// at this lane's 2V columns: each entry gathers 4V bytes of row p of X (chunk
+// `off` of the row, ldc chunks per row), adds z_p and takes the minimum into
+// its group's running minimum, which goes to the rows of the group's mask at
+// the group's end.  The range may start or end inside a group: its last
+// entry closes the group it is in, so every partial group still reaches its
+// rows.  Two rounds of U gathers are in flight; the entries are uniform in
+// the wave and read with scalar loads, a round ahead of their gathers.
+template <int V> struct ChunkOf;
+template <> struct ChunkOf<2> { typedef u32x2 type; };
+template <> struct ChunkOf<4> { typedef u32x4 type; };
+
+template <int U, int V = 4>
+__device__ __forceinline__ void block_entries(kconst_u64 en, int64_t i0, int64_t i1,
+                                              gconst<typename ChunkOf<V>::type> Xg, int64_t ldc,
+                                              uint32_t off, u16x2 (&acc)[kBlockRows][V]) {
+  typedef typename ChunkOf<V>::type chunk;
+  if (i0 >= i1) return;
+  u16x2 g[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) g[k] = splat(0xFFFFu);
+  const int64_t last = i1 - 1;
+  // the entries of the next round are loaded a round ahead (scalar loads
+  // return out of order, so a gather right after its entry's load would wait
+  // for every scalar load in flight)
+  uint64_t nx[U];
+  auto load_entries = [&](int64_t i) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) nx[u] = en[i + u < last ? i + u : last];
+  };
+  auto fetch = [&](int64_t i, uint64_t (&w)[U], chunk (&v)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = i + u;
+      const uint64_t x = nx[u];
+      // past the range's last entry: no rows, no group end
+      w[u] = k < last ? x : (k == last ? (x | kGroupEnd) : (x & 0xFFFFFFFFull));
+      v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ldc + off];
+    }
+    load_entries(i + U);
+  };
+  auto apply = [&](const uint64_t (&w)[U], const chunk (&v)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const u16x2 lab = splat((uint16_t)((w[u] >> 24) & 0xFFu));
+#pragma unroll
+      for (int k = 0; k < V; ++k) g[k] = pk_min(g[k], pk_add_sat(lab, as_pk(v[u][k])));
+      if (w[u] & kGroupEnd) {
+        apply_group<V>(acc, (uint32_t)(w[u] >> 32) & 0xFFFFu, g);
+#pragma unroll
+        for (int k = 0; k < V; ++k) g[k] = splat(0xFFFFu);
+      }
+    }
+  };
+  uint64_t wa[U], wb[U];
+  chunk va[U], vb[U];
+  load_entries(i0);
+  fetch(i0, wa, va);
+  for (int64_t i = i0;;) {
+    bool more = i + U <= last;
+    if (more) fetch(i + U, wb, vb);
+    apply(wa, va);
+    i += U;
+    if (!more) break;
+    more = i + U <= last;
+    if (more) fetch(i + U, wa, va);
+    apply(wb, vb);
+    i += U;
+    if (!more) break;
+  }
+}
+
+// One (part f, 128V-column panel) item of Y = A x X on row-block parts, for
+// a workgroup of four waves: each wave folds a quarter of the part's
+// entries into the 16 rows' minima at its lane's 2V columns (16V
+// registers), waves 2 and 3 hand theirs to waves 0 and 1 through LDS, then
+// wave 1 to wave 0, which stores the rows of the part's mask.  `part` is
+// 8V KB of LDS ([2][16 rows x V][64] words).  Columns c0 .. c0+2V-1 of X
+// and Y, c0 < ncols for the lanes that store; X rows are whole 4V-byte
+// chunks (ldx % 2V == 0).  Every wave of the workgroup must call it with the
+// same item.
+template <int U, int V>
+__device__ __forceinline__ void part_rows(kconst_i64 fptr, kconst_u64 fent, kconst_u32 finfo,
+                                          int64_t f, const uint16_t *X, int64_t ldx, uint16_t *Y,
+                                          int64_t ldy, int64_t N, int64_t ncols, int64_t c0,
+                                          int wv, int lane,
+                                          __attribute__((address_space(3))) uint32_t *part) {
+  typedef typename ChunkOf<V>::type chunk;
+  const uint32_t info = finfo[f];
+  const int64_t b = info >> 16;
+  const uint32_t rows = info & 0xFFFFu;
+  const int64_t e0 = fptr[f], e1 = fptr[f + 1];
+  const int64_t per = (e1 - e0 + 3) / 4;
+  const int64_t my0 = e0 + (int64_t)wv * per, my1 = min(e1, my0 + per);
+  u16x2 acc[kBlockRows][V];
+#pragma unroll
+  for (int r = 0; r < kBlockRows; ++r)
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[r][k] = splat(0xFFFFu);
+  block_entries<U, V>(fent, my0, my1, (gconst<chunk>)to_global(X), ldx / (2 * V),
+                      c0 < ncols ? (uint32_t)(c0 / (2 * V)) : 0u, acc);
+#pragma unroll 1
+  for (int half = 2; half >= 1; half /= 2) {
+    if (wv >= half && wv < 2 * half) {
+#pragma unroll
+      for (int r = 0; r < kBlockRows; ++r)
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+          part[((wv - half) * kBlockRows * V + r * V + k) * 64 + lane] = as_u32(acc[r][k]);
+    }
+    __syncthreads();
+    if (wv < half) {
+#pragma unroll
+      for (int r = 0; r < kBlockRows; ++r)
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+          acc[r][k] = pk_min(acc[r][k], as_pk(part[(wv * kBlockRows * V + r * V + k) * 64 + lane]));
+    }
+    __syncthreads();
+  }
+  if (wv != 0 || c0 >= ncols) return;
+#pragma unroll
+  for (int r = 0; r < kBlockRows; ++r) {
+    const int64_t q = b * kBlockRows + r;
+    if (!(rows & (1u << r)) || q >= N) continue;
+    if (c0 + 2 * V <= ncols) {
+      chunk o;
+#pragma unroll
+      for (int k = 0; k < V; ++k) o[k] = as_u32(acc[r][k]);
+      *(gmut<chunk>)(to_global_mut(Y) + q * ldy + c0) = o;
+    } else {
+      const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        if (c0 + 2 * k < ncols) y[2 * k] = acc[r][k].x;
+        if (c0 + 2 * k + 1 < ncols) y[2 * k + 1] = acc[r][k].y;
+      }
+    }
+  }
+}
+
 // Eight consecutive entries of row `row` from column `col`, widened to 16
 // bits; entries outside [0, n) x [0, n) read as 0xFFFF.
 template <typename T, bool VEC>

@@ -242,11 +242,13 @@ def test_giants_for_long_cycles(tp, oracle_table_500):
         tp.tp_ctx_destroy(ctx)
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("c", [2, 3, 7, 16, 40])
-def test_baby_step_length_does_not_change_results(tp, oracle_table_500, c):
+def test_baby_step_length_does_not_change_results(tp, oracle_table_500, c, fused):
     inst = [(n, m) for n in (3, 6, 8) for m in (3, 4, 5, 2 * c, 2 * c + 1, 3 * c + 2, 199, 350)]
     ctx = tp.tp_ctx_create(64 << 30)
     try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, fused)
         for n in (3, 6, 8):
             tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, c)
         need = tp.tp_ctx_need_bytes(ctx, [n for n, _ in inst], [m for _, m in inst])
@@ -316,5 +318,39 @@ def test_last_work_counts_what_the_batch_computes(tp):
         _run(tp, ctx, [(4, 40)])
         w = tp.tp_ctx_last_work(ctx)
         assert w["product_ops"] == N ** 3 and w["chain_ops"] == 13 * nnz * N
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_chain_powers_equal_the_oracle(tp, oracle_mod, fused):
+    # every resident chain power A^1 .. A^c, entry by entry, against the
+    # oracle's chain A^k = A x A^(k-1); in the fused mode levels k >= 2 run
+    # on row-block parts (blocks above the part bound are cut by rows at
+    # n = 8 and 9)
+    import torch
+    cs = {5: 9, 8: 7, 9: 4}
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, fused)
+        for n, c in cs.items():
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, c)
+        inst = [(n, 2 * c) for n, c in cs.items()]
+        say("chain powers, fused", fused)
+        got = _run(tp, ctx, inst)
+        for n, c in cs.items():
+            A = oracle_mod.state_matrix(n)
+            P = A
+            for k in range(1, c + 1):
+                if k > 1:
+                    P = oracle_mod.minplus(A, P)
+                G = tp.tp_ctx_copy_power(ctx, n, k)
+                torch.cuda.synchronize()
+                g = G.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.int32)
+                bad = np.argwhere(g != P)
+                assert bad.size == 0, (n, k, bad[:5].tolist())
+            assert got[list(cs).index(n)] == oracle_mod.trace_min(oracle_mod.minplus(P, P))
+        with pytest.raises(tp.TropicalError):
+            tp.tp_ctx_copy_power(ctx, 8, 99)
     finally:
         tp.tp_ctx_destroy(ctx)
