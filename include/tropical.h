@@ -464,9 +464,16 @@ int tp_gamma2_recurrence(const tp_recurrence_t *rec, const int32_t *diag_min, in
  * A^1..A^c of Algorithm 2 and giants A^(jc) formed by dense products of
  * resident powers.  gamma_2(P_n x C_m) is the trace of A^a x A^b for a + b = m
  * (Theorem 2): (ceil(m/2), floor(m/2)) when m <= 2c, else (jc, m - jc) with
- * 1 <= m - jc <= c.  Powers persist across batches until the context is
- * destroyed.  A context is used from one host thread and one stream at a
- * time. */
+ * 1 <= m - jc <= c.  Path orders from TP_PARAM_COMPACT_FROM on (default 10)
+ * keep A^3 and every higher power as shared-base compact powers instead (u8
+ * residuals over one base per power, half the bytes; A^1 .. A^3 also in 16
+ * bits): babies run to c + 2 (c >= 4), and a pair with an exponent above 3
+ * has both at 3 or above: (ceil(m/2), floor(m/2)) when m <= 2(c + 2), else
+ * (jc, m - jc) with 3 <= m - jc <= c + 2; a giant is the product of two
+ * compact powers (residuals summed in 16 bits, bases added), a trace adds the
+ * two bases to the residuals' minimum.  Powers persist across batches until
+ * the context is destroyed.  A context is used from one host thread and one
+ * stream at a time. */
 int tp_ctx_create(size_t hbm_budget_bytes, void **ctx);
 int tp_ctx_destroy(void *ctx);
 
@@ -478,6 +485,10 @@ int tp_ctx_destroy(void *ctx);
                                     grid, which then never exceeds what the chip holds);
                                     0 (default): as full-chip launches on one stream per n
                                     ahead of it */
+#define TP_PARAM_COMPACT_FROM 4  /* path orders n >= value keep compact powers from A^3 on
+                                    (0: none; default 10); fixed per n once its powers are
+                                    resident.  A batch with compact sets runs their chain
+                                    levels as launches in either mode */
 #define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
                                     n >= 8, else 32); fixed once powers of n are resident */
 int tp_ctx_set_param(void *ctx, int param, int64_t value);
@@ -528,7 +539,10 @@ int tp_ctx_last_work(void *ctx, double *ops, double *bytes);
 /* Waits for `stream` and reports whether the batches queued since the last
  * check completed: TP_OK, or TP_ECANCELED when a task's wait for its inputs
  * exceeded the wait limit (the kernel then drains without computing, the
- * results are invalid and the levels it was to compute are dropped). */
+ * results are invalid and the levels it was to compute are dropped), or
+ * TP_EOVERFLOW when a compact power would have needed a residual above 254
+ * (results invalid, its powers dropped; for the powers of A(D_n) the
+ * residuals stay within a few units of n). */
 int tp_ctx_check(void *ctx, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */

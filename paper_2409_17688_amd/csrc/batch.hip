@@ -88,6 +88,8 @@ struct Task {
   int32_t done, done2;         // counters bumped when finished (-1: none)
   int32_t inst;                // instance of a TRACE
   int32_t queue;               // queue (XCD) the task is dealt to
+  int32_t compact;             // operands (and output) are shared-base u8 powers
+  int32_t done3;               // a compact giant's count of finished tiles (-1: none)
 };
 
 struct Slot {
@@ -99,6 +101,10 @@ struct Slot {
   const int64_t *rowptr;
   const uint32_t *colz;     // successors with their labels in the top byte
   uint16_t *const *powers;  // powers[e] = A^e for the exponents of this batch
+  // shared-base compact powers (residuals u8, A^e = base[0] + residual)
+  int64_t ld8;
+  uint8_t *const *powers8;   // powers8[e]: residuals of A^e (or null)
+  int32_t *const *bases8;    // bases8[e]: its base words
   // fused mode: row-block parts (entries fptr[f] .. fptr[f+1]-1 of fent,
   // finfo[f] = block << 16 | row mask)
   const int64_t *fptr;
@@ -115,6 +121,7 @@ struct Control {
   int32_t abort;           // set when a wait exceeded the limit
   int32_t nlevels;         // fused mode: chain levels run before the tasks
   int64_t wait_limit;      // in s_memrealtime ticks (100 MHz)
+  int32_t *status;         // bit 1: a compact product left its residual range
 };
 
 constexpr int kMaxSlots = 16;
@@ -357,13 +364,45 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
     if (go) {
       const Slot sl = slots[task.slot];
       const int64_t N = sl.N, ld = sl.ld;
-      if (task.type == kGemm) {
+      if (task.type == kGemm && task.compact) {
+        // (G_x + x) (G_y + y) = (G_x + l_x + G_y + l_y) + (x y - l_x - l_y),
+        // l the factors' least residuals (final: a compact giant's tiles
+        // wait for the whole of each factor): the residuals' product in 16
+        // bits, lowered by l_x + l_y and stored as u8 (a clamped entry flags
+        // the range); the tiles fold their least residual into the base's
+        // second word.  Rebased so, a giant's residuals span what its own
+        // entries span plus one product's gap, however deep its tree.
+        const int64_t ld8 = sl.ld8;
+        const int32_t *bx = sl.bases8[task.x], *by = sl.bases8[task.y];
+        const int32_t lx = bx[1], ly = by[1];
+        int32_t *bo = sl.bases8[task.out];
+        gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint8_t, true>(
+            (int)N, (int)N, (int)N, sl.powers8[task.x], ld8, sl.powers8[task.y], ld8,
+            sl.powers8[task.out], ld8, 0, task.row0, task.c0,
+            reinterpret_cast<uint16_t(*)[kGBK][kGBM]>(lds),
+            reinterpret_cast<uint16_t(*)[kGBK][kGBN]>(lds + 2 * kGBK * kGBM), ctl->status,
+            (uint16_t)min(lx + ly, 0xFFFF), bo + 1);
+        // every tile writes the same base word; readers see it through the
+        // tile counters they wait for
+        if (threadIdx.x == 0) bo[0] = bx[0] + lx + by[0] + ly;
+      } else if (task.type == kGemm) {
         gemm_tile<kGBM, kGBN, kGBK, 8, 8, uint16_t, true>(
             (int)N, (int)N, (int)N, sl.powers[task.x], ld,
             sl.powers[task.y], ld, sl.powers[task.out], ld, 0, task.row0,
             task.c0,
             reinterpret_cast<uint16_t(*)[kGBK][kGBM]>(lds),
             reinterpret_cast<uint16_t(*)[kGBK][kGBN]>(lds + 2 * kGBK * kGBM));
+      } else if (task.compact) {
+        u16x2 acc[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = splat(kInf);
+        const int64_t ld8 = sl.ld8;
+        for (int64_t k0 = 0; k0 < N; k0 += 64)
+          trace_tile<uint8_t, true>(sl.powers8[task.x], ld8, sl.powers8[task.y], ld8, N,
+                                    task.row0, k0, lds, acc);
+        const int32_t best = block_min(acc, part);
+        if (threadIdx.x == 0 && best < (int32_t)kInf)
+          atomicMin(&results[task.inst], best + sl.bases8[task.x][0] + sl.bases8[task.y][0]);
       } else {
         u16x2 acc[4];
 #pragma unroll
@@ -384,6 +423,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
       __hip_atomic_fetch_add(&counters[task.done], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (task.done2 >= 0)
         __hip_atomic_fetch_add(&counters[task.done2], 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      if (task.done3 >= 0)
+        __hip_atomic_fetch_add(&counters[task.done3], 1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -427,12 +469,28 @@ hipError_t grow_host(Buf &b, size_t bytes, std::vector<void *> &retired) {
   return hipSuccess;
 }
 
+// Keys of a power set: the exponent e for a 16-bit power, e + kCompactKey
+// for a shared-base compact one.
+constexpr int kCompactKey = 1 << 16;
+
 struct PowerSet {
   int64_t N = 0, ld = 0;
   int c = 0;                 // baby steps (fixed at first use)
-  std::map<int, void *> pw;  // exponent -> device buffer (inside a slab)
-  std::set<int> have;        // exponents known complete on the device
+  // compact (fixed at first use): A^1 .. A^3 in 16 bits, A^3 on as u8
+  // residuals over one base per power, rows of ld8 bytes, the two base words
+  // after the residuals
+  bool compact = false;
+  int64_t ld8 = 0;
+  std::map<int, void *> pw;  // key -> device buffer (inside a slab)
+  std::set<int> have;        // keys known complete on the device
   std::vector<void *> slabs;  // one allocation per batch that added powers
+  size_t held = 0;            // bytes of the slabs
+  size_t bytes16() const { return (size_t)N * (size_t)ld * sizeof(uint16_t); }
+  size_t bytes8() const { return (size_t)N * (size_t)ld8 + 256; }
+  size_t bytes_of(int key) const { return key >= kCompactKey ? bytes8() : bytes16(); }
+  int32_t *base_of(int key) const {
+    return (int32_t *)((char *)pw.at(key) + (size_t)N * (size_t)ld8);
+  }
 };
 
 }  // namespace
@@ -454,6 +512,8 @@ struct Ctx {
   hipEvent_t chain_start = nullptr, chain_done[kMaxSlots] = {nullptr};
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
   int baby[16] = {0};               // baby steps by n; 0 = automatic
+  int compact_from = 10;            // path orders kept compact from A^3 on (0: none)
+  Buf d_status;                     // compact range flags since the last check
   int fused = 0;                    // chain levels inside the persistent launch
   int grid_override = 0;
   bool pending = false;                      // a batch was queued and not yet checked
@@ -513,29 +573,38 @@ void giant_closure(int j, std::set<int> &out) {
   out.insert(j);
 }
 
-// the pair of exponents answering instance m with baby steps c
-void split_instance(int64_t m, int c, int *a, int *b) {
-  if (m <= 2 * (int64_t)c) {
+// The pair of exponents answering instance m with baby steps c: babies
+// 1..c (1..c+2 for a compact set, whose pairs keep both exponents at 3 or
+// above once one is: a compact power pairs only with a compact one).
+void split_instance(int64_t m, int c, bool compact, int *a, int *b) {
+  const int top = compact ? c + 2 : c;
+  if (m <= 2 * (int64_t)top) {
     *a = (int)((m + 1) / 2);
     *b = (int)(m / 2);
   } else {
-    const int j = (int)((m - 1) / c);
+    const int lo = compact ? 3 : 1;  // the baby of the pair: lo .. top
+    const int j = (int)((m - lo) / c);
     *a = j * c;
     *b = (int)(m - (int64_t)j * c);
   }
 }
 
+// whether the trace of the pair (a, b) reads compact powers
+bool compact_pair(bool compact, int a, int b) { return compact && (a > 3 || b > 3); }
+
 // Exponents a batch needs for one path order with baby steps c: the chain
-// top (<= c) and the giant indices (in units of c).
-void batch_needs(const std::vector<int64_t> &ms, int c, int *chain_top, std::set<int> *giants) {
+// top and the giant indices (in units of c).
+void batch_needs(const std::vector<int64_t> &ms, int c, bool compact, int *chain_top,
+                 std::set<int> *giants) {
+  const int top = compact ? c + 2 : c;
   *chain_top = 1;
   for (int64_t m : ms) {
     int a, b;
-    split_instance(m, c, &a, &b);
-    if (m <= 2 * (int64_t)c) {
+    split_instance(m, c, compact, &a, &b);
+    if (m <= 2 * (int64_t)top) {
       *chain_top = std::max(*chain_top, a);
     } else {
-      *chain_top = std::max(*chain_top, c);
+      *chain_top = std::max(*chain_top, top);
       giant_closure(a / c, *giants);
     }
   }
@@ -605,12 +674,25 @@ int baby_of(Ctx *c, int n) {
   return t > 0 ? t : auto_baby(n);
 }
 
-std::vector<int> exponents_of(int chain_top, const std::set<int> &giants, int c) {
+// Keys of the powers a batch needs for one path order (increasing): 16-bit
+// A^1 .. A^top and the giants; for a compact set 16-bit A^1 .. A^3 and
+// compact A^3 .. A^top and giants (when any pair or giant reads one).
+std::vector<int> keys_of(int chain_top, const std::set<int> &giants, int c, bool compact) {
   std::set<int> e;
-  for (int k = 1; k <= chain_top; ++k) e.insert(k);
-  for (int j : giants) e.insert(j * c);
+  if (!compact) {
+    for (int k = 1; k <= chain_top; ++k) e.insert(k);
+    for (int j : giants) e.insert(j * c);
+  } else {
+    for (int k = 1; k <= std::min(chain_top, 3); ++k) e.insert(k);
+    if (chain_top >= 4 || !giants.empty())
+      for (int k = 3; k <= chain_top; ++k) e.insert(k + kCompactKey);
+    for (int j : giants) e.insert(j * c + kCompactKey);
+  }
   return std::vector<int>(e.begin(), e.end());
 }
+
+// compact sets: at least 4 baby steps, so every giant factor is compact
+int compact_baby(int c) { return std::max(c, 4); }
 
 }  // namespace
 
@@ -633,10 +715,15 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     PowerSet &ps = c->sets[p.n];
     ps.N = p.view.N;
     ps.ld = (p.view.N + 63) / 64 * 64;
-    if (ps.c == 0) ps.c = baby_of(c, p.n);
-    batch_needs(kv.second, ps.c, &p.chain_top, &p.giants);
-    p.exps = exponents_of(p.chain_top, p.giants, ps.c);
-    maxexp = std::max(maxexp, p.exps.back());
+    if (ps.c == 0) {
+      // a new set: its form and baby steps are fixed now
+      ps.compact = c->compact_from > 0 && p.n >= c->compact_from && p.n >= 2;
+      ps.ld8 = (p.view.N + 63) / 64 * 64;
+      ps.c = ps.compact ? compact_baby(baby_of(c, p.n)) : baby_of(c, p.n);
+    }
+    batch_needs(kv.second, ps.c, ps.compact, &p.chain_top, &p.giants);
+    p.exps = keys_of(p.chain_top, p.giants, ps.c, ps.compact);
+    for (int key : p.exps) maxexp = std::max(maxexp, key % kCompactKey);
     slot_of[p.n] = (int)plans.size();
     plans.push_back(p);
   }
@@ -645,9 +732,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     size_t extra = 0;
     for (const Plan &p : plans) {
       const PowerSet &ps = c->sets[p.n];
-      const size_t bytes = (size_t)ps.N * (size_t)ps.ld * sizeof(uint16_t);
       for (int e : p.exps)
-        if (!ps.pw.count(e)) extra += bytes;
+        if (!ps.pw.count(e)) extra += ps.bytes_of(e);
     }
     if (c->used + extra > c->budget) {
       set_error("batch needs %zu more bytes of resident powers; %zu of %zu bytes in use", extra,
@@ -657,35 +743,59 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     // the new powers of one n in one allocation (a slab), cut in order
     for (const Plan &p : plans) {
       PowerSet &ps = c->sets[p.n];
-      const size_t bytes = (size_t)ps.N * (size_t)ps.ld * sizeof(uint16_t);
       std::vector<int> missing;
+      size_t total = 0;
       for (int e : p.exps)
-        if (!ps.pw.count(e)) missing.push_back(e);
+        if (!ps.pw.count(e)) {
+          missing.push_back(e);
+          total += ps.bytes_of(e);  // multiples of 64 bytes
+        }
       if (missing.empty()) continue;
       void *slab = nullptr;
-      hipError_t err = hipMalloc(&slab, bytes * missing.size());
+      hipError_t err = hipMalloc(&slab, total);
       if (err != hipSuccess) return hip_fail(err, "hipMalloc (resident powers)");
       ps.slabs.push_back(slab);
-      c->used += bytes * missing.size();
-      for (size_t i = 0; i < missing.size(); ++i) ps.pw[missing[i]] = (char *)slab + i * bytes;
+      ps.held += total;
+      c->used += total;
+      size_t at = 0;
+      for (int e : missing) {
+        ps.pw[e] = (char *)slab + at;
+        at += ps.bytes_of(e);
+      }
     }
   }
   const int nslots = (int)plans.size();
   const bool fused = c->fused != 0;
-  // missing chain levels of each slot: k0[s] .. chain_top (none if beyond)
-  std::vector<int> k0(nslots);
+  // missing chain levels of each slot: 16-bit k0[s] .. top16[s] (none if
+  // beyond), and for a compact set compact k8[s] .. chain_top
+  std::vector<int> k0(nslots), top16(nslots), k8(nslots);
   for (int s = 0; s < nslots; ++s) {
     const PowerSet &ps = c->sets[plans[s].n];
+    top16[s] = ps.compact ? std::min(plans[s].chain_top, 3) : plans[s].chain_top;
     k0[s] = 1;
-    while (k0[s] <= plans[s].chain_top && ps.have.count(k0[s])) ++k0[s];
+    while (k0[s] <= top16[s] && ps.have.count(k0[s])) ++k0[s];
+    k8[s] = plans[s].chain_top + 1;
+    if (ps.compact && ps.pw.count(3 + kCompactKey)) {
+      k8[s] = 3;
+      while (k8[s] <= plans[s].chain_top && ps.have.count(k8[s] + kCompactKey)) ++k8[s];
+    }
   }
+  // compact range flags (cleared by tp_ctx_check)
+  if (!c->d_status.p) {
+    TP_HIP_CHECK(grow(c->d_status, 256, c->retired_dev));
+    TP_HIP_CHECK(launch_fill_i32((int32_t *)c->d_status.p, 1, 0, stream));
+  }
+  int32_t *status = (int32_t *)c->d_status.p;
 
-  // split mode: the chain levels as plain launches, from the lowest missing
-  // level of each n up to its top, on the slot's own stream after what the
-  // caller's stream has queued so far; the caller's stream waits for them
-  if (!fused) {
+  // the chain levels as plain launches (split mode, and the compact sets in
+  // either mode), from the lowest missing level of each n up to its top, on
+  // the slot's own stream after what the caller's stream has queued so far;
+  // the caller's stream waits for them
+  auto launched = [&](int s) { return !fused || c->sets[plans[s].n].compact; };
+  {
     bool any = false;
-    for (int s = 0; s < nslots; ++s) any = any || k0[s] <= plans[s].chain_top;
+    for (int s = 0; s < nslots; ++s)
+      any = any || (launched(s) && (k0[s] <= top16[s] || k8[s] <= plans[s].chain_top));
     if (any) {
       if (!c->chain_start)
         TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_start, hipEventDisableTiming));
@@ -694,20 +804,31 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     for (int s = 0; s < nslots; ++s) {
       const Plan &p = plans[s];
       PowerSet &ps = c->sets[p.n];
-      if (k0[s] > p.chain_top) continue;
+      if (!launched(s) || (k0[s] > top16[s] && k8[s] > p.chain_top)) continue;
       if (!c->chain_stream[s]) {
         TP_HIP_CHECK(hipStreamCreateWithFlags(&c->chain_stream[s], hipStreamNonBlocking));
         TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_done[s], hipEventDisableTiming));
       }
       hipStream_t cs = c->chain_stream[s];
       TP_HIP_CHECK(hipStreamWaitEvent(cs, c->chain_start, 0));
-      for (int k = k0[s]; k <= p.chain_top; ++k) {
+      for (int k = k0[s]; k <= top16[s]; ++k) {
         uint16_t *Y = (uint16_t *)ps.pw.at(k);
         if (k == 1)
           TP_HIP_CHECK(launch_dense_state(p.n, ps.N, p.view.masks, TP_U16, Y, ps.ld, cs));
         else
           TP_HIP_CHECK(state_step_view(p.view, (const uint16_t *)ps.pw.at(k - 1), ps.ld, Y,
                                        ps.ld, ps.N, cs));
+      }
+      for (int k = k8[s]; k <= p.chain_top; ++k) {
+        uint8_t *Y = (uint8_t *)ps.pw.at(k + kCompactKey);
+        int32_t *by = ps.base_of(k + kCompactKey);
+        if (k == 3)
+          TP_HIP_CHECK(launch_shared_from_u16(ps.N, ps.N, (const uint16_t *)ps.pw.at(3), ps.ld, Y,
+                                              ps.ld8, by, status, cs));
+        else
+          TP_HIP_CHECK(launch_shared_step(p.view, (const uint8_t *)ps.pw.at(k - 1 + kCompactKey),
+                                          ps.ld8, ps.base_of(k - 1 + kCompactKey), Y, ps.ld8, by,
+                                          ps.N, status, cs));
       }
       TP_HIP_CHECK(hipEventRecord(c->chain_done[s], cs));
       TP_HIP_CHECK(hipStreamWaitEvent(stream, c->chain_done[s], 0));
@@ -724,7 +845,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     int max_top = 0;
     for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
     for (int s = 0; s < nslots; ++s) {
-      if (plans[s].chain_top < std::max(k0[s], 2)) continue;
+      if (launched(s) || plans[s].chain_top < std::max(k0[s], 2)) continue;
       const int rc = state_fine_view(plans[s].n, stream, &plans[s].fine);
       if (rc != TP_OK) return rc;
     }
@@ -733,7 +854,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     for (int k = 1; k <= max_top; ++k) {
       std::vector<int> set;
       for (int s = 0; s < nslots; ++s)
-        if (k >= k0[s] && k <= plans[s].chain_top) set.push_back(s);
+        if (!launched(s) && k >= k0[s] && k <= plans[s].chain_top) set.push_back(s);
       if (set.empty()) continue;
       if (k >= 2) {
         if (set != prev_part_set) {
@@ -812,10 +933,20 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     nblk[s] = (int)((ps.N + kGBM - 1) / kGBM);
     for (int j : plans[s].giants) {
       const int e = j * ps.c;
-      if (ps.have.count(e)) continue;
+      if (ps.have.count(ps.compact ? e + kCompactKey : e)) continue;
       gbase[{s, e}] = ncounters;
-      ncounters += 2 * nblk[s];
+      // a compact giant also counts its finished tiles in all: the tiles of
+      // a giant made from it wait for the whole of it (its least residual)
+      ncounters += 2 * nblk[s] + (ps.compact ? 1 : 0);
     }
+  }
+  // a new compact giant's least residual starts above any residual; its
+  // tiles lower it
+  for (const auto &kv : gbase) {
+    const PowerSet &ps = c->sets[plans[kv.first.first].n];
+    if (ps.compact)
+      TP_HIP_CHECK(launch_fill_i32(ps.base_of(kv.first.second + kCompactKey) + 1, 1, 0x7FFFFFFF,
+                                   stream));
   }
   auto is_new_giant = [&](int s, int e) { return gbase.count({s, e}) != 0; };
   auto pending = [&](int s, int e) { return is_new_giant(s, e); };
@@ -827,7 +958,11 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   c->work_bytes = 0;
   for (int s = 0; s < nslots; ++s) {
     const double N = (double)plans[s].view.N, nnz = (double)plans[s].view.nnz;
-    for (int k = std::max(k0[s], 2); k <= plans[s].chain_top; ++k) {
+    for (int k = std::max(k0[s], 2); k <= top16[s]; ++k) {
+      c->work_ops[0] += nnz * N;
+      c->work_bytes += 4 * N * N;
+    }
+    for (int k = std::max(k8[s], 4); k <= plans[s].chain_top; ++k) {  // compact steps
       c->work_ops[0] += nnz * N;
       c->work_bytes += 4 * N * N;
     }
@@ -881,7 +1016,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   std::vector<std::vector<int>> waiting(nslots);
   for (int j = 0; j < count; ++j) {
     const int s = slot_of[ns[j]];
-    split_instance(ms[j], c->sets[ns[j]].c, &ta[j], &tb[j]);
+    split_instance(ms[j], c->sets[ns[j]].c, c->sets[ns[j]].compact, &ta[j], &tb[j]);
     waiting[s].push_back(j);
   }
   auto push_ready_traces = [&](int s, int upto) {
@@ -905,8 +1040,9 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         t.row1 = (int32_t)std::min<int64_t>(i0 + 64, N);
         rows_dep(s, a, i0, &t.dep, &t.dep_target);
         cols_dep(s, b, i0, &t.dep2, &t.dep2_target);
-        t.done = t.done2 = -1;
+        t.done = t.done2 = t.done3 = -1;
         t.inst = j;
+        t.compact = compact_pair(c->sets[plans[s].n].compact, a, b);
         tasks.push_back(t);
       }
       deal(first);
@@ -945,10 +1081,22 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
             t.y = y;
             t.row0 = (int32_t)m0;
             t.c0 = (int32_t)n0;
-            rows_dep(s, x, m0, &t.dep, &t.dep_target);
-            cols_dep(s, y, n0, &t.dep2, &t.dep2_target);
             t.done = gbase.at({s, e}) + (int)(m0 / kGBM);
             t.done2 = gbase.at({s, e}) + nblk[s] + (int)(n0 / kGBN);
+            t.done3 = -1;
+            t.compact = ps.compact;
+            if (ps.compact) {
+              // the whole of each factor that is a new giant
+              const int32_t all = nblk[s] * nblk[s];
+              t.dep = is_new_giant(s, x) ? gbase.at({s, x}) + 2 * nblk[s] : -1;
+              t.dep_target = t.dep >= 0 ? all : 0;
+              t.dep2 = is_new_giant(s, y) ? gbase.at({s, y}) + 2 * nblk[s] : -1;
+              t.dep2_target = t.dep2 >= 0 ? all : 0;
+              t.done3 = gbase.at({s, e}) + 2 * nblk[s];
+            } else {
+              rows_dep(s, x, m0, &t.dep, &t.dep_target);
+              cols_dep(s, y, n0, &t.dep2, &t.dep2_target);
+            }
             tasks.push_back(t);
           }
         }
@@ -973,6 +1121,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     t.dep2 = phys(t.dep2);
     t.done = phys(t.done);
     t.done2 = phys(t.done2);
+    t.done3 = phys(t.done3);
   }
   const int64_t counter_words = (int64_t)cfirst + (int64_t)ncounters * kLine;
 
@@ -990,8 +1139,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
 
   // staging (pinned) and device buffers
   const size_t tbytes = tasks.size() * sizeof(Task);
+  // per slot three tables by exponent: 16-bit powers, compact residuals,
+  // compact base words
   const size_t ptr_stride = (size_t)maxexp + 1;
-  const size_t nptr = ptr_stride * nslots;
+  const size_t nptr = 3 * ptr_stride * nslots;
   TP_HIP_CHECK(grow_host(c->h_tasks, std::max<size_t>(tbytes, sizeof(Task)), c->retired_host));
   TP_HIP_CHECK(grow_host(c->h_slots, kMaxSlots * sizeof(Slot), c->retired_host));
   TP_HIP_CHECK(grow_host(c->h_ptrs, nptr * sizeof(void *), c->retired_host));
@@ -1028,14 +1179,22 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     sl.masks = p.view.masks;
     sl.rowptr = p.view.rowptr;
     sl.colz = p.view.colz;
-    sl.powers = (uint16_t *const *)((void **)c->d_ptrs.p + ptr_stride * s);
+    void **tab = (void **)c->d_ptrs.p + 3 * ptr_stride * s;
+    sl.powers = (uint16_t *const *)tab;
+    sl.ld8 = ps.ld8;
+    sl.powers8 = (uint8_t *const *)(tab + ptr_stride);
+    sl.bases8 = (int32_t *const *)(tab + 2 * ptr_stride);
     sl.fptr = p.fine.fptr;
     sl.fent = p.fine.fent;
     sl.finfo = p.fine.finfo;
     hs[s] = sl;
+    void **htab = hp + 3 * ptr_stride * s;
     for (size_t e = 0; e < ptr_stride; ++e) {
       auto it = ps.pw.find((int)e);
-      hp[ptr_stride * s + e] = it == ps.pw.end() ? nullptr : it->second;
+      htab[e] = it == ps.pw.end() ? nullptr : it->second;
+      auto it8 = ps.pw.find((int)e + kCompactKey);
+      htab[ptr_stride + e] = it8 == ps.pw.end() ? nullptr : it8->second;
+      htab[2 * ptr_stride + e] = it8 == ps.pw.end() ? nullptr : ps.base_of((int)e + kCompactKey);
     }
   }
   Control *hc = (Control *)c->h_ctl.p;
@@ -1047,6 +1206,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   hc->abort = 0;
   hc->nlevels = (int32_t)levels.size();
   hc->wait_limit = c->wait_limit;
+  hc->status = status;
 
   // the level barriers need every workgroup resident at once: a fused batch
   // with chain levels never launches more than the chip holds
@@ -1115,13 +1275,27 @@ int ctx_check(Ctx *c, hipStream_t stream) {
                                 sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     TP_HIP_CHECK(hipStreamSynchronize(stream));
   }
-  if (abort) {
-    // nothing the aborted batches were to compute can be trusted
+  int32_t range = 0;
+  if (c->d_status.p) {
+    TP_HIP_CHECK(hipMemcpyAsync(&range, c->d_status.p, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                stream));
+    TP_HIP_CHECK(hipStreamSynchronize(stream));
+    if (range) {
+      TP_HIP_CHECK(launch_fill_i32((int32_t *)c->d_status.p, 1, 0, stream));
+      TP_HIP_CHECK(hipStreamSynchronize(stream));
+    }
+  }
+  if (abort || range) {
+    // nothing the failed batches were to compute can be trusted
     for (auto &kv : c->pending_new)
       for (int e : kv.second) c->sets[kv.first].have.erase(e);
     c->pending_new.clear();
-    set_error("batch aborted: a task waited longer than the limit for its inputs");
-    return TP_ECANCELED;
+    if (abort) {
+      set_error("batch aborted: a task waited longer than the limit for its inputs");
+      return TP_ECANCELED;
+    }
+    set_error("a compact power left the range of its 8-bit residuals");
+    return TP_EOVERFLOW;
   }
   c->pending_new.clear();
   return TP_OK;
@@ -1198,6 +1372,15 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
     c->fused = (int)value;
     return TP_OK;
   }
+  if (param == TP_PARAM_COMPACT_FROM) {
+    TP_REQUIRE(value >= 0 && value <= 13, "TP_PARAM_COMPACT_FROM is 0 (never) or a path order");
+    for (auto &kv : c->sets)
+      TP_REQUIRE(kv.second.pw.empty() || kv.second.compact == (value > 0 && kv.first >= value &&
+                                                               kv.first >= 2),
+                 "the form of n = %d is fixed once its powers are resident", kv.first);
+    c->compact_from = (int)value;
+    return TP_OK;
+  }
   if (param >= TP_PARAM_BABY_STEPS && param < TP_PARAM_BABY_STEPS + 16) {
     const int n = param - TP_PARAM_BABY_STEPS;
     TP_REQUIRE(value >= 0 && value <= (1 << 16), "baby steps out of range");
@@ -1232,9 +1415,8 @@ int tp_ctx_release(void *ctx, int n, hipStream_t stream) {
       ++it;
       continue;
     }
-    const size_t bytes = (size_t)it->second.N * (size_t)it->second.ld * sizeof(uint16_t);
     for (void *slab : it->second.slabs) TP_HIP_CHECK(hipFree(slab));
-    c->used -= bytes * it->second.pw.size();
+    c->used -= it->second.held;
     c->pending_new.erase(it->first);
     it = c->sets.erase(it);
   }
@@ -1247,11 +1429,20 @@ int tp_ctx_copy_power(void *ctx, int n, int e, void *d_out, int64_t ld, hipStrea
   Ctx *c = (Ctx *)ctx;
   std::lock_guard<std::mutex> lk(c->mu);
   auto it = c->sets.find(n);
-  TP_REQUIRE(it != c->sets.end() && it->second.have.count(e) && it->second.pw.count(e),
-             "the context holds no power %d of A(D_%d)", e, n);
+  TP_REQUIRE(e >= 1 && e < kCompactKey, "no power %d", e);
+  const bool have16 = it != c->sets.end() && it->second.have.count(e) && it->second.pw.count(e);
+  const int k8 = e + kCompactKey;
+  const bool have8 = it != c->sets.end() && it->second.have.count(k8) && it->second.pw.count(k8);
+  TP_REQUIRE(have16 || have8, "the context holds no power %d of A(D_%d)", e, n);
   const PowerSet &ps = it->second;
   TP_REQUIRE(ld >= ps.N, "ld = %lld < N = %lld", (long long)ld, (long long)ps.N);
   if (ps.N == 0) return TP_OK;
+  if (!have16) {
+    // a compact power: base + residual, expanded to 16 bits
+    TP_HIP_CHECK(launch_shared_to_u16(ps.N, ps.N, (const uint8_t *)ps.pw.at(k8), ps.ld8,
+                                      ps.base_of(k8), (uint16_t *)d_out, ld, stream));
+    return TP_OK;
+  }
   TP_HIP_CHECK(hipMemcpy2DAsync(d_out, (size_t)ld * sizeof(uint16_t), ps.pw.at(e),
                                 (size_t)ps.ld * sizeof(uint16_t), (size_t)ps.N * sizeof(uint16_t),
                                 (size_t)ps.N, hipMemcpyDeviceToDevice, stream));
@@ -1276,14 +1467,21 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
   int64_t extra = 0;
   for (auto &kv : by_n) {
     const int nn = kv.first;
-    const int64_t N = word_count_host(nn), ld = (N + 63) / 64 * 64;
-    const int cc = baby_of(c, nn);
+    auto it = c->sets.find(nn);
+    PowerSet probe;
+    const bool fresh = it == c->sets.end() || it->second.c == 0;
+    if (fresh) {
+      probe.N = word_count_host(nn);
+      probe.ld = probe.ld8 = (probe.N + 63) / 64 * 64;
+      probe.compact = c->compact_from > 0 && nn >= c->compact_from && nn >= 2;
+      probe.c = probe.compact ? compact_baby(baby_of(c, nn)) : baby_of(c, nn);
+    }
+    const PowerSet &ps = fresh ? probe : it->second;
     int top = 0;
     std::set<int> giants;
-    batch_needs(kv.second, cc, &top, &giants);
-    auto it = c->sets.find(nn);
-    for (int e : exponents_of(top, giants, cc))
-      if (it == c->sets.end() || !it->second.pw.count(e)) extra += N * ld * 2;
+    batch_needs(kv.second, ps.c, ps.compact, &top, &giants);
+    for (int e : keys_of(top, giants, ps.c, ps.compact))
+      if (fresh || !ps.pw.count(e)) extra += ps.bytes_of(e);
   }
   return extra;
 }

@@ -72,11 +72,18 @@ __device__ __forceinline__ uint16_t chunk_elem(const uint4 &c, int e) {
 // All 256 lanes of the workgroup call it; As and Bs are LDS buffers of
 // 2 x BK x BM and 2 x BK x BN entries.  Ends with the epilogue stores (no
 // trailing barrier: the caller synchronizes before reusing the buffers).
+// u8 entries are summed in 16 bits and stored clamped to 255.  For u8
+// operands that are residuals over a base (255 out of range, not INF):
+// `sub` is subtracted from every sum before the clamp, a tile that clamps an
+// entry sets bit 1 of *sat, and each wave folds the least entry it stores
+// into *least (atomic min).
 template <int BM, int BN, int BK, int TM, int TN, typename T, bool VEC>
 __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restrict__ A,
                                           int64_t lda, const T *__restrict__ B, int64_t ldb,
                                           T *__restrict__ C, int64_t ldc, int accumulate, int m0,
-                                          int n0, uint16_t (*As)[BK][BM], uint16_t (*Bs)[BK][BN]) {
+                                          int n0, uint16_t (*As)[BK][BM], uint16_t (*Bs)[BK][BN],
+                                          int32_t *sat = nullptr, uint16_t sub = 0,
+                                          int32_t *least = nullptr) {
   constexpr int kThreads = kGemmThreads;
   static_assert((BM / TM) * (BN / TN) == kThreads, "thread layout");
   static_assert(TM % 8 == 0 || TM == 4, "A fragment");
@@ -226,6 +233,8 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
 
   // epilogue
   constexpr uint16_t OUT_INF = Storage<T>::inf;
+  bool clamped = false;
+  int32_t low = 0xFFFF;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int r = m0 + tm * TM + i;
@@ -235,7 +244,15 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
     for (int j = 0; j < TN2; ++j) {
       const int c = n0 + tn * TN + 2 * j;
       u16x2 v = acc[i][j];
-      if constexpr (sizeof(T) == 1) v = pk_min(v, splat(OUT_INF));
+      if constexpr (sizeof(T) == 1) {
+        if (sat) {
+          v = __builtin_elementwise_sub_sat(v, splat(sub));
+          clamped |= (c < N && v.x >= OUT_INF) || (c + 1 < N && v.y >= OUT_INF);
+          if (c < N) low = min(low, (int32_t)v.x);
+          if (c + 1 < N) low = min(low, (int32_t)v.y);
+        }
+        v = pk_min(v, splat(OUT_INF));
+      }
       if (c + 1 < N) {
         if (accumulate) {
           const u16x2 old = u16x2{(uint16_t)crow[c], (uint16_t)crow[c + 1]};
@@ -258,6 +275,11 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
         crow[c] = (T)x;
       }
     }
+  }
+  if (sat && clamped) atomicOr(sat, 1);
+  if (least) {
+    for (int off = 32; off > 0; off >>= 1) low = min(low, __shfl_xor(low, off));
+    if ((threadIdx.x & 63) == 0 && low < 0xFFFF) atomicMin(least, low);
   }
 }
 

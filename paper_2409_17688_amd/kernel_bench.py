@@ -21,7 +21,8 @@ the algorithmic work of one launch:
   gather the same product by the packed per-row gather (tp_state_left_mul)
   trace  2 N^2 entries read (4 N^2 bytes)
   gemm   N^3 (min,+) operations
-  batch  one persistent launch answering the instances (cold context)
+  batch  one persistent launch answering the instances (cold context;
+         --compact-from sets which path orders keep compact powers)
   cdiff  constant-difference test of A^2 against A (tp_const_diff): 2 N^2
          entries read (4 N^2 bytes)
   recurrence  tp_recurrence(n, K, window): K powers, each compared with the
@@ -75,6 +76,8 @@ def main(argv=None):
     ap.add_argument("--instances", default="mixed64", help="batch workload: mixed64 or n:mlist")
     ap.add_argument("--fused", action="store_true",
                     help="batch: chain levels inside the persistent launch too")
+    ap.add_argument("--compact-from", type=int, default=None,
+                    help="batch: TP_PARAM_COMPACT_FROM (path orders kept as compact powers)")
     ap.add_argument("--K", type=int, default=50, help="recurrence: powers computed")
     ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
     ap.add_argument("--N", type=int, default=8192, help="apsp: order of the digraph")
@@ -223,15 +226,19 @@ def main(argv=None):
             ctx = tp.tp_ctx_create(64 << 30)
             try:
                 tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, int(args.fused))
+                if args.compact_from is not None:
+                    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, args.compact_from)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 tp.tp_batch_power_trace(ctx, ns, ms)
                 tp.tp_ctx_check(ctx)
                 times.append(time.perf_counter() - t0)
+                resident = tp.tp_ctx_resident_bytes(ctx)
             finally:
                 tp.tp_ctx_destroy(ctx)
-        out.update({"instances": len(inst), "fused": args.fused, "ms": min(times) * 1e3,
-                    "ms_all": [round(t * 1e3, 2) for t in times]})
+        out.update({"instances": len(inst), "fused": args.fused,
+                    "compact_from": args.compact_from, "resident_bytes": resident,
+                    "ms": min(times) * 1e3, "ms_all": [round(t * 1e3, 2) for t in times]})
     print(json.dumps(out), flush=True)
 
 

@@ -23,18 +23,34 @@ def _closure(j, out):
     out.add(j)
 
 
-def model_bytes(n, ms, c):
+def model_bytes(n, ms, c, compact_from=10):
+    """Bytes of the powers the planning rules call for.  Path orders from
+    compact_from on (TP_PARAM_COMPACT_FROM) keep A^1..A^3 in 16 bits and A^3
+    on as u8 residuals (rows of ld bytes) with 256 bytes of base words each;
+    their baby steps are at least 4 and run to c + 2, and a pair with a
+    baby above 3 keeps its baby at 3 or above."""
     N = tp.tp_state_dim(n)
     ld = (N + 63) // 64 * 64
+    compact = compact_from > 0 and n >= compact_from and n >= 2
+    if compact:
+        c = max(c, 4)
+    babies = c + 2 if compact else c
+    lo = 3 if compact else 1
     top, giants = 1, set()
     for m in ms:
-        if m <= 2 * c:
+        if m <= 2 * babies:
             top = max(top, (m + 1) // 2)
         else:
-            top = max(top, c)
-            _closure((m - 1) // c, giants)
-    exps = set(range(1, top + 1)) | {j * c for j in giants}
-    return len(exps) * N * ld * 2
+            top = max(top, babies)
+            _closure((m - lo) // c, giants)
+    if not compact:
+        exps = set(range(1, top + 1)) | {j * c for j in giants}
+        return len(exps) * N * ld * 2
+    wide = set(range(1, min(top, 3) + 1))
+    narrow = {j * c for j in giants}
+    if top >= 4 or giants:
+        narrow |= set(range(3, top + 1))
+    return len(wide) * N * ld * 2 + len(narrow) * (N * ld + 256)
 
 
 @pytest.fixture
@@ -56,6 +72,29 @@ def test_need_bytes_matches_the_planning_rules(ctx, c):
             continue
         got = tp.tp_ctx_need_bytes(ctx, [n] * len(ms), ms)
         assert got == model_bytes(n, ms, c), (n, ms, c)
+
+
+@pytest.mark.parametrize("compact_from", [0, 3, 7])
+def test_need_bytes_follows_the_compact_rules(ctx, compact_from):
+    rng = np.random.default_rng(100 + compact_from)
+    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, compact_from)
+    for n in (2, 3, 5, 7, 9, 11):
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 5)
+    for trial in range(30):
+        n = int(rng.choice([2, 3, 5, 7, 9, 11]))
+        ms = [int(m) for m in rng.integers(3, 400, int(rng.integers(1, 12)))]
+        if n * max(ms) >= 65535:
+            continue
+        got = tp.tp_ctx_need_bytes(ctx, [n] * len(ms), ms)
+        assert got == model_bytes(n, ms, 5, compact_from), (n, ms, compact_from)
+
+
+def test_compact_parameter_bounds(ctx):
+    for bad in (-1, 14):
+        with pytest.raises(tp.TropicalError):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, bad)
+    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 0)
+    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 13)
 
 
 def test_need_bytes_adds_over_path_orders(ctx):

@@ -354,3 +354,65 @@ def test_chain_powers_equal_the_oracle(tp, oracle_mod, fused):
             tp.tp_ctx_copy_power(ctx, 8, 99)
     finally:
         tp.tp_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+def test_compact_sets_equal_the_oracle(tp, oracle_table_500, fused):
+    # path orders from 3 on keep A^3 and above as shared-base compact powers:
+    # pairs of compact babies, giants as products of compact powers (bases
+    # added) and traces adding the two bases, against the oracle; m = 3..6
+    # are answered by the 16-bit A^1..A^3, m >= 7 by compact pairs
+    rng = np.random.default_rng(31)
+    inst = [(int(rng.integers(2, 9)), int(rng.integers(3, 501))) for _ in range(60)]
+    inst += [(n, m) for n in (3, 6, 8) for m in (3, 4, 5, 6, 7, 8, 13, 14, 15, 16, 17, 40, 41)]
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, fused)
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 3)
+        for n in range(2, 9):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 5)
+        say("compact batch, fused", fused)
+        need = tp.tp_ctx_need_bytes(ctx, [n for n, _ in inst], [m for _, m in inst])
+        got = _run(tp, ctx, inst)
+        assert got == [int(oracle_table_500[n][m - 1]) for n, m in inst]
+        assert tp.tp_ctx_resident_bytes(ctx) == need
+        # resident compact powers answer the next batch, which adds giants
+        inst2 = [(8, m) for m in (499, 400, 257, 129, 9)] + [(5, 450), (3, 7), (7, 333)]
+        got2 = _run(tp, ctx, inst2)
+        assert got2 == [int(oracle_table_500[n][m - 1]) for n, m in inst2]
+        with pytest.raises(tp.TropicalError):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 0)
+    finally:
+        tp.tp_ctx_destroy(ctx)
+
+
+def test_compact_powers_equal_the_oracle(tp, oracle_mod):
+    # compact babies and giants, expanded to 16 bits by tp_ctx_copy_power,
+    # entry by entry against the oracle's chain A^k = A x A^(k-1)
+    import torch
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 3)
+        for n in (5, 8):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 4)
+        inst = [(5, 12), (8, 12), (5, 40), (8, 40)]
+        got = _run(tp, ctx, inst)
+        for n in (5, 8):
+            A = oracle_mod.state_matrix(n)
+            P = A
+            want = {}
+            for k in range(1, 37):
+                if k > 1:
+                    P = oracle_mod.minplus(A, P)
+                if k in (1, 2, 3, 4, 5, 6, 8, 16, 32, 36):
+                    want[k] = P
+            for k, W in want.items():
+                G = tp.tp_ctx_copy_power(ctx, n, k)
+                torch.cuda.synchronize()
+                g = G.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.int32)
+                bad = np.argwhere(g != W)
+                assert bad.size == 0, (n, k, bad[:5].tolist())
+            assert got[[i for i, (a, _) in enumerate(inst) if a == n][0]] == \
+                oracle_mod.trace_min(oracle_mod.minplus(want[6], want[6]))
+    finally:
+        tp.tp_ctx_destroy(ctx)
