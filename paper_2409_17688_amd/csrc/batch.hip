@@ -193,7 +193,7 @@ __device__ __forceinline__ void part_item(const Slot *__restrict__ slots, uint32
   const int64_t N = wave_uniform((int64_t)sl.N), ld = wave_uniform(sl.ld);
   const int64_t panel = (code >> 20) & 0xFFu, f = code & 0xFFFFFu;
   uint16_t *const *powers = wave_uniform(sl.powers);
-  part_rows<4, 4>((kconst_i64)wave_uniform(sl.fptr), (kconst_u64)wave_uniform(sl.fent),
+  part_rows<4, 4, 2>((kconst_i64)wave_uniform(sl.fptr), (kconst_u64)wave_uniform(sl.fent),
                   (kconst_u32)wave_uniform(sl.finfo), f, wave_uniform(powers[lev - 1]), ld,
                   wave_uniform(powers[lev]), ld, N, N, panel * kPanel + (int64_t)lane * 8, wv,
                   lane, (__attribute__((address_space(3))) uint32_t *)lds_words);

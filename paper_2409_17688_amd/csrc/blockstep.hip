@@ -306,7 +306,12 @@ __global__ void __launch_bounds__(256) block_step_pipe_kernel(
 // blocks (entries ptr[f] .. ptr[f+1]-1 of part f, info[f] = block << 16 | the
 // part's row mask): a part bound at half the longest block halves the
 // longest run of entries a wave walks, for a few more gathers.
-template <int U, int W, int V, int WPE>
+//
+// T4: the tree stops at four waves, which all hand their minima to LDS; each
+// then folds four of the 16 rows over the four and stores them (one round
+// and two barriers fewer than halving down to wave 0, and four waves
+// storing instead of one).
+template <int U, int W, int V, int WPE, bool T4 = true>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE)))
 block_split_step_kernel(
     int64_t N, int64_t nitems, const int64_t *__restrict__ bptr,
@@ -314,7 +319,9 @@ block_split_step_kernel(
     const uint32_t *__restrict__ info, const uint16_t *__restrict__ X, int64_t ldx,
     uint16_t *__restrict__ Y, int64_t ldy, int64_t ncols) {
   typedef typename ChunkOf<V>::type chunk;
-  __shared__ uint32_t part[W / 2][kRows * V][64];
+  static_assert(!T4 || W >= 4, "four waves at least");
+  constexpr int kSlots = (T4 && W / 2 < 4) ? 4 : W / 2;
+  __shared__ uint32_t part[kSlots][kRows * V][64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -346,7 +353,7 @@ block_split_step_kernel(
   block_entries<U, V>(en, my0, my1, Xg, ldc, off, acc);
   // the W partial minima meet in LDS, halving the waves each round
 #pragma unroll 1
-  for (int half = W / 2; half >= 1; half /= 2) {
+  for (int half = W / 2; half >= (T4 ? 4 : 1); half /= 2) {
     if (wave >= half && wave < 2 * half) {
 #pragma unroll
       for (int r = 0; r < kRows; ++r)
@@ -362,6 +369,43 @@ block_split_step_kernel(
           acc[r][k] = pk_min(acc[r][k], as_pk(part[wave][r * V + k][lane]));
     }
     __syncthreads();
+  }
+  if constexpr (T4) {
+    if (wave < 4) {
+#pragma unroll
+      for (int r = 0; r < kRows; ++r)
+#pragma unroll
+        for (int k = 0; k < V; ++k) part[wave][r * V + k][lane] = as_u32(acc[r][k]);
+    }
+    __syncthreads();
+    if (wave >= 4 || c0 >= ncols) return;
+#pragma unroll
+    for (int i = 0; i < kRows / 4; ++i) {
+      const int r = wave * (kRows / 4) + i;
+      const int64_t q = b * kRows + r;
+      if (q >= N || !(rows & (1u << r))) continue;
+      u16x2 m[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        m[k] = as_pk(part[0][r * V + k][lane]);
+#pragma unroll
+        for (int w = 1; w < 4; ++w) m[k] = pk_min(m[k], as_pk(part[w][r * V + k][lane]));
+      }
+      if (c0 + 2 * V <= ncols) {
+        chunk o;
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = as_u32(m[k]);
+        *(gmut<chunk>)(to_global_mut(Y) + q * ldy + c0) = o;
+      } else {
+        const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          if (c0 + 2 * k < ncols) y[2 * k] = m[k].x;
+          if (c0 + 2 * k + 1 < ncols) y[2 * k + 1] = m[k].y;
+        }
+      }
+    }
+    return;
   }
   if (wave != 0 || c0 >= ncols) return;
 #pragma unroll
@@ -401,15 +445,15 @@ __global__ void __launch_bounds__(256) part_step_kernel(
     const uint32_t *__restrict__ finfo, const int32_t *__restrict__ forder,
     const uint16_t *__restrict__ X, int64_t ldx, uint16_t *__restrict__ Y, int64_t ldy,
     int64_t ncols) {
-  __shared__ uint32_t part[2 * kRows * 2 * 64];
+  __shared__ uint32_t part[4 * kRows * 2 * 64];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t panel = t / nf;
   const int64_t f = ((kconst_i32)forder)[t - panel * nf];
-  part_rows<U, 2>((kconst_i64)fptr, (kconst_u64)fent, (kconst_u32)finfo, f, X, ldx, Y, ldy, N,
-                  ncols, panel * 256 + (int64_t)lane * 4, wv, lane,
-                  (__attribute__((address_space(3))) uint32_t *)part);
+  part_rows<U, 2, 4>((kconst_i64)fptr, (kconst_u64)fent, (kconst_u32)finfo, f, X, ldx, Y, ldy,
+                     N, ncols, panel * 256 + (int64_t)lane * 4, wv, lane,
+                     (__attribute__((address_space(3))) uint32_t *)part);
 }
 
 hipError_t launch_block_step_u16(int64_t N, const int64_t *bptr, const uint64_t *ent,

@@ -295,13 +295,14 @@ __device__ __forceinline__ void block_entries(kconst_u64 en, int64_t i0, int64_t
 // One (part f, 128V-column panel) item of Y = A x X on row-block parts, for
 // a workgroup of four waves: each wave folds a quarter of the part's
 // entries into the 16 rows' minima at its lane's 2V columns (16V
-// registers), waves 2 and 3 hand theirs to waves 0 and 1 through LDS, then
-// wave 1 to wave 0, which stores the rows of the part's mask.  `part` is
-// 8V KB of LDS ([2][16 rows x V][64] words).  Columns c0 .. c0+2V-1 of X
-// and Y, c0 < ncols for the lanes that store; X rows are whole 4V-byte
-// chunks (ldx % 2V == 0).  Every wave of the workgroup must call it with the
-// same item.
-template <int U, int V>
+// registers).  The minima meet in `part`, S slots of LDS ([S][16 rows x
+// V][64] words, 4 S V KB): with S = 2 waves 2 and 3 first hand theirs to
+// waves 0 and 1; then the S waves write theirs and each folds 16 / S of the
+// rows over the S slots and stores those of the part's mask (S waves
+// storing, not one).  Columns c0 .. c0+2V-1 of X and Y, c0 < ncols for the
+// lanes that store; X rows are whole 4V-byte chunks (ldx % 2V == 0).  Every
+// wave of the workgroup must call it with the same item.
+template <int U, int V, int S>
 __device__ __forceinline__ void part_rows(kconst_i64 fptr, kconst_u64 fent, kconst_u32 finfo,
                                           int64_t f, const uint16_t *X, int64_t ldx, uint16_t *Y,
                                           int64_t ldy, int64_t N, int64_t ncols, int64_t c0,
@@ -321,17 +322,17 @@ __device__ __forceinline__ void part_rows(kconst_i64 fptr, kconst_u64 fent, kcon
     for (int k = 0; k < V; ++k) acc[r][k] = splat(0xFFFFu);
   block_entries<U, V>(fent, my0, my1, (gconst<chunk>)to_global(X), ldx / (2 * V),
                       c0 < ncols ? (uint32_t)(c0 / (2 * V)) : 0u, acc);
-#pragma unroll 1
-  for (int half = 2; half >= 1; half /= 2) {
-    if (wv >= half && wv < 2 * half) {
+  static_assert(S == 2 || S == 4, "two or four slots");
+  if constexpr (S == 2) {
+    if (wv >= 2) {
 #pragma unroll
       for (int r = 0; r < kBlockRows; ++r)
 #pragma unroll
         for (int k = 0; k < V; ++k)
-          part[((wv - half) * kBlockRows * V + r * V + k) * 64 + lane] = as_u32(acc[r][k]);
+          part[((wv - 2) * kBlockRows * V + r * V + k) * 64 + lane] = as_u32(acc[r][k]);
     }
     __syncthreads();
-    if (wv < half) {
+    if (wv < 2) {
 #pragma unroll
       for (int r = 0; r < kBlockRows; ++r)
 #pragma unroll
@@ -340,25 +341,45 @@ __device__ __forceinline__ void part_rows(kconst_i64 fptr, kconst_u64 fent, kcon
     }
     __syncthreads();
   }
-  if (wv != 0 || c0 >= ncols) return;
+  if (wv < S) {
 #pragma unroll
-  for (int r = 0; r < kBlockRows; ++r) {
-    const int64_t q = b * kBlockRows + r;
-    if (!(rows & (1u << r)) || q >= N) continue;
-    if (c0 + 2 * V <= ncols) {
-      chunk o;
+    for (int r = 0; r < kBlockRows; ++r)
 #pragma unroll
-      for (int k = 0; k < V; ++k) o[k] = as_u32(acc[r][k]);
-      *(gmut<chunk>)(to_global_mut(Y) + q * ldy + c0) = o;
-    } else {
-      const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
+      for (int k = 0; k < V; ++k)
+        part[(wv * kBlockRows * V + r * V + k) * 64 + lane] = as_u32(acc[r][k]);
+  }
+  __syncthreads();
+  if (wv < S && c0 < ncols) {
+#pragma unroll
+    for (int i = 0; i < kBlockRows / S; ++i) {
+      const int r = wv * (kBlockRows / S) + i;
+      const int64_t q = b * kBlockRows + r;
+      if (!(rows & (1u << r)) || q >= N) continue;
+      u16x2 m[V];
 #pragma unroll
       for (int k = 0; k < V; ++k) {
-        if (c0 + 2 * k < ncols) y[2 * k] = acc[r][k].x;
-        if (c0 + 2 * k + 1 < ncols) y[2 * k + 1] = acc[r][k].y;
+        m[k] = as_pk(part[(r * V + k) * 64 + lane]);
+#pragma unroll
+        for (int w = 1; w < S; ++w)
+          m[k] = pk_min(m[k], as_pk(part[(w * kBlockRows * V + r * V + k) * 64 + lane]));
+      }
+      if (c0 + 2 * V <= ncols) {
+        chunk o;
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = as_u32(m[k]);
+        *(gmut<chunk>)(to_global_mut(Y) + q * ldy + c0) = o;
+      } else {
+        const gmut<uint16_t> y = to_global_mut(Y) + q * ldy + c0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          if (c0 + 2 * k < ncols) y[2 * k] = m[k].x;
+          if (c0 + 2 * k + 1 < ncols) y[2 * k + 1] = m[k].y;
+        }
       }
     }
   }
+  // the slots are read before the workgroup's next item writes them
+  __syncthreads();
 }
 
 // Eight consecutive entries of row `row` from column `col`, widened to 16
