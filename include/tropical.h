@@ -471,9 +471,10 @@ int tp_gamma2_recurrence(const tp_recurrence_t *rec, const int32_t *diag_min, in
  * has both at 3 or above: (ceil(m/2), floor(m/2)) when m <= 2(c + 2), else
  * (jc, m - jc) with 3 <= m - jc <= c + 2; a giant is the product of two
  * compact powers (residuals summed in 16 bits, bases added), a trace adds the
- * two bases to the residuals' minimum.  Powers persist across batches until
- * the context is destroyed.  A context is used from one host thread and one
- * stream at a time. */
+ * two bases to the residuals' minimum.  From TP_PARAM_CHAIN_GIANTS_FROM on
+ * (default 10) the giants come from the chain itself instead.  Powers persist
+ * across batches until the context is destroyed.  A context is used from one
+ * host thread and one stream at a time. */
 int tp_ctx_create(size_t hbm_budget_bytes, void **ctx);
 int tp_ctx_destroy(void *ctx);
 
@@ -489,6 +490,11 @@ int tp_ctx_destroy(void *ctx);
                                     (0: none; default 10); fixed per n once its powers are
                                     resident.  A batch with compact sets runs their chain
                                     levels as launches in either mode */
+#define TP_PARAM_CHAIN_GIANTS_FROM 5 /* path orders n >= value make their giants by continuing
+                                    the chain (sparse left steps through two more buffers of
+                                    the set, no smaller giants) instead of dense products
+                                    (0: never; default 10, where jc steps cost less than the
+                                    products); fixed per n once its powers are resident */
 #define TP_PARAM_BABY_STEPS 32   /* TP_PARAM_BABY_STEPS + n: chain length c; 0 = auto (16 for
                                     n >= 8, else 32); fixed once powers of n are resident */
 int tp_ctx_set_param(void *ctx, int param, int64_t value);

@@ -31,6 +31,7 @@ TP_PARAM_WAIT_LIMIT_US = 1
 TP_PARAM_GRID = 2
 TP_PARAM_FUSED_CHAIN = 3
 TP_PARAM_COMPACT_FROM = 4
+TP_PARAM_CHAIN_GIANTS_FROM = 5
 TP_PARAM_BABY_STEPS = 32
 TP_STEP_AUTO = 0
 TP_STEP_CSR = 1

@@ -470,8 +470,10 @@ hipError_t grow_host(Buf &b, size_t bytes, std::vector<void *> &retired) {
 }
 
 // Keys of a power set: the exponent e for a 16-bit power, e + kCompactKey
-// for a shared-base compact one.
+// for a shared-base compact one, kTempKey and kTempKey + 1 for the two
+// buffers a chain of giants steps through (in the set's chain form).
 constexpr int kCompactKey = 1 << 16;
+constexpr int kTempKey = 1 << 20;
 
 struct PowerSet {
   int64_t N = 0, ld = 0;
@@ -481,13 +483,17 @@ struct PowerSet {
   // after the residuals
   bool compact = false;
   int64_t ld8 = 0;
+  // giants by continuing the chain (sparse steps) instead of dense products
+  // (fixed at first use)
+  bool chain_giants = false;
   std::map<int, void *> pw;  // key -> device buffer (inside a slab)
   std::set<int> have;        // keys known complete on the device
   std::vector<void *> slabs;  // one allocation per batch that added powers
   size_t held = 0;            // bytes of the slabs
   size_t bytes16() const { return (size_t)N * (size_t)ld * sizeof(uint16_t); }
   size_t bytes8() const { return (size_t)N * (size_t)ld8 + 256; }
-  size_t bytes_of(int key) const { return key >= kCompactKey ? bytes8() : bytes16(); }
+  bool narrow(int key) const { return key >= kTempKey ? compact : key >= kCompactKey; }
+  size_t bytes_of(int key) const { return narrow(key) ? bytes8() : bytes16(); }
   int32_t *base_of(int key) const {
     return (int32_t *)((char *)pw.at(key) + (size_t)N * (size_t)ld8);
   }
@@ -513,6 +519,7 @@ struct Ctx {
   int64_t wait_limit = 2000000000;  // 20 s at 100 MHz
   int baby[16] = {0};               // baby steps by n; 0 = automatic
   int compact_from = 10;            // path orders kept compact from A^3 on (0: none)
+  int chain_giants_from = 10;       // path orders whose giants continue the chain (0: none)
   Buf d_status;                     // compact range flags since the last check
   int fused = 0;                    // chain levels inside the persistent launch
   int grid_override = 0;
@@ -594,8 +601,8 @@ bool compact_pair(bool compact, int a, int b) { return compact && (a > 3 || b > 
 
 // Exponents a batch needs for one path order with baby steps c: the chain
 // top and the giant indices (in units of c).
-void batch_needs(const std::vector<int64_t> &ms, int c, bool compact, int *chain_top,
-                 std::set<int> *giants) {
+void batch_needs(const std::vector<int64_t> &ms, int c, bool compact, bool chain_giants,
+                 int *chain_top, std::set<int> *giants) {
   const int top = compact ? c + 2 : c;
   *chain_top = 1;
   for (int64_t m : ms) {
@@ -605,7 +612,11 @@ void batch_needs(const std::vector<int64_t> &ms, int c, bool compact, int *chain
       *chain_top = std::max(*chain_top, a);
     } else {
       *chain_top = std::max(*chain_top, top);
-      giant_closure(a / c, *giants);
+      // a chained giant needs no smaller giants; a product giant its closure
+      if (chain_giants)
+        giants->insert(a / c);
+      else
+        giant_closure(a / c, *giants);
     }
   }
 }
@@ -677,8 +688,13 @@ int baby_of(Ctx *c, int n) {
 // Keys of the powers a batch needs for one path order (increasing): 16-bit
 // A^1 .. A^top and the giants; for a compact set 16-bit A^1 .. A^3 and
 // compact A^3 .. A^top and giants (when any pair or giant reads one).
-std::vector<int> keys_of(int chain_top, const std::set<int> &giants, int c, bool compact) {
+std::vector<int> keys_of(int chain_top, const std::set<int> &giants, int c, bool compact,
+                         bool chain_giants) {
   std::set<int> e;
+  if (chain_giants && !giants.empty()) {
+    e.insert(kTempKey);
+    e.insert(kTempKey + 1);
+  }
   if (!compact) {
     for (int k = 1; k <= chain_top; ++k) e.insert(k);
     for (int j : giants) e.insert(j * c);
@@ -718,11 +734,12 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     if (ps.c == 0) {
       // a new set: its form and baby steps are fixed now
       ps.compact = c->compact_from > 0 && p.n >= c->compact_from && p.n >= 2;
+      ps.chain_giants = c->chain_giants_from > 0 && p.n >= c->chain_giants_from;
       ps.ld8 = (p.view.N + 63) / 64 * 64;
       ps.c = ps.compact ? compact_baby(baby_of(c, p.n)) : baby_of(c, p.n);
     }
-    batch_needs(kv.second, ps.c, ps.compact, &p.chain_top, &p.giants);
-    p.exps = keys_of(p.chain_top, p.giants, ps.c, ps.compact);
+    batch_needs(kv.second, ps.c, ps.compact, ps.chain_giants, &p.chain_top, &p.giants);
+    p.exps = keys_of(p.chain_top, p.giants, ps.c, ps.compact, ps.chain_giants);
     for (int key : p.exps) maxexp = std::max(maxexp, key % kCompactKey);
     slot_of[p.n] = (int)plans.size();
     plans.push_back(p);
@@ -791,11 +808,26 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   // either mode), from the lowest missing level of each n up to its top, on
   // the slot's own stream after what the caller's stream has queued so far;
   // the caller's stream waits for them
-  auto launched = [&](int s) { return !fused || c->sets[plans[s].n].compact; };
+  auto launched = [&](int s) {
+    const PowerSet &ps = c->sets[plans[s].n];
+    return !fused || ps.compact || ps.chain_giants;
+  };
+  // giants a chain makes: the missing ones of the sets that chain them
+  std::vector<std::vector<int>> gchain(nslots);
+  std::vector<int64_t> gsteps(nslots, 0);  // steps those chains take
+  for (int s = 0; s < nslots; ++s) {
+    const PowerSet &ps = c->sets[plans[s].n];
+    if (!ps.chain_giants) continue;
+    for (int j : plans[s].giants) {
+      const int e = j * ps.c;
+      if (!ps.have.count(ps.compact ? e + kCompactKey : e)) gchain[s].push_back(e);
+    }
+  }
   {
     bool any = false;
     for (int s = 0; s < nslots; ++s)
-      any = any || (launched(s) && (k0[s] <= top16[s] || k8[s] <= plans[s].chain_top));
+      any = any || (launched(s) && (k0[s] <= top16[s] || k8[s] <= plans[s].chain_top ||
+                                    !gchain[s].empty()));
     if (any) {
       if (!c->chain_start)
         TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_start, hipEventDisableTiming));
@@ -804,7 +836,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     for (int s = 0; s < nslots; ++s) {
       const Plan &p = plans[s];
       PowerSet &ps = c->sets[p.n];
-      if (!launched(s) || (k0[s] > top16[s] && k8[s] > p.chain_top)) continue;
+      if (!launched(s) || (k0[s] > top16[s] && k8[s] > p.chain_top && gchain[s].empty()))
+        continue;
       if (!c->chain_stream[s]) {
         TP_HIP_CHECK(hipStreamCreateWithFlags(&c->chain_stream[s], hipStreamNonBlocking));
         TP_HIP_CHECK(hipEventCreateWithFlags(&c->chain_done[s], hipEventDisableTiming));
@@ -829,6 +862,35 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
           TP_HIP_CHECK(launch_shared_step(p.view, (const uint8_t *)ps.pw.at(k - 1 + kCompactKey),
                                           ps.ld8, ps.base_of(k - 1 + kCompactKey), Y, ps.ld8, by,
                                           ps.N, status, cs));
+      }
+      // giants by continuing the chain: from the highest power below each
+      // missing giant (the babies' top, a resident giant or the last one
+      // made), through the two step buffers, into the giant
+      if (!gchain[s].empty()) {
+        const int top = p.chain_top;
+        auto form_key = [&](int e) { return ps.compact ? e + kCompactKey : e; };
+        int from = top;  // the babies' top is complete on this stream
+        for (int e : gchain[s]) {
+          for (const auto &kv : ps.pw) {
+            const int k = kv.first;
+            if (k >= kTempKey || (ps.compact != (k >= kCompactKey))) continue;
+            const int ek = k % kCompactKey;
+            if (ek < e && ek > from && ps.have.count(k)) from = ek;
+          }
+          gsteps[s] += e - from;
+          for (int k = from + 1; k <= e; ++k) {
+            const int xk = k - 1 == from ? form_key(from) : kTempKey + ((k - 1) & 1);
+            const int yk = k == e ? form_key(e) : kTempKey + (k & 1);
+            if (ps.compact)
+              TP_HIP_CHECK(launch_shared_step(p.view, (const uint8_t *)ps.pw.at(xk), ps.ld8,
+                                              ps.base_of(xk), (uint8_t *)ps.pw.at(yk), ps.ld8,
+                                              ps.base_of(yk), ps.N, status, cs));
+            else
+              TP_HIP_CHECK(state_step_view(p.view, (const uint16_t *)ps.pw.at(xk), ps.ld,
+                                           (uint16_t *)ps.pw.at(yk), ps.ld, ps.N, cs));
+          }
+          from = e;
+        }
       }
       TP_HIP_CHECK(hipEventRecord(c->chain_done[s], cs));
       TP_HIP_CHECK(hipStreamWaitEvent(stream, c->chain_done[s], 0));
@@ -933,6 +995,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
     nblk[s] = (int)((ps.N + kGBM - 1) / kGBM);
     for (int j : plans[s].giants) {
       const int e = j * ps.c;
+      if (ps.chain_giants) continue;  // made by the chain before the kernel
       if (ps.have.count(ps.compact ? e + kCompactKey : e)) continue;
       gbase[{s, e}] = ncounters;
       // a compact giant also counts its finished tiles in all: the tiles of
@@ -966,6 +1029,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       c->work_ops[0] += nnz * N;
       c->work_bytes += 4 * N * N;
     }
+    c->work_ops[0] += (double)gsteps[s] * nnz * N;  // chained giants
+    c->work_bytes += (double)gsteps[s] * 4 * N * N;
     if (k0[s] <= 1 && plans[s].chain_top >= 1) c->work_bytes += 2 * N * N;  // A^1 written
   }
   for (const auto &kv : gbase) {
@@ -1372,6 +1437,16 @@ int tp_ctx_set_param(void *ctx, int param, int64_t value) {
     c->fused = (int)value;
     return TP_OK;
   }
+  if (param == TP_PARAM_CHAIN_GIANTS_FROM) {
+    TP_REQUIRE(value >= 0 && value <= 13,
+               "TP_PARAM_CHAIN_GIANTS_FROM is 0 (never) or a path order");
+    for (auto &kv : c->sets)
+      TP_REQUIRE(kv.second.pw.empty() ||
+                     kv.second.chain_giants == (value > 0 && kv.first >= value),
+                 "how n = %d makes its giants is fixed once its powers are resident", kv.first);
+    c->chain_giants_from = (int)value;
+    return TP_OK;
+  }
   if (param == TP_PARAM_COMPACT_FROM) {
     TP_REQUIRE(value >= 0 && value <= 13, "TP_PARAM_COMPACT_FROM is 0 (never) or a path order");
     for (auto &kv : c->sets)
@@ -1474,13 +1549,14 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
       probe.N = word_count_host(nn);
       probe.ld = probe.ld8 = (probe.N + 63) / 64 * 64;
       probe.compact = c->compact_from > 0 && nn >= c->compact_from && nn >= 2;
+      probe.chain_giants = c->chain_giants_from > 0 && nn >= c->chain_giants_from;
       probe.c = probe.compact ? compact_baby(baby_of(c, nn)) : baby_of(c, nn);
     }
     const PowerSet &ps = fresh ? probe : it->second;
     int top = 0;
     std::set<int> giants;
-    batch_needs(kv.second, ps.c, ps.compact, &top, &giants);
-    for (int e : keys_of(top, giants, ps.c, ps.compact))
+    batch_needs(kv.second, ps.c, ps.compact, ps.chain_giants, &top, &giants);
+    for (int e : keys_of(top, giants, ps.c, ps.compact, ps.chain_giants))
       if (fresh || !ps.pw.count(e)) extra += ps.bytes_of(e);
   }
   return extra;

@@ -22,7 +22,8 @@ the algorithmic work of one launch:
   trace  2 N^2 entries read (4 N^2 bytes)
   gemm   N^3 (min,+) operations
   batch  one persistent launch answering the instances (cold context;
-         --compact-from sets which path orders keep compact powers)
+         --compact-from sets which path orders keep compact powers,
+         --chain-giants-from which make their giants by the chain)
   cdiff  constant-difference test of A^2 against A (tp_const_diff): 2 N^2
          entries read (4 N^2 bytes)
   recurrence  tp_recurrence(n, K, window): K powers, each compared with the
@@ -78,6 +79,8 @@ def main(argv=None):
                     help="batch: chain levels inside the persistent launch too")
     ap.add_argument("--compact-from", type=int, default=None,
                     help="batch: TP_PARAM_COMPACT_FROM (path orders kept as compact powers)")
+    ap.add_argument("--chain-giants-from", type=int, default=None,
+                    help="batch: TP_PARAM_CHAIN_GIANTS_FROM (path orders whose giants the chain makes)")
     ap.add_argument("--K", type=int, default=50, help="recurrence: powers computed")
     ap.add_argument("--window", type=int, default=0, help="recurrence: comparison window")
     ap.add_argument("--N", type=int, default=8192, help="apsp: order of the digraph")
@@ -228,6 +231,9 @@ def main(argv=None):
                 tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, int(args.fused))
                 if args.compact_from is not None:
                     tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, args.compact_from)
+                if args.chain_giants_from is not None:
+                    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_CHAIN_GIANTS_FROM,
+                                        args.chain_giants_from)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 tp.tp_batch_power_trace(ctx, ns, ms)
@@ -237,7 +243,8 @@ def main(argv=None):
             finally:
                 tp.tp_ctx_destroy(ctx)
         out.update({"instances": len(inst), "fused": args.fused,
-                    "compact_from": args.compact_from, "resident_bytes": resident,
+                    "compact_from": args.compact_from,
+                    "chain_giants_from": args.chain_giants_from, "resident_bytes": resident,
                     "ms": min(times) * 1e3, "ms_all": [round(t * 1e3, 2) for t in times]})
     print(json.dumps(out), flush=True)
 

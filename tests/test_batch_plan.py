@@ -23,15 +23,18 @@ def _closure(j, out):
     out.add(j)
 
 
-def model_bytes(n, ms, c, compact_from=10):
+def model_bytes(n, ms, c, compact_from=10, chain_from=10):
     """Bytes of the powers the planning rules call for.  Path orders from
     compact_from on (TP_PARAM_COMPACT_FROM) keep A^1..A^3 in 16 bits and A^3
     on as u8 residuals (rows of ld bytes) with 256 bytes of base words each;
     their baby steps are at least 4 and run to c + 2, and a pair with a
-    baby above 3 keeps its baby at 3 or above."""
+    baby above 3 keeps its baby at 3 or above.  Path orders from chain_from
+    on (TP_PARAM_CHAIN_GIANTS_FROM) make each giant by continuing the chain:
+    no smaller giants, two step buffers of the chain's form."""
     N = tp.tp_state_dim(n)
     ld = (N + 63) // 64 * 64
     compact = compact_from > 0 and n >= compact_from and n >= 2
+    chained = chain_from > 0 and n >= chain_from
     if compact:
         c = max(c, 4)
     babies = c + 2 if compact else c
@@ -42,15 +45,19 @@ def model_bytes(n, ms, c, compact_from=10):
             top = max(top, (m + 1) // 2)
         else:
             top = max(top, babies)
-            _closure((m - lo) // c, giants)
+            if chained:
+                giants.add((m - lo) // c)
+            else:
+                _closure((m - lo) // c, giants)
+    temps = 2 if chained and giants else 0
     if not compact:
         exps = set(range(1, top + 1)) | {j * c for j in giants}
-        return len(exps) * N * ld * 2
+        return (len(exps) + temps) * N * ld * 2
     wide = set(range(1, min(top, 3) + 1))
     narrow = {j * c for j in giants}
     if top >= 4 or giants:
         narrow |= set(range(3, top + 1))
-    return len(wide) * N * ld * 2 + len(narrow) * (N * ld + 256)
+    return len(wide) * N * ld * 2 + (len(narrow) + temps) * (N * ld + 256)
 
 
 @pytest.fixture
@@ -74,10 +81,11 @@ def test_need_bytes_matches_the_planning_rules(ctx, c):
         assert got == model_bytes(n, ms, c), (n, ms, c)
 
 
-@pytest.mark.parametrize("compact_from", [0, 3, 7])
-def test_need_bytes_follows_the_compact_rules(ctx, compact_from):
-    rng = np.random.default_rng(100 + compact_from)
+@pytest.mark.parametrize("compact_from,chain_from", [(0, 0), (3, 0), (7, 5), (0, 3), (10, 10)])
+def test_need_bytes_follows_the_compact_rules(ctx, compact_from, chain_from):
+    rng = np.random.default_rng(100 + compact_from + 17 * chain_from)
     tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, compact_from)
+    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_CHAIN_GIANTS_FROM, chain_from)
     for n in (2, 3, 5, 7, 9, 11):
         tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 5)
     for trial in range(30):
@@ -86,15 +94,16 @@ def test_need_bytes_follows_the_compact_rules(ctx, compact_from):
         if n * max(ms) >= 65535:
             continue
         got = tp.tp_ctx_need_bytes(ctx, [n] * len(ms), ms)
-        assert got == model_bytes(n, ms, 5, compact_from), (n, ms, compact_from)
+        assert got == model_bytes(n, ms, 5, compact_from, chain_from), (n, ms, compact_from)
 
 
 def test_compact_parameter_bounds(ctx):
-    for bad in (-1, 14):
-        with pytest.raises(tp.TropicalError):
-            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, bad)
-    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 0)
-    tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, 13)
+    for param in (tp.TP_PARAM_COMPACT_FROM, tp.TP_PARAM_CHAIN_GIANTS_FROM):
+        for bad in (-1, 14):
+            with pytest.raises(tp.TropicalError):
+                tp.tp_ctx_set_param(ctx, param, bad)
+        tp.tp_ctx_set_param(ctx, param, 0)
+        tp.tp_ctx_set_param(ctx, param, 13)
 
 
 def test_need_bytes_adds_over_path_orders(ctx):

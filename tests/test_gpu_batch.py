@@ -416,3 +416,42 @@ def test_compact_powers_equal_the_oracle(tp, oracle_mod):
                 oracle_mod.trace_min(oracle_mod.minplus(want[6], want[6]))
     finally:
         tp.tp_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("compact", [0, 3])
+@pytest.mark.parametrize("fused", [0, 1])
+def test_chained_giants_equal_the_oracle(tp, oracle_table_500, oracle_mod, compact, fused):
+    # giants made by continuing the chain (TP_PARAM_CHAIN_GIANTS_FROM), in 16
+    # bits and in compact form, against the oracle; a second batch seeds its
+    # chain from a resident giant; a chained giant entry by entry
+    import torch
+    rng = np.random.default_rng(41 + compact + fused)
+    inst = [(int(rng.integers(2, 9)), int(rng.integers(3, 501))) for _ in range(40)]
+    inst += [(5, 40), (5, 41), (8, 333), (8, 13)]
+    ctx = tp.tp_ctx_create(64 << 30)
+    try:
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, fused)
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_COMPACT_FROM, compact)
+        tp.tp_ctx_set_param(ctx, tp.TP_PARAM_CHAIN_GIANTS_FROM, 3)
+        for n in range(2, 9):
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 5)
+        say("chained giants, compact", compact, "fused", fused)
+        need = tp.tp_ctx_need_bytes(ctx, [n for n, _ in inst], [m for _, m in inst])
+        got = _run(tp, ctx, inst)
+        assert got == [int(oracle_table_500[n][m - 1]) for n, m in inst]
+        assert tp.tp_ctx_resident_bytes(ctx) == need
+        inst2 = [(8, m) for m in (499, 400, 257, 129, 9)] + [(5, 450), (3, 7), (7, 333)]
+        got2 = _run(tp, ctx, inst2)
+        assert got2 == [int(oracle_table_500[n][m - 1]) for n, m in inst2]
+        # (5, 40): a giant of exponent 35 (40 = 35 + 5 in 16 bits; 37 + 3 is
+        # not a pair, so compact c = 5 gives 35 + 5 as well)
+        A = oracle_mod.state_matrix(5)
+        P = A
+        for _ in range(34):
+            P = oracle_mod.minplus(A, P)
+        G = tp.tp_ctx_copy_power(ctx, 5, 35)
+        torch.cuda.synchronize()
+        g = G.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.int32)
+        assert np.array_equal(g, P)
+    finally:
+        tp.tp_ctx_destroy(ctx)
