@@ -32,8 +32,10 @@
 //      512-column panel) item per wave; a level k >= 2 takes the row blocks
 //      of A (16 rows, the union of their successors grouped by row mask, as
 //      in the library's blocked step) cut by rows into parts of bounded
-//      length, one (part, 256-column panel) item per workgroup, whose four
-//      waves split the part's entries and meet in LDS.  The
+//      length, one (part, 512-column panel) item per workgroup, whose four
+//      waves split the part's entries and meet in LDS; each XCD's
+//      workgroups take the items of a range of columns, longest first, each
+//      workgroup its next item from a counter when it is free.  The
 //      barrier needs every workgroup resident at once, so this mode never
 //      launches more workgroups than the chip holds, and such launches of
 //      the process are ordered one after another on each device; a batch
@@ -127,15 +129,27 @@ struct Control {
 constexpr int kMaxSlots = 16;
 
 // Fused mode: one chain level (exponent k) of every slot that needs it.  Its
-// work items are (slot, 512-column panel, r) triples packed in 32 bits (slot
-// in bits 28..31, panel in 20..27, r in 0..19), items[off .. off + count) of
-// the launch's item list.  Level 1 (A^1, from the masks): r is a row, one
-// item per wave.  Levels k >= 2 (`parts` set): r is a part of a row block,
-// one item per workgroup, ordered by decreasing entry count.  Levels of one
-// kind with the same slots share one list.
+// work items are (slot, panel, r) triples packed in 32 bits (slot in bits
+// 28..31, panel in 20..27, r in 0..19), items[off .. off + count) of the
+// launch's item list, all on 512-column panels.  Level 1 (A^1, from the
+// masks): r is a row, one item per wave.  Levels k >= 2 (`parts` set): r is
+// a part of a row block, one item per workgroup.  Their list is in column
+// order (slot, then panel) cut into nx ranges of about equal work, xr[x] ..
+// xr[x+1]-1, one for the workgroups of each XCD (workgroup g runs on XCD g
+// mod 8, so each XCD gathers from a few column panels of A^(k-1)), each
+// range by decreasing entry count.  The workgroups of XCD x take the items
+// of its range in that order from a counter of their own, which only grows
+// over the launch: every workgroup takes until it draws past the range, so
+// a level moves the counter by the range's count plus its workgroups, and
+// xbase[x] is where the level starts.  Levels of one kind with the same
+// slots share one list.
+constexpr int kXcds = 8;
 struct Level {
   int32_t k, parts;
   int64_t off, count;
+  int32_t nx;
+  int32_t xr[kXcds + 1];
+  int32_t xbase[kXcds];
 };
 __host__ __device__ constexpr uint32_t item_code(int slot, int64_t panel, int64_t q) {
   return ((uint32_t)slot << 28) | ((uint32_t)panel << 20) | (uint32_t)q;
@@ -147,7 +161,8 @@ __host__ __device__ constexpr uint32_t item_code(int slot, int64_t panel, int64_
 constexpr int kLine = 64;  // int32 per line
 constexpr int kMaxXcc = 16;
 constexpr int kRegTotal = kMaxXcc, kArrive = kMaxXcc + 1, kXccDone = 2 * kMaxXcc + 1;
-constexpr int kLevelCounters = (2 * kMaxXcc + 2) * kLine;
+constexpr int kTake = 2 * kMaxXcc + 2;  // the item counters of the XCDs
+constexpr int kLevelCounters = (kTake + kXcds) * kLine;
 // XCC_ID hardware register (bits 3:0): which XCD, and so which L2, a wave is on
 constexpr int kHwRegXccId = (3 << 11) | 20;
 constexpr uint16_t kInf = 0xFFFFu;
@@ -182,7 +197,7 @@ __device__ __forceinline__ int wait_counter(const int32_t *counters, int dep, in
   return 1;
 }
 
-// Fused mode, chain level k >= 2: the workgroup's item (slot, 256-column
+// Fused mode, chain level k >= 2: the workgroup's item (slot, 512-column
 // panel, part of a row block) of A^k = A x A^(k-1) (part_rows: the four
 // waves split the part's entries and meet in the LDS arena).  Slot fields
 // are made wave-uniform so the entry loads are scalar loads.
@@ -194,9 +209,9 @@ __device__ __forceinline__ void part_item(const Slot *__restrict__ slots, uint32
   const int64_t panel = (code >> 20) & 0xFFu, f = code & 0xFFFFFu;
   uint16_t *const *powers = wave_uniform(sl.powers);
   part_rows<4, 4, 2>((kconst_i64)wave_uniform(sl.fptr), (kconst_u64)wave_uniform(sl.fent),
-                  (kconst_u32)wave_uniform(sl.finfo), f, wave_uniform(powers[lev - 1]), ld,
-                  wave_uniform(powers[lev]), ld, N, N, panel * kPanel + (int64_t)lane * 8, wv,
-                  lane, (__attribute__((address_space(3))) uint32_t *)lds_words);
+                     (kconst_u32)wave_uniform(sl.finfo), f, wave_uniform(powers[lev - 1]), ld,
+                     wave_uniform(powers[lev]), ld, N, N, panel * kPanel + (int64_t)lane * 8, wv,
+                     lane, (__attribute__((address_space(3))) uint32_t *)lds_words);
 }
 
 __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl,
@@ -250,18 +265,26 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
       const int lgo = __builtin_amdgcn_readfirstlane(s_go);
       __syncthreads();
       if (lgo && levels[L].parts) {
-        // one (slot, panel, part) per workgroup, its entries split over the
-        // four waves, whose minima meet in LDS; items dealt to the
-        // workgroups in a snake, longest first
+        // one (slot, panel, part) per workgroup, its entries split over
+        // the four waves, whose minima meet in LDS; the workgroup takes the
+        // next item of its XCD's range (longest first) whenever it is free
         const Level &lv = levels[L];
-        const int64_t count = wave_uniform(lv.count);
         const int k = __builtin_amdgcn_readfirstlane(lv.k);
-        const kconst_u32 list = (kconst_u32)wave_uniform(items + lv.off);
-        const int32_t G = (int32_t)gridDim.x, g = (int32_t)blockIdx.x;
-        int32_t odd = 0;
-        for (int64_t base = 0; base < count; base += G, odd ^= 1) {
-          const int64_t p = base + (odd ? G - 1 - g : g);
-          if (p >= count) continue;
+        const int32_t nx = __builtin_amdgcn_readfirstlane(lv.nx);
+        const int32_t x = (int32_t)blockIdx.x % nx;
+        const int32_t x0 = __builtin_amdgcn_readfirstlane(lv.xr[x]);
+        const int32_t count = __builtin_amdgcn_readfirstlane(lv.xr[x + 1]) - x0;
+        const int32_t xbase = __builtin_amdgcn_readfirstlane(lv.xbase[x]);
+        const kconst_u32 list = (kconst_u32)wave_uniform(items + lv.off + x0);
+        while (true) {
+          if (threadIdx.x == 0)
+            s_task = __hip_atomic_fetch_add(&counters[(kTake + x) * kLine], 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT) - xbase;
+          __syncthreads();
+          const int32_t p = __builtin_amdgcn_readfirstlane(s_task);
+          if (p >= count) break;
+          // part_rows ends in a barrier: every wave has read s_task before
+          // thread 0 writes the next
           part_item(slots, list[p], k, wv, lane, reinterpret_cast<uint32_t *>(lds));
         }
       } else if (lgo) {
@@ -903,6 +926,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   // in both modes
   std::vector<Level> levels;
   std::vector<uint32_t> items;
+  // the grid of a launch with levels (every workgroup resident)
+  const int resident = default_grid();
+  const int grid_levels =
+      c->grid_override > 0 ? std::min(c->grid_override, resident) : resident;
   if (fused) {
     int max_top = 0;
     for (const Plan &p : plans) max_top = std::max(max_top, p.chain_top);
@@ -911,8 +938,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       const int rc = state_fine_view(plans[s].n, stream, &plans[s].fine);
       if (rc != TP_OK) return rc;
     }
+    int32_t xbase[kXcds] = {0};
     std::vector<int> prev_set, prev_part_set;
     int64_t off = 0, cnt = 0, part_off = 0, part_cnt = 0;
+    Level part_cut{};
     for (int k = 1; k <= max_top; ++k) {
       std::vector<int> set;
       for (int s = 0; s < nslots; ++s)
@@ -920,28 +949,48 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       if (set.empty()) continue;
       if (k >= 2) {
         if (set != prev_part_set) {
-          // (slot, panel, part) items by decreasing entry count
-          std::vector<std::pair<int64_t, uint32_t>> by_len;
+          // (slot, panel, part) items in column order with their work: the
+          // part's entry count plus the item's fixed cost (its start and
+          // its minima meeting in LDS, about 140 entries' worth at n = 9)
+          constexpr int64_t kItemCost = 140;
+          std::vector<std::pair<int64_t, uint32_t>> its;
           for (int s : set) {
             const Plan &p = plans[s];
             const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
-            for (int64_t f = 0; f < p.fine.nf; ++f)
-              for (int64_t P = 0; P < panels; ++P)
-                by_len.push_back({p.fine.fptrh[f + 1] - p.fine.fptrh[f], item_code(s, P, f)});
+            for (int64_t P = 0; P < panels; ++P)
+              for (int64_t f = 0; f < p.fine.nf; ++f)
+                its.push_back({p.fine.fptrh[f + 1] - p.fine.fptrh[f] + kItemCost, item_code(s, P, f)});
           }
-          std::stable_sort(by_len.begin(), by_len.end(),
-                           [](const std::pair<int64_t, uint32_t> &a,
-                              const std::pair<int64_t, uint32_t> &b) { return a.first > b.first; });
+          // ranges of about equal work, one per XCD, each longest first
+          Level cut{};
+          cut.nx = std::max(1, std::min(kXcds, grid_levels));
+          int64_t total = 0, acc = 0;
+          for (const auto &x : its) total += x.first;
+          int x = 1;
+          for (size_t i = 0; i < its.size() && x < cut.nx; ++i) {
+            acc += its[i].first;
+            while (x < cut.nx && acc * cut.nx >= total * x) cut.xr[x++] = (int32_t)(i + 1);
+          }
+          for (; x <= cut.nx; ++x) cut.xr[x] = (int32_t)its.size();
+          for (int r = 0; r < cut.nx; ++r)
+            std::stable_sort(its.begin() + cut.xr[r], its.begin() + cut.xr[r + 1],
+                             [](const std::pair<int64_t, uint32_t> &a,
+                                const std::pair<int64_t, uint32_t> &b) { return a.first > b.first; });
           part_off = (int64_t)items.size();
-          part_cnt = (int64_t)by_len.size();
-          for (const auto &x : by_len) items.push_back(x.second);
+          part_cnt = (int64_t)its.size();
+          for (const auto &it : its) items.push_back(it.second);
+          part_cut = cut;
           prev_part_set = set;
         }
-        Level lv{};
+        Level lv = part_cut;
         lv.k = k;
         lv.parts = 1;
         lv.off = part_off;
         lv.count = part_cnt;
+        for (int x = 0; x < lv.nx; ++x) {
+          lv.xbase[x] = xbase[x];
+          xbase[x] += lv.xr[x + 1] - lv.xr[x] + (grid_levels - 1 - x) / lv.nx + 1;
+        }
         levels.push_back(lv);
         continue;
       }
@@ -1275,9 +1324,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
 
   // the level barriers need every workgroup resident at once: a fused batch
   // with chain levels never launches more than the chip holds
-  const int resident = default_grid();
   int grid = c->grid_override > 0 ? c->grid_override : resident;
-  if (!levels.empty()) grid = std::min(grid, resident);
+  if (!levels.empty()) grid = grid_levels;
   if (!c->exec || c->g_key[0] != c->d_tasks.p || c->g_key[1] != c->d_counters.p ||
       c->g_key[2] != c->d_results.p || c->g_key[3] != c->d_levels.p ||
       c->g_key[4] != c->d_items.p || c->g_grid != grid ||
