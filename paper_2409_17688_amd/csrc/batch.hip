@@ -156,13 +156,16 @@ __host__ __device__ constexpr uint32_t item_code(int slot, int64_t panel, int64_
 }
 // Level barrier counters at the start of the counter array, each on a
 // 256-byte line of its own (atomics on one line serialize): workgroups per
-// XCC, then the registrations, then arrivals per XCC and the XCCs done.  The
-// arrival counters only grow: level L is complete at (L + 1) x the count.
+// XCC, then the registrations, then arrivals per XCC and the XCCs done, the
+// item counters of the XCDs, and the release of each XCC.  The arrival,
+// done and release counters only grow: level L is complete at (L + 1) x the
+// count.
 constexpr int kLine = 64;  // int32 per line
 constexpr int kMaxXcc = 16;
 constexpr int kRegTotal = kMaxXcc, kArrive = kMaxXcc + 1, kXccDone = 2 * kMaxXcc + 1;
-constexpr int kTake = 2 * kMaxXcc + 2;  // the item counters of the XCDs
-constexpr int kLevelCounters = (kTake + kXcds) * kLine;
+constexpr int kTake = 2 * kMaxXcc + 2;
+constexpr int kRelease = kTake + kXcds;
+constexpr int kLevelCounters = (kRelease + kMaxXcc) * kLine;
 // XCC_ID hardware register (bits 3:0): which XCD, and so which L2, a wave is on
 constexpr int kHwRegXccId = (3 << 11) | 20;
 constexpr uint16_t kInf = 0xFFFFu;
@@ -241,7 +244,9 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
   // stores to reach its L2, the workgroup counts itself on its XCC's
   // arrival counter, and the last arrival of an XCC (the workgroups per XCC
   // are counted once at the start) writes that L2 back and counts the XCC.
-  // Every workgroup then waits (bounded) until all XCCs are in and acquires.
+  // That workgroup then waits (bounded) until all XCCs are in and releases
+  // its XCC, whose other workgroups wait on that (a few pollers on the
+  // global count instead of the whole grid), and every workgroup acquires.
   const int nlev = ctl->nlevels;
   if (nlev > 0) {
     __shared__ int32_t s_on_xcc, s_xccs;
@@ -344,8 +349,12 @@ __global__ void __launch_bounds__(256, 4) batch_kernel(Control *__restrict__ ctl
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           __hip_atomic_fetch_add(&counters[kXccDone * kLine], 1, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
+          (void)wait_counter<true>(counters, kXccDone * kLine, xccs * (L + 1), ctl, limit);
+          __hip_atomic_store(&counters[(kRelease + xcc) * kLine], L + 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          (void)wait_counter<true>(counters, (kRelease + xcc) * kLine, L + 1, ctl, limit);
         }
-        (void)wait_counter<true>(counters, kXccDone * kLine, xccs * (L + 1), ctl, limit);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
