@@ -171,10 +171,14 @@ int tp_gemm_choice(int dtype, int64_t M, int64_t N, int64_t K, int *config, int 
 int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s);
 
 /* Library-wide defaults of the batch engine's baby steps c at path order n
- * (1..12), for the default mode and for TP_PARAM_FUSED_CHAIN (where chain
- * levels cost more, so fewer pay); 0 keeps the built-in rule.  A context's
- * TP_PARAM_BABY_STEPS takes precedence; baby steps already fixed in a context
- * do not change. */
+ * (1..12), for the default mode and for TP_PARAM_FUSED_CHAIN (where the
+ * levels of all n of a batch run together); 0 keeps the built-in rule.  A
+ * context's TP_PARAM_BABY_STEPS takes precedence; baby steps already fixed in
+ * a context do not change.  A set created from these defaults (16-bit powers,
+ * giants by products) takes c = ceil(m_max / 2) instead, m_max the largest
+ * cycle order of n in the batch that creates it, when that is at most 2c,
+ * some instance needs a giant at c, and tp_tune_planner's rates put the
+ * extra chain levels below the giants' products. */
 int tp_tune_batch(int n, int baby_steps, int fused_baby_steps);
 
 /* Matrix-vector products with the M x K matrix A:
@@ -516,7 +520,10 @@ int tp_ctx_release(void *ctx, int n, hipStream_t stream);
 int tp_ctx_copy_power(void *ctx, int n, int e, void *d_out, int64_t ld, hipStream_t stream);
 
 /* Bytes of powers a batch of these instances would add to the context (0
- * when everything it needs is resident); for admission control. */
+ * when everything it needs is resident); for admission control.  Host
+ * planning only, except that a new set whose baby steps come from
+ * tp_tune_batch's defaults and whose choice needs the planner's cost builds
+ * the state of n (once per process, as the batch would). */
 int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t *m);
 
 /* gamma2_dev[j] (device int32) = gamma_2(P_{n[j]} x C_{m[j]}) for j < count,

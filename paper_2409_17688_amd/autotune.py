@@ -2,6 +2,7 @@
 
     python -m paper_2409_17688_amd.autotune                 # full sweep
     python -m paper_2409_17688_amd.autotune --quick --out /tmp/t.json
+    python -m paper_2409_17688_amd.autotune --only batch   # one section, others kept
 
 What it tunes (none of it changes a result, only which kernel shape runs):
   * dense products: for the state-matrix orders N(n), n = 4..11, and each
@@ -52,6 +53,7 @@ KSPLITS = (1, 2, 4, 8, 16)
 # replace the best so far (large tiles first: they win near-ties at large N)
 CONFIG_ORDER = (4, 1, 2, 0, 3)
 TIE = 0.01
+SECTIONS = ("gemm", "planner", "batch")
 
 
 def _events(fn, min_ms=20.0, max_reps=50):
@@ -238,7 +240,16 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--quick", action="store_true", help="small sweep (tests)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--only", action="append", choices=SECTIONS,
+                    help="tune only this section (repeatable); the others are kept from the "
+                         "table at --out (or the package's table) and loaded before tuning")
     args = ap.parse_args(argv)
+    only = set(args.only or SECTIONS)
+    base = {}
+    if only != set(SECTIONS):
+        src = args.out if os.path.exists(args.out) else DEFAULT_TABLE
+        with open(src) as f:
+            base = json.load(f)
 
     def log(msg):
         print(msg, flush=True)
@@ -255,18 +266,26 @@ def main(argv=None):
         baby_list = (8, 16)
     else:
         gemm_ns, planner_ns, batch_ns = tuple(range(4, 12)), tuple(range(1, 13)), tuple(range(4, 10))
-        baby_list = (4, 6, 8, 12, 16, 24, 32, 48, 64)
+        baby_list = (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192)
     table = {"arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
              "device": torch.cuda.get_device_name(0),
              "date": time.strftime("%Y-%m-%d"),
              "note": "written by python -m paper_2409_17688_amd.autotune; changes only kernel "
                      "shapes, never results"}
-    table["gemm"] = tune_gemm(gemm_ns, (tp.TP_U16,), log)
-    table["gemm"].update(tune_gemm(tuple(n for n in gemm_ns if n <= 10), (tp.TP_U8,), log))
+    if "gemm" in only:
+        table["gemm"] = tune_gemm(gemm_ns, (tp.TP_U16,), log)
+        table["gemm"].update(tune_gemm(tuple(n for n in gemm_ns if n <= 10), (tp.TP_U8,), log))
+    else:
+        table["gemm"] = base["gemm"]
     for name, rows in table["gemm"].items():
         apply_gemm_rows(tp.TP_U16 if name == "u16" else tp.TP_U8, rows)
-    table["planner"], table["step"] = tune_planner(planner_ns, log)
-    table["batch"] = tune_batch(batch_ns, baby_list, args.seed, log)
+    if "planner" in only:
+        table["planner"], table["step"] = tune_planner(planner_ns, log)
+    else:
+        table["planner"], table["step"] = base["planner"], base["step"]
+        apply_tuning(table={"planner": table["planner"], "step": table["step"]})
+    table["batch"] = tune_batch(batch_ns, baby_list, args.seed, log) if "batch" in only \
+        else base["batch"]
     with open(args.out, "w") as f:
         _dump(table, f)
     log(f"wrote {args.out}")

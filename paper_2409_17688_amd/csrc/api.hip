@@ -583,6 +583,12 @@ int power_trace_locked(int n, int64_t m, int32_t *gamma2_host, hipStream_t s) {
 
 }  // namespace
 
+void step_and_product_seconds(int n, double N, double nnz, double *step, double *product) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  *step = nnz * N / g_spmm_rate[n] + kLaunch;
+  *product = N * N * N / g_gemm_rate[n] + kLaunch;
+}
+
 hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, uint16_t *Y,
                            int64_t ldy, int64_t ncols, hipStream_t s) {
   int form;

@@ -742,6 +742,35 @@ std::vector<int> keys_of(int chain_top, const std::set<int> &giants, int c, bool
 // compact sets: at least 4 baby steps, so every giant factor is compact
 int compact_baby(int c) { return std::max(c, 4); }
 
+// Baby steps of a new set of path order n for the cycle orders ms of the
+// batch that creates it: the tuned (or built-in) c0, or c1 = ceil(m_max / 2)
+// when some cycle order needs giants at c0, c1 <= 2 c0 and the planner's
+// rates put the extra c1 - c0 chain levels below the giants' products (c1
+// answers every instance from two babies).  Baby steps set on the context,
+// compact sets and chained giants keep c0.  `view` supplies the state's N
+// and nnz when the choice needs them (it may build the state); a negative
+// status from it is returned as is.
+template <typename ViewFn>
+int fresh_baby(Ctx *c, int n, const std::vector<int64_t> &ms, bool compact, bool chain_giants,
+               ViewFn view) {
+  const int c0 = compact ? compact_baby(baby_of(c, n)) : baby_of(c, n);
+  if (compact || chain_giants || c->baby[n] > 0 || ms.empty()) return c0;
+  const int64_t mmax = *std::max_element(ms.begin(), ms.end());
+  if ((mmax + 1) / 2 > 2 * (int64_t)c0) return c0;
+  const int c1 = (int)((mmax + 1) / 2);
+  if (c1 <= c0) return c0;
+  int top0 = 0;
+  std::set<int> g0;
+  batch_needs(ms, c0, false, false, &top0, &g0);
+  if (g0.empty()) return c0;
+  StateView v{};
+  const int rc = view(&v);
+  if (rc != TP_OK) return rc;
+  double step = 0, product = 0;
+  step_and_product_seconds(n, (double)v.N, (double)v.nnz, &step, &product);
+  return (double)(c1 - top0) * step < (double)g0.size() * product ? c1 : c0;
+}
+
 }  // namespace
 
 int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *gamma2_dev,
@@ -768,7 +797,10 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       ps.compact = c->compact_from > 0 && p.n >= c->compact_from && p.n >= 2;
       ps.chain_giants = c->chain_giants_from > 0 && p.n >= c->chain_giants_from;
       ps.ld8 = (p.view.N + 63) / 64 * 64;
-      ps.c = ps.compact ? compact_baby(baby_of(c, p.n)) : baby_of(c, p.n);
+      const int cb = fresh_baby(c, p.n, kv.second, ps.compact, ps.chain_giants,
+                                [&](StateView *v) { *v = p.view; return (int)TP_OK; });
+      if (cb < 0) return cb;
+      ps.c = cb;
     }
     batch_needs(kv.second, ps.c, ps.compact, ps.chain_giants, &p.chain_top, &p.giants);
     p.exps = keys_of(p.chain_top, p.giants, ps.c, ps.compact, ps.chain_giants);
@@ -1607,7 +1639,11 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
       probe.ld = probe.ld8 = (probe.N + 63) / 64 * 64;
       probe.compact = c->compact_from > 0 && nn >= c->compact_from && nn >= 2;
       probe.chain_giants = c->chain_giants_from > 0 && nn >= c->chain_giants_from;
-      probe.c = probe.compact ? compact_baby(baby_of(c, nn)) : baby_of(c, nn);
+      // the state (built now if the choice needs it and it is not yet)
+      const int cb = fresh_baby(c, nn, kv.second, probe.compact, probe.chain_giants,
+                                [&](StateView *v) { return state_view(nn, nullptr, v); });
+      if (cb < 0) return cb;
+      probe.c = cb;
     }
     const PowerSet &ps = fresh ? probe : it->second;
     int top = 0;

@@ -155,6 +155,9 @@ struct StateView {
 };
 int state_view(int n, hipStream_t s, StateView *out);
 int state_fine_view(int n, hipStream_t s, FineView *out);
+// The plain path's cost model for path order n (its tuned rates): seconds of
+// one sparse left step (nnz N operations) and of one dense product (N^3).
+void step_and_product_seconds(int n, double N, double nnz, double *step, double *product);
 // Y = A(D_n) x X (u16) in the form the library picks for n (tp_tune_step).
 hipError_t state_step_view(const StateView &v, const uint16_t *X, int64_t ldx, uint16_t *Y,
                            int64_t ldy, int64_t ncols, hipStream_t s);

@@ -1,7 +1,9 @@
 """Host logic of the batch engine, on the CPU: which powers a batch needs.
 
 tp_ctx_need_bytes runs the engine's planning on the host only (no device
-call): per path order, the chain up to the largest baby step an instance
+call with baby steps set on the context, as here; the choice that may
+consult the state's cost is tested on the GPU): per path order, the chain
+up to the largest baby step an instance
 needs and the giants A^(jc) with their closure under j = h + (j - h), h the
 largest power of two <= j (j/2 + j/2 when j is a power of two).  The model
 below restates those rules independently; the byte counts must agree."""

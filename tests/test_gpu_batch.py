@@ -455,3 +455,43 @@ def test_chained_giants_equal_the_oracle(tp, oracle_table_500, oracle_mod, compa
         assert np.array_equal(g, P)
     finally:
         tp.tp_ctx_destroy(ctx)
+
+
+def test_new_sets_may_chain_to_half_the_longest_cycle(tp, oracle_table):
+    # baby steps from the library defaults (c0 = 16): cycle orders up to 50
+    # need the giants A^32 and A^48, or, with c1 = 25, none; the planner's
+    # rates decide (dense products made slow, then cheap)
+    n, ms = 6, [3, 10, 40, 47, 50]
+    N = tp.tp_state_dim(n)
+    per = N * ((N + 63) // 64 * 64) * 2
+    try:
+        for gemm_rate, fused, powers in ((1e3, 0, 25), (1e18, 0, 18), (1e3, 1, 25)):
+            say("planner gemm rate", gemm_rate, "fused", fused)
+            tp.tp_tune_batch(n, 16, 16)
+            tp.tp_tune_planner(n, 1e12, gemm_rate)
+            ctx = tp.tp_ctx_create(1 << 34)
+            try:
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, fused)
+                need = tp.tp_ctx_need_bytes(ctx, [n] * len(ms), ms)
+                assert need == powers * per
+                got = _run(tp, ctx, [(n, m) for m in ms])
+                assert got == [int(oracle_table[n][m - 1]) for m in ms]
+                assert tp.tp_ctx_resident_bytes(ctx) == need
+                # the set keeps its baby steps: a longer cycle adds giants
+                more = tp.tp_ctx_need_bytes(ctx, [n], [120])
+                assert more > 0
+                assert _run(tp, ctx, [(n, 120)]) == [int(oracle_table[n][119])]
+            finally:
+                tp.tp_ctx_destroy(ctx)
+        # baby steps set on the context are kept as they are
+        tp.tp_tune_planner(n, 1e12, 1e3)
+        ctx = tp.tp_ctx_create(1 << 34)
+        try:
+            tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + n, 16)
+            assert tp.tp_ctx_need_bytes(ctx, [n] * len(ms), ms) == 18 * per
+        finally:
+            tp.tp_ctx_destroy(ctx)
+    finally:
+        tp.tp_tune_batch(n, 0, 0)
+        tp.tp_tune_planner(n, 0.0, 0.0)
+        tp.apply_tuning()

@@ -188,3 +188,23 @@ def test_autotuner_quick_run_writes_a_loadable_table(tp, tmp_path):
         assert autotune.apply_tuning(str(out))
     finally:
         _reset_tables(tp)
+
+
+def test_autotuner_only_one_section_keeps_the_others(tp, tmp_path):
+    from paper_2409_17688_amd import autotune
+    out = tmp_path / "table.json"
+    try:
+        assert autotune.main(["--quick", "--out", str(out)]) == 0
+        first = json.loads(out.read_text())
+        # mark the kept sections so that a re-tune would show
+        first["gemm"]["u16"][0][3] = 123.0
+        first["planner"]["4"] = [1.5e9, 2.5e9]
+        out.write_text(json.dumps(first))
+        assert autotune.main(["--quick", "--only", "batch", "--out", str(out)]) == 0
+        second = json.loads(out.read_text())
+        assert second["gemm"] == first["gemm"] and second["planner"] == first["planner"]
+        assert second["step"] == first["step"]
+        assert set(second["batch"]) == {"4"} and second["batch"]["4"][0] in (8, 16)
+        assert autotune.apply_tuning(str(out))
+    finally:
+        _reset_tables(tp)
