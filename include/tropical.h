@@ -176,9 +176,10 @@ int tp_tune_planner(int n, double spmm_ops_per_s, double gemm_ops_per_s);
  * context's TP_PARAM_BABY_STEPS takes precedence; baby steps already fixed in
  * a context do not change.  A set created from these defaults (16-bit powers,
  * giants by products) takes c = ceil(m_max / 2) instead, m_max the largest
- * cycle order of n in the batch that creates it, when that is at most 2c,
- * some instance needs a giant at c, and tp_tune_planner's rates put the
- * extra chain levels below the giants' products. */
+ * cycle order of n in the batch that creates it, when some instance needs a
+ * giant at c and either that is at most 2c and tp_tune_planner's rates put
+ * the extra chain levels below the giants' products, or (fused mode) it is
+ * within the batch's deepest chain of levels, which run anyway. */
 int tp_tune_batch(int n, int baby_steps, int fused_baby_steps);
 
 /* Matrix-vector products with the M x K matrix A:

@@ -16,12 +16,9 @@ What it tunes (none of it changes a result, only which kernel shape runs):
   * the batch engine, n = 4..9: baby steps c for the default mode and for
     the fused mode, on a batch of 32 instances with m uniform in 3..256,
     median of three cold batches per candidate (``tp_tune_batch``).  The
-    fused mode runs the chain levels of all path orders of a batch
-    together, so a smaller n rides along with the levels of the largest:
-    its fused baby steps are then tuned again on a batch of 64 instances
-    with n uniform over the tuned orders (one pass from the largest n
-    down, the others held at their best so far); the table keeps that
-    mixed batch's time for them.
+    batch engine adapts these per batch (longer chains instead of giants
+    where they pay, and in the fused mode where the batch's deepest chain
+    runs anyway).
 
 Every candidate is checked against the reference shape (tile configuration
 0 without a split for products, the built-in batch parameters for batches):
@@ -170,9 +167,7 @@ def _batch_time(ns, ms, params, reps=3):
 
 def tune_batch(ns, baby_list, seed, log):
     """{n: [baby steps, seconds, fused baby steps, seconds]}: fastest cold
-    batch of 32 instances in each mode (median of three per candidate); with
-    several n, the fused baby steps of all but the largest n are then those
-    of the fastest mixed batch of 64 instances."""
+    batch of 32 instances in each mode (median of three per candidate)."""
     rng = np.random.default_rng(seed)
     out = {}
     # load the batch kernel once so that the first candidate is not charged for it
@@ -195,25 +190,6 @@ def tune_batch(ns, baby_list, seed, log):
             log(f"batch n={n} fused={fused}: baby steps {best[0]} {best[1] * 1e3:.2f} ms")
             row += best
         out[n] = row
-    if len(ns) > 1:
-        ms = [int(m) for m in rng.integers(3, 257, 64)]
-        nl = [int(ns[i]) for i in rng.integers(0, len(ns), 64)]
-        cur = {n: out[n][2] for n in ns}
-        params = lambda: {tp.TP_PARAM_FUSED_CHAIN: 1,
-                          **{tp.TP_PARAM_BABY_STEPS + n: c for n, c in cur.items()}}
-        _, ref = _batch_time(nl, ms, {}, reps=1)
-        for n in sorted(ns, reverse=True)[1:]:
-            best = None
-            for c in baby_list:
-                cur[n] = c
-                t, res = _batch_time(nl, ms, params())
-                if res != ref:
-                    raise RuntimeError(f"mixed batch n={n} c={c} fused differs")
-                if best is None or t < best[1] * (1.0 - TIE):
-                    best = [c, t]
-            cur[n] = best[0]
-            out[n][2:4] = best
-            log(f"mixed batch fused: n={n} baby steps {best[0]} {best[1] * 1e3:.2f} ms")
     return out
 
 

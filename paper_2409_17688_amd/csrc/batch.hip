@@ -771,6 +771,59 @@ int fresh_baby(Ctx *c, int n, const std::vector<int64_t> &ms, bool compact, bool
   return (double)(c1 - top0) * step < (double)g0.size() * product ? c1 : c0;
 }
 
+// Baby steps of every path order of a batch (into *out): a resident set
+// keeps its own; a new one takes fresh_baby's choice.  In fused mode, where
+// the levels of every path order run together, a new 16-bit set that would
+// still make giants chains to c1 = ceil(m_max / 2) instead when c1 is within
+// the batch's deepest in-kernel chain (its levels run anyway).  view(n, v)
+// supplies a state when a choice needs its cost.
+template <typename ViewFn>
+int plan_babies(Ctx *c, const std::map<int, std::vector<int64_t>> &by_n, ViewFn view,
+                std::map<int, int> *out) {
+  struct Form {
+    bool fresh, compact, chain;
+  };
+  auto form_of = [&](int n) {
+    auto it = c->sets.find(n);
+    Form f{};
+    f.fresh = it == c->sets.end() || it->second.c == 0;
+    f.compact = f.fresh ? (c->compact_from > 0 && n >= c->compact_from && n >= 2)
+                        : it->second.compact;
+    f.chain = f.fresh ? (c->chain_giants_from > 0 && n >= c->chain_giants_from)
+                      : it->second.chain_giants;
+    return f;
+  };
+  int depth = 0;
+  for (const auto &kv : by_n) {
+    const int n = kv.first;
+    const Form f = form_of(n);
+    int cb = f.fresh ? fresh_baby(c, n, kv.second, f.compact, f.chain,
+                                  [&](StateView *v) { return view(n, v); })
+                     : c->sets[n].c;
+    if (cb < 0) return cb;
+    (*out)[n] = cb;
+    if (c->fused && !f.compact && !f.chain) {
+      int top = 0;
+      std::set<int> g;
+      batch_needs(kv.second, cb, false, false, &top, &g);
+      depth = std::max(depth, top);
+    }
+  }
+  if (!c->fused) return TP_OK;
+  for (const auto &kv : by_n) {
+    const int n = kv.first;
+    const Form f = form_of(n);
+    if (!f.fresh || f.compact || f.chain || c->baby[n] > 0) continue;
+    const int64_t c1 = (*std::max_element(kv.second.begin(), kv.second.end()) + 1) / 2;
+    if (c1 <= (*out)[n] || c1 > depth) continue;
+    int top = 0;
+    std::set<int> g;
+    batch_needs(kv.second, (*out)[n], false, false, &top, &g);
+    if (!g.empty()) (*out)[n] = (int)c1;
+  }
+  return TP_OK;
+}
+
 }  // namespace
 
 int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *gamma2_dev,
@@ -781,6 +834,13 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   for (int j = 0; j < count; ++j) by_n[ns[j]].push_back(ms[j]);
   TP_REQUIRE((int)by_n.size() <= kMaxSlots, "more than %d distinct n in one batch", kMaxSlots);
 
+  std::map<int, int> babies;
+  {
+    const int rc = plan_babies(c, by_n,
+                               [&](int n, StateView *v) { return state_view(n, stream, v); },
+                               &babies);
+    if (rc != TP_OK) return rc;
+  }
   std::vector<Plan> plans;
   std::map<int, int> slot_of;
   int maxexp = 1;
@@ -797,10 +857,7 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       ps.compact = c->compact_from > 0 && p.n >= c->compact_from && p.n >= 2;
       ps.chain_giants = c->chain_giants_from > 0 && p.n >= c->chain_giants_from;
       ps.ld8 = (p.view.N + 63) / 64 * 64;
-      const int cb = fresh_baby(c, p.n, kv.second, ps.compact, ps.chain_giants,
-                                [&](StateView *v) { *v = p.view; return (int)TP_OK; });
-      if (cb < 0) return cb;
-      ps.c = cb;
+      ps.c = babies[p.n];
     }
     batch_needs(kv.second, ps.c, ps.compact, ps.chain_giants, &p.chain_top, &p.giants);
     p.exps = keys_of(p.chain_top, p.giants, ps.c, ps.compact, ps.chain_giants);
@@ -1628,6 +1685,14 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
     }
     by_n[n[j]].push_back(m[j]);
   }
+  // the states are built now if a choice of baby steps needs one
+  std::map<int, int> babies;
+  {
+    const int rc = plan_babies(c, by_n,
+                               [&](int n, StateView *v) { return state_view(n, nullptr, v); },
+                               &babies);
+    if (rc != TP_OK) return rc;
+  }
   int64_t extra = 0;
   for (auto &kv : by_n) {
     const int nn = kv.first;
@@ -1639,11 +1704,7 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
       probe.ld = probe.ld8 = (probe.N + 63) / 64 * 64;
       probe.compact = c->compact_from > 0 && nn >= c->compact_from && nn >= 2;
       probe.chain_giants = c->chain_giants_from > 0 && nn >= c->chain_giants_from;
-      // the state (built now if the choice needs it and it is not yet)
-      const int cb = fresh_baby(c, nn, kv.second, probe.compact, probe.chain_giants,
-                                [&](StateView *v) { return state_view(nn, nullptr, v); });
-      if (cb < 0) return cb;
-      probe.c = cb;
+      probe.c = babies[nn];
     }
     const PowerSet &ps = fresh ? probe : it->second;
     int top = 0;

@@ -495,3 +495,32 @@ def test_new_sets_may_chain_to_half_the_longest_cycle(tp, oracle_table):
         tp.tp_tune_batch(n, 0, 0)
         tp.tp_tune_planner(n, 0.0, 0.0)
         tp.apply_tuning()
+
+
+def test_fused_sets_chain_within_the_batch_deepest_chain(tp, oracle_table):
+    # fused mode: n = 7 (baby steps set to 30 on the context) runs 30 levels;
+    # n = 6 (library default c0 = 8) would make giants for cycles up to 50,
+    # and chains to 25 instead, within those levels; split mode keeps c0
+    # when dense products look cheap
+    inst = [(7, 3), (7, 60), (6, 5), (6, 33), (6, 50)]
+    ns, ms = [a for a, _ in inst], [b for _, b in inst]
+    per = {n: tp.tp_state_dim(n) * ((tp.tp_state_dim(n) + 63) // 64 * 64) * 2 for n in (6, 7)}
+    try:
+        tp.tp_tune_batch(6, 8, 8)
+        tp.tp_tune_planner(6, 1e12, 1e18)
+        for fused, n6_powers in ((1, 25), (0, 8 + 3)):
+            say("fused", fused)
+            ctx = tp.tp_ctx_create(1 << 34)
+            try:
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_FUSED_CHAIN, fused)
+                tp.tp_ctx_set_param(ctx, tp.TP_PARAM_BABY_STEPS + 7, 30)
+                need = tp.tp_ctx_need_bytes(ctx, ns, ms)
+                assert need == 30 * per[7] + n6_powers * per[6]
+                assert _run(tp, ctx, inst) == [int(oracle_table[n][m - 1]) for n, m in inst]
+                assert tp.tp_ctx_resident_bytes(ctx) == need
+            finally:
+                tp.tp_ctx_destroy(ctx)
+    finally:
+        tp.tp_tune_batch(6, 0, 0)
+        tp.tp_tune_planner(6, 0.0, 0.0)
+        tp.apply_tuning()
