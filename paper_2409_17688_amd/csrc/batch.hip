@@ -826,6 +826,81 @@ int plan_babies(Ctx *c, const std::map<int, std::vector<int64_t>> &by_n, ViewFn 
 
 }  // namespace
 
+// Fused mode's level item lists.  A level k >= 2: (slot, panel, part)
+// items in column order, cut into nx ranges of about equal work (a part's
+// entry count plus the item's fixed cost, its start and its minima meeting
+// in LDS, about 140 entries' worth at n = 9), each range longest first.
+// Level 1: (slot, panel, row) items by decreasing length of the row's
+// successor list (a bucket per out-degree), a row's panels together.  A list
+// depends only on its slots' path orders and nx, so the process keeps those
+// it built (g_lists).
+struct LevelList {
+  std::vector<uint32_t> items;
+  Level cut{};
+};
+std::mutex g_list_mu;
+std::map<std::vector<int>, LevelList> g_lists;  // (kind, nx, slot, n, slot, n, ...)
+
+LevelList part_list(const std::vector<Plan> &plans, const std::vector<int> &set, int nx) {
+  constexpr int64_t kItemCost = 140;
+  std::vector<std::pair<int64_t, uint32_t>> its;
+  for (int s : set) {
+    const Plan &p = plans[s];
+    const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
+    for (int64_t P = 0; P < panels; ++P)
+      for (int64_t f = 0; f < p.fine.nf; ++f)
+        its.push_back({p.fine.fptrh[f + 1] - p.fine.fptrh[f] + kItemCost, item_code(s, P, f)});
+  }
+  LevelList out;
+  Level &cut = out.cut;
+  cut.nx = nx;
+  int64_t total = 0, acc = 0;
+  for (const auto &x : its) total += x.first;
+  int x = 1;
+  for (size_t i = 0; i < its.size() && x < cut.nx; ++i) {
+    acc += its[i].first;
+    while (x < cut.nx && acc * cut.nx >= total * x) cut.xr[x++] = (int32_t)(i + 1);
+  }
+  for (; x <= cut.nx; ++x) cut.xr[x] = (int32_t)its.size();
+  for (int r = 0; r < cut.nx; ++r)
+    std::stable_sort(its.begin() + cut.xr[r], its.begin() + cut.xr[r + 1],
+                     [](const std::pair<int64_t, uint32_t> &a,
+                        const std::pair<int64_t, uint32_t> &b) { return a.first > b.first; });
+  out.items.reserve(its.size());
+  for (const auto &it : its) out.items.push_back(it.second);
+  return out;
+}
+
+LevelList row_list(const std::vector<Plan> &plans, const std::vector<int> &set) {
+  int maxdeg = 0;
+  for (int s : set) {
+    const Plan &p = plans[s];
+    for (int64_t q = 0; q < p.view.N; ++q) maxdeg = std::max(maxdeg, (int)p.view.degh[q]);
+  }
+  std::vector<int64_t> pos((size_t)maxdeg + 1, 0);
+  for (int s : set) {
+    const Plan &p = plans[s];
+    const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
+    for (int64_t q = 0; q < p.view.N; ++q) pos[p.view.degh[q]] += panels;
+  }
+  int64_t at = 0;
+  for (int d = maxdeg; d >= 0; --d) {
+    const int64_t n_d = pos[d];
+    pos[d] = at;
+    at += n_d;
+  }
+  LevelList out;
+  out.items.resize((size_t)at);
+  for (int s : set) {
+    const Plan &p = plans[s];
+    const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
+    for (int64_t q = 0; q < p.view.N; ++q)
+      for (int64_t P = 0; P < panels; ++P)
+        out.items[(size_t)pos[p.view.degh[q]]++] = item_code(s, P, q);
+  }
+  return out;
+}
+
 int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *gamma2_dev,
               hipStream_t stream) {
   // wait until the previous batch's staging buffers have been consumed
@@ -1024,6 +1099,26 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
   // in both modes
   std::vector<Level> levels;
   std::vector<uint32_t> items;
+  // one level item list (its items appended to `items`, at *off, *cnt),
+  // from the process's cache when these slots held these path orders before
+  auto add_list = [&](int kind, const std::vector<int> &set, int nx, Level *cut, int64_t *off,
+                      int64_t *cnt) {
+    std::vector<int> key{kind, nx};
+    for (int s : set) {
+      key.push_back(s);
+      key.push_back(plans[s].n);
+    }
+    std::lock_guard<std::mutex> lk(g_list_mu);
+    auto it = g_lists.find(key);
+    if (it == g_lists.end()) {
+      if (g_lists.size() >= 256) g_lists.clear();
+      it = g_lists.emplace(key, kind == 1 ? row_list(plans, set) : part_list(plans, set, nx)).first;
+    }
+    *off = (int64_t)items.size();
+    *cnt = (int64_t)it->second.items.size();
+    items.insert(items.end(), it->second.items.begin(), it->second.items.end());
+    *cut = it->second.cut;
+  };
   // the grid of a launch with levels (every workgroup resident)
   const int resident = default_grid();
   const int grid_levels =
@@ -1047,37 +1142,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
       if (set.empty()) continue;
       if (k >= 2) {
         if (set != prev_part_set) {
-          // (slot, panel, part) items in column order with their work: the
-          // part's entry count plus the item's fixed cost (its start and
-          // its minima meeting in LDS, about 140 entries' worth at n = 9)
-          constexpr int64_t kItemCost = 140;
-          std::vector<std::pair<int64_t, uint32_t>> its;
-          for (int s : set) {
-            const Plan &p = plans[s];
-            const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
-            for (int64_t P = 0; P < panels; ++P)
-              for (int64_t f = 0; f < p.fine.nf; ++f)
-                its.push_back({p.fine.fptrh[f + 1] - p.fine.fptrh[f] + kItemCost, item_code(s, P, f)});
-          }
-          // ranges of about equal work, one per XCD, each longest first
-          Level cut{};
-          cut.nx = std::max(1, std::min(kXcds, grid_levels));
-          int64_t total = 0, acc = 0;
-          for (const auto &x : its) total += x.first;
-          int x = 1;
-          for (size_t i = 0; i < its.size() && x < cut.nx; ++i) {
-            acc += its[i].first;
-            while (x < cut.nx && acc * cut.nx >= total * x) cut.xr[x++] = (int32_t)(i + 1);
-          }
-          for (; x <= cut.nx; ++x) cut.xr[x] = (int32_t)its.size();
-          for (int r = 0; r < cut.nx; ++r)
-            std::stable_sort(its.begin() + cut.xr[r], its.begin() + cut.xr[r + 1],
-                             [](const std::pair<int64_t, uint32_t> &a,
-                                const std::pair<int64_t, uint32_t> &b) { return a.first > b.first; });
-          part_off = (int64_t)items.size();
-          part_cnt = (int64_t)its.size();
-          for (const auto &it : its) items.push_back(it.second);
-          part_cut = cut;
+          add_list(2, set, std::max(1, std::min(kXcds, grid_levels)), &part_cut, &part_off,
+                   &part_cnt);
           prev_part_set = set;
         }
         Level lv = part_cut;
@@ -1093,35 +1159,8 @@ int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *
         continue;
       }
       if (set != prev_set) {
-        // the items of these slots by decreasing length of the row's
-        // successor list (a bucket per out-degree), a row's panels together
-        int maxdeg = 0;
-        for (int s : set) {
-          const Plan &p = plans[s];
-          for (int64_t q = 0; q < p.view.N; ++q) maxdeg = std::max(maxdeg, (int)p.view.degh[q]);
-        }
-        std::vector<int64_t> pos((size_t)maxdeg + 1, 0);
-        for (int s : set) {
-          const Plan &p = plans[s];
-          const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
-          for (int64_t q = 0; q < p.view.N; ++q) pos[p.view.degh[q]] += panels;
-        }
-        off = (int64_t)items.size();
-        int64_t at = off;
-        for (int d = maxdeg; d >= 0; --d) {
-          const int64_t n_d = pos[d];
-          pos[d] = at;
-          at += n_d;
-        }
-        cnt = at - off;
-        items.resize((size_t)at);
-        for (int s : set) {
-          const Plan &p = plans[s];
-          const int64_t panels = (p.view.N + kPanel - 1) / kPanel;
-          for (int64_t q = 0; q < p.view.N; ++q)
-            for (int64_t P = 0; P < panels; ++P)
-              items[(size_t)pos[p.view.degh[q]]++] = item_code(s, P, q);
-        }
+        Level unused{};
+        add_list(1, set, 0, &unused, &off, &cnt);
         prev_set = set;
       }
       Level lv{};
