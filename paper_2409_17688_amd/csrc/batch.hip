@@ -1724,12 +1724,19 @@ int64_t tp_ctx_need_bytes(void *ctx, int count, const int32_t *n, const int64_t 
     }
     by_n[n[j]].push_back(m[j]);
   }
-  // the states are built now if a choice of baby steps needs one
+  // the states are built now if a choice of baby steps needs one, on the
+  // context's own non-blocking stream (the legacy stream would also wait
+  // for the work of every blocking stream)
   std::map<int, int> babies;
   {
-    const int rc = plan_babies(c, by_n,
-                               [&](int n, StateView *v) { return state_view(n, nullptr, v); },
-                               &babies);
+    const int rc = plan_babies(
+        c, by_n,
+        [&](int n, StateView *v) {
+          if (!c->cap_stream)
+            TP_HIP_CHECK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+          return state_view(n, c->cap_stream, v);
+        },
+        &babies);
     if (rc != TP_OK) return rc;
   }
   int64_t extra = 0;
