@@ -826,6 +826,8 @@ int plan_babies(Ctx *c, const std::map<int, std::vector<int64_t>> &by_n, ViewFn 
 
 }  // namespace
 
+namespace {
+
 // Fused mode's level item lists.  A level k >= 2: (slot, panel, part)
 // items in column order, cut into nx ranges of about equal work (a part's
 // entry count plus the item's fixed cost, its start and its minima meeting
@@ -900,6 +902,8 @@ LevelList row_list(const std::vector<Plan> &plans, const std::vector<int> &set) 
   }
   return out;
 }
+
+}  // namespace
 
 int batch_run(Ctx *c, int count, const int32_t *ns, const int64_t *ms, int32_t *gamma2_dev,
               hipStream_t stream) {
