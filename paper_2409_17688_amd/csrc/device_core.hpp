@@ -241,24 +241,41 @@ __device__ __forceinline__ void block_entries(kconst_u64 en, int64_t i0, int64_t
   u16x2 g[V];
 #pragma unroll
   for (int k = 0; k < V; ++k) g[k] = splat(0xFFFFu);
-  const int64_t last = i1 - 1;
+  // entry indices in 32 bits (a state matrix's blocked form has far fewer
+  // than 2^32 entries), so the range tests and clamps are single scalar ops
+  const uint32_t first = (uint32_t)i0, last = (uint32_t)(i1 - 1);
   // the entries of the next round are loaded a round ahead (scalar loads
   // return out of order, so a gather right after its entry's load would wait
-  // for every scalar load in flight)
+  // for every scalar load in flight); a round inside the range is one
+  // scalar load of U consecutive entries
   uint64_t nx[U];
-  auto load_entries = [&](int64_t i) {
+  typedef uint64_t round_t __attribute__((ext_vector_type(U), aligned(8)));
+  auto load_entries = [&](uint32_t i) {
+    if (i + (U - 1) <= last) {
+      const round_t r = *(const __attribute__((address_space(4))) round_t *)(en + i);
 #pragma unroll
-    for (int u = 0; u < U; ++u) nx[u] = en[i + u < last ? i + u : last];
-  };
-  auto fetch = [&](int64_t i, uint64_t (&w)[U], chunk (&v)[U]) {
+      for (int u = 0; u < U; ++u) nx[u] = r[u];
+    } else {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t k = i + u;
-      const uint64_t x = nx[u];
-      // past the range's last entry: no rows, no group end
-      w[u] = k < last ? x : (k == last ? (x | kGroupEnd) : (x & 0xFFFFFFFFull));
-      v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ldc + off];
+      for (int u = 0; u < U; ++u) nx[u] = en[min(i + u, last)];
     }
+  };
+  auto fetch = [&](uint32_t i, uint64_t (&w)[U], chunk (&v)[U]) {
+    if (i + (U - 1) < last) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = nx[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t k = i + u;
+        const uint64_t x = nx[u];
+        // the range's last entry closes its group; past it: no rows, no
+        // group end
+        w[u] = k < last ? x : (k == last ? (x | kGroupEnd) : (x & 0xFFFFFFFFull));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = Xg[(int64_t)(uint32_t)(nx[u] & 0xFFFFFFu) * ldc + off];
     load_entries(i + U);
   };
   auto apply = [&](const uint64_t (&w)[U], const chunk (&v)[U]) {
@@ -276,9 +293,9 @@ __device__ __forceinline__ void block_entries(kconst_u64 en, int64_t i0, int64_t
   };
   uint64_t wa[U], wb[U];
   chunk va[U], vb[U];
-  load_entries(i0);
-  fetch(i0, wa, va);
-  for (int64_t i = i0;;) {
+  load_entries(first);
+  fetch(first, wa, va);
+  for (uint32_t i = first;;) {
     bool more = i + U <= last;
     if (more) fetch(i + U, wb, vb);
     apply(wa, va);
