@@ -352,17 +352,27 @@ __global__ void __launch_bounds__(256) shared_step_kernel(
 
   const int64_t e0 = bp[b], e1 = bp[b + 1];
   if (e0 < e1) {
-    const int64_t last = e1 - 1;
-    auto fetch = [&](int64_t i, uint64_t (&w)[U], u32x2 (&v)[U]) {
+    // entry indices in 32 bits; a round inside the block is one scalar load
+    // of U consecutive entries, only the last round clamps
+    const uint32_t first = (uint32_t)e0, last = (uint32_t)(e1 - 1);
+    typedef uint64_t round_t __attribute__((ext_vector_type(U), aligned(8)));
+    auto fetch = [&](uint32_t i, uint64_t (&w)[U], u32x2 (&v)[U]) {
+      if (i + (U - 1) <= last) {
+        const round_t r = *(const __attribute__((address_space(4))) round_t *)(en + i);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t k = i + u;
-        const uint64_t x = en[k < last ? k : last];
-        // past the end: no rows and no group end (the last entry's group was
-        // applied, so what it adds to the group minimum is never used)
-        w[u] = k <= last ? x : (x & 0xFFFFFFFFull);
-        v[u] = Xg[(int64_t)(uint32_t)(x & 0xFFFFFFu) * ld8 + off];
+        for (int u = 0; u < U; ++u) w[u] = r[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t k = i + u;
+          const uint64_t x = en[min(k, last)];
+          // past the end: no rows and no group end (the last entry's group
+          // was applied, so what it adds to the group minimum is never used)
+          w[u] = k <= last ? x : (x & 0xFFFFFFFFull);
+        }
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = Xg[(int64_t)(uint32_t)(w[u] & 0xFFFFFFu) * ld8 + off];
     };
     auto apply = [&](const uint64_t (&w)[U], const u32x2 (&v)[U]) {
 #pragma unroll
@@ -393,8 +403,8 @@ __global__ void __launch_bounds__(256) shared_step_kernel(
     };
     uint64_t wa[U], wb[U];
     u32x2 va[U], vb[U];
-    fetch(e0, wa, va);
-    for (int64_t i = e0;;) {
+    fetch(first, wa, va);
+    for (uint32_t i = first;;) {
       bool more = i + U <= last;
       if (more) fetch(i + U, wb, vb);
       apply(wa, va);
